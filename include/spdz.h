@@ -1,0 +1,184 @@
+/*
+ * spdz.h -- C ABI of libspdz, the MI355X (gfx950) library for the online
+ * phase of SPDZ on additive secret shares over a prime field F_p.
+ *
+ * All n parties are simulated in one process on one GPU: a party's share of
+ * a vector is a slice of a device buffer, and "opening" a value is an
+ * in-device sum of the party shares.  Citations refer to "An LLVM-Based
+ * Optimization Pipeline for SPDZ" (Dai, Mendes, Lim, arXiv 2512.11112).
+ *
+ * ------------------------------------------------------------------------
+ * Representation (Sec. II-A, "Secret sharing and authentication")
+ *   A secret x is held as shares x_i with x = sum_i x_i mod p, and every
+ *   share carries a MAC share m_i with sum_i m_i = alpha * x, where the global
+ *   key alpha = sum_i alpha_i is itself additively shared.
+ *
+ *   Residues are canonical (in [0, p)) and stored as L little-endian 64-bit
+ *   limbs: L = 1 for p = 2^61 - 1, L = 2 for p = 2^127 - 1.  These are the
+ *   two supported moduli; any other returns SPDZ_E_MODULUS.
+ *
+ *   spdz_shares describes values and MAC shares of a batch of `len`
+ *   elements (the paper's batched value/MAC buffers, Sec. III, Fig. 1, and
+ *   its ShareBatch views, Sec. III-D "Data slicing"): limb l of party i's
+ *   share of element e is val[i * party_stride + l * limb_stride + e], and the
+ *   MAC share is at the same offset in `mac`.  The canonical layout is
+ *   limb_stride = len, party_stride = L * len.  Both pointers are DEVICE
+ *   memory owned by the caller.
+ *
+ *   Public vectors (opened values) are device arrays [L][len], contiguous.
+ *
+ * Conventions of every call
+ *   - Asynchronous: work is enqueued on the context's HIP stream and the call
+ *     returns; exceptions are spdz_ctx_create / spdz_ctx_destroy and
+ *     spdz_mac_check, which synchronise.
+ *   - Negative status: the call did nothing.  SPDZ_MAC_REJECT: the protocol
+ *     aborted (Sec. II-A, "Security model"); every later call except
+ *     spdz_ctx_destroy returns SPDZ_E_ABORTED.
+ *   - Inputs must be canonical residues; the library does not re-check them
+ *     (a non-canonical input gives unspecified, but in-bounds, results).
+ *   - The opened-value log: spdz_open, spdz_mul_batch, spdz_mul_fused and
+ *     spdz_matmul_triple append every value they open to the context's log
+ *     (in the order documented per call); spdz_mac_check checks the whole log
+ *     and empties it.  The log is kept as running random-linear-combination
+ *     sums on the device, never as a list of values.
+ *   - Triples are consumed once; not re-using them is the caller's duty
+ *     (Sec. II-A, "Secure operations").
+ *   - Not thread-safe: one host thread drives a context at a time.
+ * ------------------------------------------------------------------------
+ */
+#ifndef SPDZ_H
+#define SPDZ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct spdz_ctx spdz_ctx;
+
+typedef enum {
+  SPDZ_OK = 0,
+  SPDZ_MAC_REJECT = 1,   /* MAC check failed: protocol aborted */
+  SPDZ_E_INVAL = -1,     /* bad argument (null pointer, bad count, aliasing) */
+  SPDZ_E_MODULUS = -2,   /* modulus other than 2^61-1 / 2^127-1, or limb count mismatch */
+  SPDZ_E_SHAPE = -3,     /* operand lengths or matrix sizes do not match */
+  SPDZ_E_NOMEM = -4,     /* device allocation failed */
+  SPDZ_E_HIP = -5,       /* a HIP runtime call failed */
+  SPDZ_E_ABORTED = -6,   /* context aborted by an earlier failed MAC check */
+  SPDZ_E_UNSUPPORTED = -7 /* party count outside 2..8, or variant not built */
+} spdz_status;
+
+typedef struct {
+  uint64_t *val;          /* device */
+  uint64_t *mac;          /* device */
+  int64_t len;            /* elements */
+  int64_t party_stride;   /* in uint64 words */
+  int64_t limb_stride;    /* in uint64 words */
+} spdz_shares;
+
+typedef struct {
+  spdz_shares a, b, c;    /* c = a * b; consumed once */
+} spdz_triple;
+
+/* Human-readable name of a status code (static storage). */
+const char *spdz_status_str(spdz_status s);
+
+/* ---------------------------------------------------------------------- */
+/* Context                                                                  */
+/* ---------------------------------------------------------------------- */
+
+/* Create a context for n_parties (2..8) over the prime given by p_limbs[0..n_limbs-1]
+ * (little-endian).  alpha_shares is HOST [n_parties][n_limbs]: party i's MAC-key
+ * share alpha_i (Sec. II-A).  check_seed keys the public coefficients of the MAC
+ * check.  hip_stream is a hipStream_t (NULL = the default stream) on which every
+ * call of this context is enqueued; the device is the current one.  Synchronous.
+ * *out receives a library-owned context (free with spdz_ctx_destroy). */
+spdz_status spdz_ctx_create(spdz_ctx **out, int n_parties, const uint64_t *p_limbs, int n_limbs,
+                            const uint64_t *alpha_shares, uint64_t check_seed, void *hip_stream);
+
+/* Free the context and its device scratch.  Synchronous.  NULL is a no-op. */
+spdz_status spdz_ctx_destroy(spdz_ctx *ctx);
+
+/* Number of values opened since the last MAC check (the log length). */
+int64_t spdz_opened_count(const spdz_ctx *ctx);
+
+/* ---------------------------------------------------------------------- */
+/* Online phase                                                             */
+/* ---------------------------------------------------------------------- */
+
+/* Open (Sec. II-A, "Secure operations": d = sum_i d_i made public).
+ * out_pub [L][x->len] (device) receives sum_i x_i mod p for each element.
+ * Appends the x->len opened values to the log. */
+spdz_status spdz_open(spdz_ctx *ctx, const spdz_shares *x, uint64_t *out_pub);
+
+/* Element-wise Beaver multiplication z = x * y (Sec. II-A, "Secure operations").
+ *   d_i = x_i - a_i, e_i = y_i - b_i; d = sum d_i, e = sum e_i are opened;
+ *   z_i    = c_i + d b_i + e a_i + [i = 0] d e
+ *   m(z)_i = m(c)_i + d m(b)_i + e m(a)_i + alpha_i d e
+ * All operands have the same len.  z must not alias x, y or the triple.
+ * d_pub / e_pub: device [L][len] receiving the opened d and e, or NULL.
+ * Appends d (len values) then e (len values) to the log. */
+spdz_status spdz_mul_batch(spdz_ctx *ctx, const spdz_shares *x, const spdz_shares *y,
+                           const spdz_triple *t, spdz_shares *z, uint64_t *d_pub, uint64_t *e_pub);
+
+/* Local linear combination (Sec. II-A, "Addition (local)", generalised to
+ * public coefficients and a public constant):
+ *   out_i    = sum_k coeffs[k] x_{k,i} + [i = 0] c0
+ *   m(out)_i = sum_k coeffs[k] m(x_k)_i + alpha_i c0
+ * terms: HOST array of n_terms (1..8) share descriptors, all of the same len.
+ * coeffs: HOST [n_terms][L]; c0: HOST [L] or NULL (= 0).  out may alias a term.
+ * Opens nothing. */
+spdz_status spdz_linear(spdz_ctx *ctx, int n_terms, const spdz_shares *terms,
+                        const uint64_t *coeffs, const uint64_t *c0, spdz_shares *out);
+
+/* ReduceAdd (Sec. III-B, "Vectorization is first-class"): per-party sum over
+ * the elements of x, values and MAC shares.  out has len 1.  Opens nothing. */
+spdz_status spdz_reduce_add(spdz_ctx *ctx, const spdz_shares *x, spdz_shares *out);
+
+/* One pass that fuses a Beaver product with a linear op and a reduction
+ * (the same results as spdz_mul_batch, then spdz_linear, spdz_open of w and
+ * spdz_reduce_add of z, in that order):
+ *   z = x * y                                   (as spdz_mul_batch)
+ *   w = lin[0] z + lin[1] x + lin[2] y + lin[3] (if w != NULL; lin HOST [4][L])
+ *   w_pub = open(w)                             (if w_pub != NULL; needs w)
+ *   s = ReduceAdd(z)                            (if s != NULL; s->len == 1)
+ * Log order: d, e, then w (if opened).  d_pub / e_pub may be NULL. */
+spdz_status spdz_mul_fused(spdz_ctx *ctx, const spdz_shares *x, const spdz_shares *y,
+                           const spdz_triple *t, spdz_shares *z, uint64_t *d_pub,
+                           uint64_t *e_pub, const uint64_t *lin, spdz_shares *w,
+                           uint64_t *w_pub, spdz_shares *s);
+
+/* MAC check over every value in the log (Sec. II-A, "Security model"; the
+ * check is the random-linear-combination check): with public coefficients
+ * r_j drawn from check_seed and the check number,
+ *   a = sum_j r_j a_j,  sigma_i = sum_j r_j gamma_i(a_j) - alpha_i a,
+ *   accept iff sum_i sigma_i = 0 mod p.
+ * *accepted (HOST) receives 1 or 0; sigma_out (HOST [n][L], nullable) receives
+ * the sigma_i.  Synchronises the stream, empties the log and advances the check
+ * number.  Returns SPDZ_MAC_REJECT (and aborts the context) on failure. */
+spdz_status spdz_mac_check(spdz_ctx *ctx, int *accepted, uint64_t *sigma_out);
+
+/* ---------------------------------------------------------------------- */
+/* Fake preprocessing (trusted dealer; Sec. IV-A uses fake preprocessing).  */
+/* Not part of the online phase; used to build inputs on the device.        */
+/* ---------------------------------------------------------------------- */
+
+/* Party MAC-key shares alpha_i for `seed` (HOST [n][L]); computed on the host. */
+spdz_status spdz_deal_alpha(const uint64_t *p_limbs, int n_limbs, int n_parties, uint64_t seed,
+                            uint64_t *alpha_out);
+
+/* Deal array `array_id` of `seed`: if values == NULL the secret values are
+ * drawn uniformly (and written to values_out [L][len] if it is not NULL);
+ * otherwise values (device [L][len]) are shared.  Shares and MAC shares are
+ * written to out (out->len elements). */
+spdz_status spdz_deal_secret(spdz_ctx *ctx, uint64_t seed, uint64_t array_id,
+                             const uint64_t *values, spdz_shares *out, uint64_t *values_out);
+
+/* Deal a Beaver triple with ids array_id (a), +1 (b), +2 (c = a b). */
+spdz_status spdz_deal_triple(spdz_ctx *ctx, uint64_t seed, uint64_t array_id, spdz_triple *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPDZ_H */

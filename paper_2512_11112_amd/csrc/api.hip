@@ -1,0 +1,293 @@
+// C-ABI entry points of libspdz: argument validation, context state and the
+// opened-value log bookkeeping.  The arithmetic lives in the kernels.
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+
+#include "ctx.h"
+
+using namespace spdz;
+
+namespace {
+
+bool supported_modulus(const u64 *p, int L) {
+  if (L == 1) return p[0] == F61::P;
+  if (L == 2) return p[0] == ~0ull && p[1] == F127::PHI;
+  return false;
+}
+
+// every element of a descriptor must stay inside the caller's buffers; only
+// the descriptor itself can be checked here
+spdz_status check_sv(const spdz_ctx *c, const spdz_shares *s, int64_t len) {
+  if (!s) return SPDZ_E_INVAL;
+  if (s->len != len || len < 0) return SPDZ_E_SHAPE;
+  if (len == 0) return SPDZ_OK;
+  if (!s->val || !s->mac) return SPDZ_E_INVAL;
+  if (s->limb_stride < (c->L > 1 ? s->len : 0) || s->party_stride < c->L * s->len) return SPDZ_E_SHAPE;
+  return SPDZ_OK;
+}
+
+bool overlaps(const spdz_ctx *c, const spdz_shares *a, const spdz_shares *b) {
+  // conservative byte-range test of the value and MAC extents
+  auto ext = [&](const u64 *p, const spdz_shares *s, const u64 *&lo, const u64 *&hi) {
+    lo = p;
+    hi = p + (int64_t)(c->n - 1) * s->party_stride + (int64_t)(c->L - 1) * s->limb_stride + s->len;
+  };
+  const u64 *ptrs_a[2] = {a->val, a->mac}, *ptrs_b[2] = {b->val, b->mac};
+  for (int i = 0; i < 2; i++)
+    for (int j = 0; j < 2; j++) {
+      const u64 *alo, *ahi, *blo, *bhi;
+      ext(ptrs_a[i], a, alo, ahi);
+      ext(ptrs_b[j], b, blo, bhi);
+      if (alo < bhi && blo < ahi) return true;
+    }
+  return false;
+}
+
+#define SPDZ_CHECK(expr)                     \
+  do {                                       \
+    spdz_status _s = (expr);                 \
+    if (_s != SPDZ_OK) return _s;            \
+  } while (0)
+
+#define SPDZ_LIVE(c)                              \
+  do {                                            \
+    if (!(c)) return SPDZ_E_INVAL;                \
+    if ((c)->aborted) return SPDZ_E_ABORTED;      \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+const char *spdz_status_str(spdz_status s) {
+  switch (s) {
+    case SPDZ_OK: return "ok";
+    case SPDZ_MAC_REJECT: return "MAC check rejected: protocol aborted";
+    case SPDZ_E_INVAL: return "invalid argument";
+    case SPDZ_E_MODULUS: return "unsupported modulus";
+    case SPDZ_E_SHAPE: return "shape mismatch";
+    case SPDZ_E_NOMEM: return "device allocation failed";
+    case SPDZ_E_HIP: return "HIP runtime error";
+    case SPDZ_E_ABORTED: return "context aborted by a failed MAC check";
+    case SPDZ_E_UNSUPPORTED: return "unsupported party count or variant";
+  }
+  return "unknown status";
+}
+
+spdz_status spdz_ctx_create(spdz_ctx **out, int n_parties, const uint64_t *p_limbs, int n_limbs,
+                            const uint64_t *alpha_shares, uint64_t check_seed, void *hip_stream) {
+  if (!out || !p_limbs || !alpha_shares) return SPDZ_E_INVAL;
+  *out = nullptr;
+  if (n_parties < MIN_PARTIES || n_parties > MAX_PARTIES) return SPDZ_E_UNSUPPORTED;
+  if (!supported_modulus(p_limbs, n_limbs)) return SPDZ_E_MODULUS;
+  spdz_ctx *c = new (std::nothrow) spdz_ctx();
+  if (!c) return SPDZ_E_NOMEM;
+  c->n = n_parties;
+  c->L = n_limbs;
+  for (int l = 0; l < n_limbs; l++) c->p[l] = p_limbs[l];
+  for (int i = 0; i < n_parties; i++) {
+    for (int l = 0; l < n_limbs; l++) c->alpha[i][l] = alpha_shares[i * n_limbs + l];
+    // alpha_i must be canonical
+    bool ok = n_limbs == 1 ? c->alpha[i][0] < F61::P
+                           : (c->alpha[i][1] < F127::PHI || (c->alpha[i][1] == F127::PHI && c->alpha[i][0] != ~0ull));
+    if (!ok) {
+      delete c;
+      return SPDZ_E_INVAL;
+    }
+  }
+  c->check_seed = check_seed;
+  c->stream = (hipStream_t)hip_stream;
+  if (const char *g = getenv("SPDZ_GRID_PER_CU")) c->grid_mult = atoi(g);
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&c->device) != hipSuccess || hipGetDeviceProperties(&prop, c->device) != hipSuccess) {
+    delete c;
+    return SPDZ_E_HIP;
+  }
+  c->num_cus = prop.multiProcessorCount;
+  const size_t acc_words = (size_t)MAX_SLOTS * (n_parties + 1) * n_limbs;
+  const size_t red_words = (size_t)MAX_SLOTS * 2 * n_parties * n_limbs;
+  if (hipMalloc((void **)&c->d_acc, acc_words * 8) != hipSuccess ||
+      hipMalloc((void **)&c->d_red, red_words * 8) != hipSuccess ||
+      hipMalloc((void **)&c->d_sigma, (size_t)n_parties * n_limbs * 8) != hipSuccess ||
+      hipHostMalloc((void **)&c->h_sigma, (size_t)n_parties * n_limbs * 8, hipHostMallocDefault) != hipSuccess) {
+    spdz_ctx_destroy(c);
+    return SPDZ_E_NOMEM;
+  }
+  if (hipMemset(c->d_acc, 0, acc_words * 8) != hipSuccess || hipMemset(c->d_red, 0, red_words * 8) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
+    spdz_ctx_destroy(c);
+    return SPDZ_E_HIP;
+  }
+  *out = c;
+  return SPDZ_OK;
+}
+
+spdz_status spdz_ctx_destroy(spdz_ctx *c) {
+  if (!c) return SPDZ_OK;
+  if (c->stream || c->d_acc) hipStreamSynchronize(c->stream);
+  if (c->d_acc) hipFree(c->d_acc);
+  if (c->d_red) hipFree(c->d_red);
+  if (c->d_sigma) hipFree(c->d_sigma);
+  if (c->h_sigma) hipHostFree(c->h_sigma);
+  delete c;
+  return SPDZ_OK;
+}
+
+int64_t spdz_opened_count(const spdz_ctx *c) { return c ? c->log_count : -1; }
+
+spdz_status spdz_open(spdz_ctx *c, const spdz_shares *x, uint64_t *out_pub) {
+  SPDZ_LIVE(c);
+  if (!x || !out_pub) return SPDZ_E_INVAL;
+  SPDZ_CHECK(check_sv(c, x, x->len));
+  if (x->len == 0) return SPDZ_OK;
+  return launch_open(c, x, out_pub);
+}
+
+static spdz_status check_mul_operands(spdz_ctx *c, const spdz_shares *x, const spdz_shares *y, const spdz_triple *t,
+                                      const spdz_shares *z) {
+  if (!x || !y || !t || !z) return SPDZ_E_INVAL;
+  const int64_t W = x->len;
+  SPDZ_CHECK(check_sv(c, x, W));
+  SPDZ_CHECK(check_sv(c, y, W));
+  SPDZ_CHECK(check_sv(c, &t->a, W));
+  SPDZ_CHECK(check_sv(c, &t->b, W));
+  SPDZ_CHECK(check_sv(c, &t->c, W));
+  SPDZ_CHECK(check_sv(c, z, W));
+  if (W == 0) return SPDZ_OK;
+  if (overlaps(c, z, x) || overlaps(c, z, y) || overlaps(c, z, &t->a) || overlaps(c, z, &t->b) ||
+      overlaps(c, z, &t->c))
+    return SPDZ_E_INVAL;
+  return SPDZ_OK;
+}
+
+spdz_status spdz_mul_batch(spdz_ctx *c, const spdz_shares *x, const spdz_shares *y, const spdz_triple *t,
+                           spdz_shares *z, uint64_t *d_pub, uint64_t *e_pub) {
+  SPDZ_LIVE(c);
+  SPDZ_CHECK(check_mul_operands(c, x, y, t, z));
+  if (x->len == 0) return SPDZ_OK;
+  return launch_beaver(c, x, y, t, z, d_pub, e_pub, nullptr, nullptr, nullptr, nullptr);
+}
+
+spdz_status spdz_mul_fused(spdz_ctx *c, const spdz_shares *x, const spdz_shares *y, const spdz_triple *t,
+                           spdz_shares *z, uint64_t *d_pub, uint64_t *e_pub, const uint64_t *lin, spdz_shares *w,
+                           uint64_t *w_pub, spdz_shares *s) {
+  SPDZ_LIVE(c);
+  SPDZ_CHECK(check_mul_operands(c, x, y, t, z));
+  if (w) {
+    if (!lin) return SPDZ_E_INVAL;
+    SPDZ_CHECK(check_sv(c, w, x->len));
+    if (x->len > 0 && overlaps(c, w, x) || overlaps(c, w, y) || overlaps(c, w, z)) return SPDZ_E_INVAL;
+  } else if (w_pub) {
+    return SPDZ_E_INVAL;
+  }
+  if (s) SPDZ_CHECK(check_sv(c, s, 1));
+  if (x->len == 0) return SPDZ_OK;
+  return launch_beaver(c, x, y, t, z, d_pub, e_pub, lin, w, w_pub, s);
+}
+
+spdz_status spdz_linear(spdz_ctx *c, int n_terms, const spdz_shares *terms, const uint64_t *coeffs,
+                        const uint64_t *c0, spdz_shares *out) {
+  SPDZ_LIVE(c);
+  if (!terms || !coeffs || !out || n_terms < 1 || n_terms > 8) return SPDZ_E_INVAL;
+  for (int k = 0; k < n_terms; k++) SPDZ_CHECK(check_sv(c, &terms[k], out->len));
+  SPDZ_CHECK(check_sv(c, out, out->len));
+  if (out->len == 0) return SPDZ_OK;
+  return launch_linear(c, n_terms, terms, coeffs, c0, out);
+}
+
+spdz_status spdz_reduce_add(spdz_ctx *c, const spdz_shares *x, spdz_shares *out) {
+  SPDZ_LIVE(c);
+  if (!x || !out) return SPDZ_E_INVAL;
+  SPDZ_CHECK(check_sv(c, x, x->len));
+  SPDZ_CHECK(check_sv(c, out, 1));
+  return launch_reduce(c, x, out);
+}
+
+spdz_status spdz_mac_check(spdz_ctx *c, int *accepted, uint64_t *sigma_out) {
+  SPDZ_LIVE(c);
+  if (!accepted) return SPDZ_E_INVAL;
+  *accepted = 0;
+  SPDZ_CHECK(launch_maccheck_finalize(c));
+  const size_t bytes = (size_t)c->n * c->L * 8;
+  if (hipMemcpyAsync(c->h_sigma, c->d_sigma, bytes, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return SPDZ_E_HIP;
+  if (sigma_out) memcpy(sigma_out, c->h_sigma, bytes);
+  // accept iff sum_i sigma_i = 0 mod p (host-side sum of n residues)
+  bool zero;
+  if (c->L == 1) {
+    u64 s = 0;
+    for (int i = 0; i < c->n; i++) {
+      s += c->h_sigma[i];
+      if (s >= F61::P) s -= F61::P;
+    }
+    zero = s == 0;
+  } else {
+    u128 p = ((u128)F127::PHI << 64) | ~0ull, s = 0;
+    for (int i = 0; i < c->n; i++) {
+      s += ((u128)c->h_sigma[2 * i + 1] << 64) | c->h_sigma[2 * i];
+      if (s >= p) s -= p;
+    }
+    zero = s == 0;
+  }
+  c->epoch += 1;
+  c->log_count = 0;
+  c->slots = 0;
+  if (!zero) {
+    c->aborted = true;
+    return SPDZ_MAC_REJECT;
+  }
+  *accepted = 1;
+  return SPDZ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// fake preprocessing
+// ---------------------------------------------------------------------------
+spdz_status spdz_deal_alpha(const uint64_t *p_limbs, int n_limbs, int n_parties, uint64_t seed,
+                            uint64_t *alpha_out) {
+  if (!p_limbs || !alpha_out || n_parties < 1 || n_parties > MAX_PARTIES) return SPDZ_E_INVAL;
+  if (!supported_modulus(p_limbs, n_limbs)) return SPDZ_E_MODULUS;
+  const u64 state = sm_out(seed, stream_id(TAG_ALPHA, 0, 0));
+  for (int i = 0; i < n_parties; i++) {
+    // element i of the uniform stream (same rejection rule as the device dealer)
+    const u64 base = (u64)i * 32u;
+    u64 lo = 0, hi = 0;
+    for (int k = 0; k < 16; k++) {
+      if (n_limbs == 1) {
+        u64 u = sm_out(state, base + k) & F61::P;
+        if (u < F61::P) { lo = u; break; }
+      } else {
+        u64 l = sm_out(state, base + 2 * k), h = sm_out(state, base + 2 * k + 1) & F127::PHI;
+        if (!(h == F127::PHI && l == ~0ull)) { lo = l; hi = h; break; }
+      }
+    }
+    alpha_out[i * n_limbs] = lo;
+    if (n_limbs == 2) alpha_out[i * n_limbs + 1] = hi;
+  }
+  return SPDZ_OK;
+}
+
+spdz_status spdz_deal_secret(spdz_ctx *c, uint64_t seed, uint64_t array_id, const uint64_t *values, spdz_shares *out,
+                             uint64_t *values_out) {
+  SPDZ_LIVE(c);
+  if (!out) return SPDZ_E_INVAL;
+  SPDZ_CHECK(check_sv(c, out, out->len));
+  if (out->len == 0) return SPDZ_OK;
+  return launch_deal_secret(c, seed, array_id, values, out, values_out);
+}
+
+spdz_status spdz_deal_triple(spdz_ctx *c, uint64_t seed, uint64_t array_id, spdz_triple *t) {
+  SPDZ_LIVE(c);
+  if (!t) return SPDZ_E_INVAL;
+  const int64_t W = t->a.len;
+  SPDZ_CHECK(check_sv(c, &t->a, W));
+  SPDZ_CHECK(check_sv(c, &t->b, W));
+  SPDZ_CHECK(check_sv(c, &t->c, W));
+  if (W == 0) return SPDZ_OK;
+  return launch_deal_triple(c, seed, array_id, t);
+}
+
+}  // extern "C"

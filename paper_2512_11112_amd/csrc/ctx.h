@@ -1,0 +1,91 @@
+// Internal state of a libspdz context and the launchers shared by the
+// translation units.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "../../include/spdz.h"
+#include "field.h"
+
+namespace spdz {
+
+constexpr int MAX_PARTIES = 8;
+constexpr int MIN_PARTIES = 2;
+constexpr int BLOCK = 256;          // threads per block of the element-wise kernels
+constexpr int WAVES = BLOCK / 64;   // wave64
+constexpr int MAX_SLOTS = 4096;     // per-block accumulator slots (upper bound on grid size)
+
+// stream-id layout of the dealer and the MAC-check coefficients:
+// stream = tag << 56 | array_id << 8 | party
+constexpr u64 TAG_ALPHA = 1, TAG_VALUE = 2, TAG_SHARE = 3, TAG_MACSH = 4, TAG_COEF = 5;
+inline u64 stream_id(u64 tag, u64 array_id, u64 party) { return (tag << 56) | (array_id << 8) | party; }
+
+// device view of a spdz_shares descriptor
+struct SV {
+  u64 *val, *mac;
+  int64_t ps, ls;
+};
+inline SV sv_of(const spdz_shares *s) { return SV{s->val, s->mac, s->party_stride, s->limb_stride}; }
+
+}  // namespace spdz
+
+struct spdz_ctx {
+  int n = 0, L = 0;
+  spdz::u64 p[2] = {0, 0};
+  spdz::u64 alpha[spdz::MAX_PARTIES][2] = {};
+  spdz::u64 check_seed = 0, epoch = 0;
+  int64_t log_count = 0;
+  bool aborted = false;
+  hipStream_t stream = nullptr;
+  int device = 0, num_cus = 0;
+  int slots = 0;                // accumulator slots in use (= max grid of accumulating kernels)
+  spdz::u64 *d_acc = nullptr;   // MAC-check partial sums [MAX_SLOTS][n + 1][L]
+  spdz::u64 *d_red = nullptr;   // ReduceAdd partial sums [MAX_SLOTS][2 n][L]
+  spdz::u64 *d_sigma = nullptr; // [n][L]
+  spdz::u64 *h_sigma = nullptr; // pinned host copy of d_sigma
+  int grid_mult = 0;            // blocks per CU for streaming kernels (0 = from occupancy)
+};
+
+namespace spdz {
+
+// coefficient-stream state of the current MAC check
+inline u64 coef_state(const spdz_ctx *c) { return sm_out(c->check_seed, stream_id(TAG_COEF, c->epoch, 0)); }
+
+// run fn(F{}, std::integral_constant<int, N>{}) for the context's field and party count
+template <class F, class Fn>
+spdz_status visit_n(int n, Fn &&fn) {
+  switch (n) {
+    case 2: return fn(F{}, std::integral_constant<int, 2>{});
+    case 3: return fn(F{}, std::integral_constant<int, 3>{});
+    case 4: return fn(F{}, std::integral_constant<int, 4>{});
+    case 5: return fn(F{}, std::integral_constant<int, 5>{});
+    case 6: return fn(F{}, std::integral_constant<int, 6>{});
+    case 7: return fn(F{}, std::integral_constant<int, 7>{});
+    case 8: return fn(F{}, std::integral_constant<int, 8>{});
+  }
+  return SPDZ_E_UNSUPPORTED;
+}
+template <class Fn>
+spdz_status visit(const spdz_ctx *c, Fn &&fn) {
+  return c->L == 1 ? visit_n<F61>(c->n, fn) : visit_n<F127>(c->n, fn);
+}
+
+inline spdz_status hip_status(hipError_t e) { return e == hipSuccess ? SPDZ_OK : SPDZ_E_HIP; }
+
+// launchers (elementwise.hip)
+spdz_status launch_open(spdz_ctx *c, const spdz_shares *x, u64 *out_pub);
+spdz_status launch_beaver(spdz_ctx *c, const spdz_shares *x, const spdz_shares *y, const spdz_triple *t,
+                          spdz_shares *z, u64 *d_pub, u64 *e_pub, const u64 *lin, spdz_shares *w, u64 *w_pub,
+                          spdz_shares *s);
+spdz_status launch_linear(spdz_ctx *c, int nt, const spdz_shares *terms, const u64 *coeffs, const u64 *c0,
+                          spdz_shares *out);
+spdz_status launch_reduce(spdz_ctx *c, const spdz_shares *x, spdz_shares *out);
+spdz_status launch_reduce_finalize(spdz_ctx *c, int grid, spdz_shares *out);
+spdz_status launch_maccheck_finalize(spdz_ctx *c);
+spdz_status launch_deal_secret(spdz_ctx *c, u64 seed, u64 array_id, const u64 *values, spdz_shares *out,
+                               u64 *values_out);
+spdz_status launch_deal_triple(spdz_ctx *c, u64 seed, u64 array_id, spdz_triple *t);
+
+}  // namespace spdz

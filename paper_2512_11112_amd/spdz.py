@@ -1,0 +1,267 @@
+"""ctypes binding of libspdz (include/spdz.h): argument marshalling only.
+
+Device buffers are torch tensors on the GPU (int64 storage holding the raw
+64-bit limbs); every computation runs in the library's HIP kernels.  The
+binding fails loudly when libspdz.so is missing or a call returns an error.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspdz.so")
+
+P61 = (1 << 61) - 1
+P127 = (1 << 127) - 1
+
+SPDZ_OK = 0
+SPDZ_MAC_REJECT = 1
+
+
+class SpdzError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_str(status)} ({status})")
+
+
+class Shares(ctypes.Structure):
+    _fields_ = [("val", ctypes.c_void_p), ("mac", ctypes.c_void_p), ("len", ctypes.c_int64),
+                ("party_stride", ctypes.c_int64), ("limb_stride", ctypes.c_int64)]
+
+
+class Triple(ctypes.Structure):
+    _fields_ = [("a", Shares), ("b", Shares), ("c", Shares)]
+
+
+u64p = ctypes.POINTER(ctypes.c_uint64)
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libspdz.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libspdz.so not built at {LIB_PATH}: run python -m paper_2512_11112_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+        sig = {
+            "spdz_status_str": (ctypes.c_char_p, [i32]),
+            "spdz_ctx_create": (i32, [ctypes.POINTER(vp), i32, u64p, i32, u64p, ctypes.c_uint64, vp]),
+            "spdz_ctx_destroy": (i32, [vp]),
+            "spdz_opened_count": (i64, [vp]),
+            "spdz_open": (i32, [vp, ctypes.POINTER(Shares), vp]),
+            "spdz_mul_batch": (i32, [vp, ctypes.POINTER(Shares), ctypes.POINTER(Shares),
+                                     ctypes.POINTER(Triple), ctypes.POINTER(Shares), vp, vp]),
+            "spdz_mul_fused": (i32, [vp, ctypes.POINTER(Shares), ctypes.POINTER(Shares),
+                                     ctypes.POINTER(Triple), ctypes.POINTER(Shares), vp, vp, u64p,
+                                     ctypes.POINTER(Shares), vp, ctypes.POINTER(Shares)]),
+            "spdz_linear": (i32, [vp, i32, ctypes.POINTER(Shares), u64p, u64p, ctypes.POINTER(Shares)]),
+            "spdz_reduce_add": (i32, [vp, ctypes.POINTER(Shares), ctypes.POINTER(Shares)]),
+            "spdz_mac_check": (i32, [vp, ctypes.POINTER(i32), u64p]),
+            "spdz_deal_alpha": (i32, [u64p, i32, i32, ctypes.c_uint64, u64p]),
+            "spdz_deal_secret": (i32, [vp, ctypes.c_uint64, ctypes.c_uint64, vp,
+                                       ctypes.POINTER(Shares), vp]),
+            "spdz_deal_triple": (i32, [vp, ctypes.c_uint64, ctypes.c_uint64, ctypes.POINTER(Triple)]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_str(s: int) -> str:
+    return lib().spdz_status_str(int(s)).decode()
+
+
+def _check(s: int, where: str) -> int:
+    if s < 0:
+        raise SpdzError(s, where)
+    return s
+
+
+def n_limbs(p: int) -> int:
+    return 1 if p < (1 << 64) else 2
+
+
+def limbs(v: int, L: int):
+    return (ctypes.c_uint64 * L)(*[(v >> (64 * l)) & ((1 << 64) - 1) for l in range(L)])
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------------------------
+@dataclass
+class ShareTensor:
+    """Values and MAC shares of a batch, device tensors [n][L][W] (canonical layout)."""
+    val: torch.Tensor
+    mac: torch.Tensor
+
+    @staticmethod
+    def empty(n: int, L: int, W: int, device="cuda") -> "ShareTensor":
+        return ShareTensor(torch.empty((n, L, W), dtype=torch.int64, device=device),
+                           torch.empty((n, L, W), dtype=torch.int64, device=device))
+
+    @property
+    def width(self) -> int:
+        return self.val.shape[-1]
+
+    def desc(self) -> Shares:
+        v, m = self.val, self.mac
+        assert v.is_cuda and m.is_cuda and v.dtype == torch.int64 and v.shape == m.shape
+        if v.numel() == 0:
+            return Shares(None, None, v.shape[2], 0, 0)
+        assert v.stride() == m.stride() and v.stride(2) == 1
+        return Shares(v.data_ptr(), m.data_ptr(), v.shape[2], v.stride(0), v.stride(1))
+
+
+@dataclass
+class TripleTensor:
+    a: ShareTensor
+    b: ShareTensor
+    c: ShareTensor
+
+    @staticmethod
+    def empty(n, L, W, device="cuda") -> "TripleTensor":
+        return TripleTensor(*(ShareTensor.empty(n, L, W, device) for _ in range(3)))
+
+    def desc(self) -> Triple:
+        return Triple(self.a.desc(), self.b.desc(), self.c.desc())
+
+
+def deal_alpha(p: int, n: int, seed: int) -> list:
+    """alpha_i of the fake-preprocessing dealer, as Python ints."""
+    L = n_limbs(p)
+    out = (ctypes.c_uint64 * (n * L))()
+    _check(lib().spdz_deal_alpha(limbs(p, L), L, n, ctypes.c_uint64(seed), out), "spdz_deal_alpha")
+    return [sum(int(out[i * L + l]) << (64 * l) for l in range(L)) for i in range(n)]
+
+
+class Context:
+    """A libspdz context (spdz_ctx) for n parties over p, on a torch stream."""
+
+    def __init__(self, n: int, p: int, alpha_shares: Sequence[int], check_seed: int,
+                 stream: Optional[torch.cuda.Stream] = None):
+        self.n, self.p, self.L = n, p, n_limbs(p)
+        self.alpha = list(alpha_shares)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        al = (ctypes.c_uint64 * (n * self.L))()
+        for i, a in enumerate(self.alpha):
+            for l in range(self.L):
+                al[i * self.L + l] = (a >> (64 * l)) & ((1 << 64) - 1)
+        h = ctypes.c_void_p()
+        _check(lib().spdz_ctx_create(ctypes.byref(h), n, limbs(p, self.L), self.L, al,
+                                     ctypes.c_uint64(check_seed),
+                                     ctypes.c_void_p(self.stream.cuda_stream)), "spdz_ctx_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().spdz_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- helpers --------------------------------------------------------------
+    def new_shares(self, W: int) -> ShareTensor:
+        return ShareTensor.empty(self.n, self.L, W)
+
+    def new_public(self, W: int) -> torch.Tensor:
+        return torch.empty((self.L, W), dtype=torch.int64, device="cuda")
+
+    def opened_count(self) -> int:
+        return int(lib().spdz_opened_count(self._h))
+
+    # -- online phase ----------------------------------------------------------
+    def spdz_open(self, x: ShareTensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        out = self.new_public(x.width) if out is None else out
+        d = x.desc()
+        _check(lib().spdz_open(self._h, ctypes.byref(d), _ptr(out)), "spdz_open")
+        return out
+
+    def spdz_mul_batch(self, x: ShareTensor, y: ShareTensor, t: TripleTensor, z: ShareTensor,
+                       d_pub: Optional[torch.Tensor] = None, e_pub: Optional[torch.Tensor] = None):
+        dx, dy, dt, dz = x.desc(), y.desc(), t.desc(), z.desc()
+        _check(lib().spdz_mul_batch(self._h, ctypes.byref(dx), ctypes.byref(dy), ctypes.byref(dt),
+                                    ctypes.byref(dz), _ptr(d_pub), _ptr(e_pub)), "spdz_mul_batch")
+        return z
+
+    def spdz_mul_fused(self, x, y, t, z, d_pub=None, e_pub=None, lin: Optional[Sequence[int]] = None,
+                       w: Optional[ShareTensor] = None, w_pub: Optional[torch.Tensor] = None,
+                       s: Optional[ShareTensor] = None):
+        dx, dy, dt, dz = x.desc(), y.desc(), t.desc(), z.desc()
+        lin_arr = None
+        if lin is not None:
+            lin_arr = (ctypes.c_uint64 * (4 * self.L))()
+            for k, c in enumerate(lin):
+                for l in range(self.L):
+                    lin_arr[k * self.L + l] = (c >> (64 * l)) & ((1 << 64) - 1)
+        dw = w.desc() if w is not None else None
+        ds = s.desc() if s is not None else None
+        _check(lib().spdz_mul_fused(self._h, ctypes.byref(dx), ctypes.byref(dy), ctypes.byref(dt),
+                                    ctypes.byref(dz), _ptr(d_pub), _ptr(e_pub), lin_arr,
+                                    ctypes.byref(dw) if dw is not None else None, _ptr(w_pub),
+                                    ctypes.byref(ds) if ds is not None else None), "spdz_mul_fused")
+
+    def spdz_linear(self, terms: Sequence[ShareTensor], coeffs: Sequence[int], c0: int = 0,
+                    out: Optional[ShareTensor] = None) -> ShareTensor:
+        k = len(terms)
+        out = self.new_shares(terms[0].width) if out is None else out
+        arr = (Shares * k)(*[t.desc() for t in terms])
+        cf = (ctypes.c_uint64 * (k * self.L))()
+        for i, c in enumerate(coeffs):
+            for l in range(self.L):
+                cf[i * self.L + l] = (c >> (64 * l)) & ((1 << 64) - 1)
+        do = out.desc()
+        _check(lib().spdz_linear(self._h, k, arr, cf, limbs(c0, self.L), ctypes.byref(do)),
+               "spdz_linear")
+        return out
+
+    def spdz_reduce_add(self, x: ShareTensor, out: Optional[ShareTensor] = None) -> ShareTensor:
+        out = self.new_shares(1) if out is None else out
+        dx, do = x.desc(), out.desc()
+        _check(lib().spdz_reduce_add(self._h, ctypes.byref(dx), ctypes.byref(do)), "spdz_reduce_add")
+        return out
+
+    def spdz_mac_check(self):
+        """(accepted, [sigma_i as ints])."""
+        acc = ctypes.c_int(0)
+        sig = (ctypes.c_uint64 * (self.n * self.L))()
+        s = _check(lib().spdz_mac_check(self._h, ctypes.byref(acc), sig), "spdz_mac_check")
+        sigma = [sum(int(sig[i * self.L + l]) << (64 * l) for l in range(self.L)) for i in range(self.n)]
+        return bool(acc.value) and s == SPDZ_OK, sigma
+
+    # -- fake preprocessing ---------------------------------------------------
+    def spdz_deal_secret(self, seed: int, array_id: int, out: ShareTensor,
+                         values: Optional[torch.Tensor] = None,
+                         values_out: Optional[torch.Tensor] = None) -> ShareTensor:
+        d = out.desc()
+        _check(lib().spdz_deal_secret(self._h, ctypes.c_uint64(seed), ctypes.c_uint64(array_id),
+                                      _ptr(values), ctypes.byref(d), _ptr(values_out)),
+               "spdz_deal_secret")
+        return out
+
+    def spdz_deal_triple(self, seed: int, array_id: int, out: TripleTensor) -> TripleTensor:
+        d = out.desc()
+        _check(lib().spdz_deal_triple(self._h, ctypes.c_uint64(seed), ctypes.c_uint64(array_id),
+                                      ctypes.byref(d)), "spdz_deal_triple")
+        return out

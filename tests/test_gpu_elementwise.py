@@ -1,0 +1,235 @@
+"""Bit-exact parity of the element-wise HIP path against the CPU oracle.
+
+Inputs are dealt by the oracle (CPU) and copied to the device; every output
+array (shares, MAC shares, opened values), every sigma_i and every verdict
+must equal the oracle's bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle.fast as F
+from oracle.pipelines import beaver_run, bump_share, deal_elementwise, pipeline_run
+from tests._util import dev, host, ints_of_sigma, share_to_dev, triple_to_dev
+from workloads import ARR_A, ARR_X, P61, P127, tamper_index
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2512_11112_amd import spdz
+    spdz.lib()
+
+
+def make_ctx(D, check_seed):
+    from paper_2512_11112_amd.spdz import Context
+    return Context(D.n, D.f.p, ints_of_sigma(D.alpha), check_seed)
+
+
+def eq_shares(t, s: F.Shares, what=""):
+    assert np.array_equal(host(t.val), s.val), f"{what} values differ"
+    assert np.array_equal(host(t.mac), s.mac), f"{what} MAC shares differ"
+
+
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("p,n,W", [(P61, 2, 1000), (P61, 5, 4097), (P127, 3, 4099), (P127, 2, 1)])
+def test_device_dealer_matches_oracle(p, n, W):
+    from paper_2512_11112_amd.spdz import ShareTensor, TripleTensor
+    D = deal_elementwise(p, n, W, 7)
+    ctx = make_ctx(D, 0)
+    L = D.f.L
+    x = ShareTensor.empty(n, L, W)
+    xv = torch.empty((L, W), dtype=torch.int64, device="cuda")
+    ctx.spdz_deal_secret(7, ARR_X, x, values_out=xv)
+    t = TripleTensor.empty(n, L, W)
+    ctx.spdz_deal_triple(7, ARR_A, t)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(xv), D.xs)
+    eq_shares(x, D.x, "x")
+    eq_shares(t.a, D.t.a, "a")
+    eq_shares(t.b, D.t.b, "b")
+    eq_shares(t.c, D.t.c, "c")
+    # sharing given values
+    y = ShareTensor.empty(n, L, W)
+    ctx.spdz_deal_secret(7, 1, y, values=dev(D.ys))
+    torch.cuda.synchronize()
+    eq_shares(y, D.y, "y")
+
+
+# --------------------------------------------------------------------------
+MUL_CASES = [(P61, 2, 1), (P61, 2, 1 << 16), (P61, 3, 100003), (P61, 8, 3001),
+             (P127, 3, 1), (P127, 3, 65539), (P127, 2, 5000), (P127, 6, 777)]
+
+
+@pytest.mark.parametrize("p,n,W", MUL_CASES)
+def test_mul_batch_and_mac_check(p, n, W):
+    from paper_2512_11112_amd.spdz import ShareTensor
+    print(f"case p-bits={p.bit_length()} n={n} W={W}", flush=True)
+    D = deal_elementwise(p, n, W, 1)
+    ref = beaver_run(D, check_seed=1)
+    ctx = make_ctx(D, 1)
+    z = ShareTensor.empty(n, D.f.L, W)
+    dp, ep = ctx.new_public(W), ctx.new_public(W)
+    ctx.spdz_mul_batch(share_to_dev(D.x), share_to_dev(D.y), triple_to_dev(D.t), z, dp, ep)
+    assert ctx.opened_count() == 2 * W
+    ok, sigma = ctx.spdz_mac_check()
+    eq_shares(z, ref["z"], "z")
+    assert np.array_equal(host(dp), ref["d"]) and np.array_equal(host(ep), ref["e"])
+    assert ok and ref["ok"]
+    assert sigma == ints_of_sigma(ref["sigma"])
+    assert ctx.opened_count() == 0
+
+
+@pytest.mark.parametrize("p,n,W", [(P61, 2, 70001), (P127, 3, 70001), (P127, 4, 333)])
+def test_open_linear_reduce(p, n, W):
+    """open(x); w = c1 x + c2 y + c0; s = ReduceAdd(w); open(s); MAC check over [x, s]."""
+    D = deal_elementwise(p, n, W, 2)
+    f = D.f
+    c = [p - 2, (1 << 60) + 12345, 987654321]
+    log = F.MacLog(f, n, 2, 0)
+    xo = f.open(D.x.val)
+    log.add(xo, D.x.mac)
+    w = f.linear(D.alpha, [D.x, D.y], c[:2], c[2])
+    s = f.reduce_add(w)
+    so = f.open(s.val)
+    log.add(so, s.mac)
+    ok, sig = log.check(D.alpha)
+
+    ctx = make_ctx(D, 2)
+    xd, yd = share_to_dev(D.x), share_to_dev(D.y)
+    xo_d = ctx.spdz_open(xd)
+    wd = ctx.spdz_linear([xd, yd], c[:2], c[2])
+    sd = ctx.spdz_reduce_add(wd)
+    so_d = ctx.spdz_open(sd)
+    ok_d, sig_d = ctx.spdz_mac_check()
+    assert np.array_equal(host(xo_d), xo)
+    eq_shares(wd, w, "w")
+    eq_shares(sd, s, "s")
+    assert np.array_equal(host(so_d), so)
+    assert ok and ok_d and sig_d == ints_of_sigma(sig)
+
+
+def test_linear_aliasing_output():
+    """spdz_linear allows out to alias a term: x <- 5 x + y."""
+    D = deal_elementwise(P127, 3, 5001, 3)
+    f = D.f
+    ref = f.linear(D.alpha, [D.x, D.y], [5, 1], 0)
+    ctx = make_ctx(D, 3)
+    xd, yd = share_to_dev(D.x), share_to_dev(D.y)
+    ctx.spdz_linear([xd, yd], [5, 1], 0, out=xd)
+    torch.cuda.synchronize()
+    eq_shares(xd, ref, "x")
+
+
+# --------------------------------------------------------------------------
+def run_fused(D, check_seed, lin=None, with_pub=True):
+    from paper_2512_11112_amd.spdz import ShareTensor
+    n, L, W = D.n, D.f.L, D.x.width
+    ctx = make_ctx(D, check_seed)
+    lin = lin if lin is not None else (1, 3, D.f.p - 1, 0)
+    z, w, s = ShareTensor.empty(n, L, W), ShareTensor.empty(n, L, W), ShareTensor.empty(n, L, 1)
+    dp = ctx.new_public(W) if with_pub else None
+    ep = ctx.new_public(W) if with_pub else None
+    wp = ctx.new_public(W)
+    ctx.spdz_mul_fused(share_to_dev(D.x), share_to_dev(D.y), triple_to_dev(D.t), z, dp, ep,
+                       lin=lin, w=w, w_pub=wp, s=s)
+    sp = ctx.spdz_open(s)
+    assert ctx.opened_count() == 3 * W + 1
+    ok, sigma = ctx.spdz_mac_check()
+    return ctx, dict(z=z, w=w, s=s, d=dp, e=ep, wpub=wp, spub=sp, ok=ok, sigma=sigma)
+
+
+def check_fused(got, ref):
+    eq_shares(got["z"], ref["z"], "z")
+    eq_shares(got["w"], ref["w"], "w")
+    eq_shares(got["s"], ref["s"], "s")
+    if got["d"] is not None:
+        assert np.array_equal(host(got["d"]), ref["d"])
+        assert np.array_equal(host(got["e"]), ref["e"])
+    assert np.array_equal(host(got["wpub"]), ref["wpub"])
+    assert np.array_equal(host(got["spub"]), ref["spub"])
+    assert got["ok"] == ref["ok"]
+    assert got["sigma"] == ints_of_sigma(ref["sigma"])
+
+
+@pytest.mark.parametrize("p,n,W", [(P127, 3, (1 << 16) + 5), (P61, 2, 100001), (P127, 2, 3),
+                                   (P61, 4, 12345)])
+def test_fused_pipeline(p, n, W):
+    print(f"case p-bits={p.bit_length()} n={n} W={W}", flush=True)
+    D = deal_elementwise(p, n, W, 4)
+    ref = pipeline_run(D, check_seed=4)
+    _, got = run_fused(D, 4)
+    check_fused(got, ref)
+    assert got["ok"]
+
+
+def test_fused_general_coefficients():
+    p = P127
+    D = deal_elementwise(p, 3, 9999, 5)
+    lin = (p - 7, (1 << 126) + 3, 1 << 64, p - 1)
+    ref = pipeline_run(D, check_seed=5, lin=lin)
+    _, got = run_fused(D, 5, lin=lin, with_pub=False)
+    check_fused(got, ref)
+
+
+@pytest.mark.parametrize("p,n,W", [(P127, 3, 50000), (P61, 2, 50000)])
+def test_tampered_share_is_rejected(p, n, W):
+    """Party n-1's value share of one element of x bumped by one: the check must reject."""
+    from paper_2512_11112_amd.spdz import SpdzError
+    D = deal_elementwise(p, n, W, 6)
+    k = tamper_index(6, W)
+    bump_share(D.f, D.x, n - 1, k)
+    ref = pipeline_run(D, check_seed=6)
+    assert not ref["ok"]
+    ctx, got = run_fused(D, 6)
+    check_fused(got, ref)
+    assert not got["ok"]
+    with pytest.raises(SpdzError) as ei:
+        ctx.spdz_open(got["z"])
+    assert ei.value.status == -6
+
+
+def test_zero_width_and_shape_errors():
+    from paper_2512_11112_amd.spdz import ShareTensor, SpdzError
+    D = deal_elementwise(P61, 2, 10, 8)
+    ctx = make_ctx(D, 8)
+    e0 = ShareTensor.empty(2, 1, 0)
+    ctx.spdz_mul_batch(e0, e0, triple_to_dev(deal_elementwise(P61, 2, 0, 8).t), ShareTensor.empty(2, 1, 0))
+    assert ctx.opened_count() == 0
+    xd, yd = share_to_dev(D.x), share_to_dev(D.y)
+    short = ShareTensor.empty(2, 1, 9)
+    with pytest.raises(SpdzError) as ei:
+        ctx.spdz_mul_batch(xd, yd, triple_to_dev(D.t), short)
+    assert ei.value.status == -3
+    with pytest.raises(SpdzError) as ei:
+        ctx.spdz_mul_batch(xd, yd, triple_to_dev(D.t), xd)   # z aliases x
+    assert ei.value.status == -1
+    ok, _ = ctx.spdz_mac_check()   # empty log accepts
+    assert ok
+
+
+# --------------------------------------------------------------------------
+# full-size pipeline: 3 parties, p = 2^127 - 1, 2^24 elements, launched as the
+# benchmark launches it; compared in full, then repeated with a tampered share
+# --------------------------------------------------------------------------
+@pytest.mark.timeout(900)
+def test_pipeline_full_size_p127_n3():
+    W = 1 << 24
+    print("case full-size pipeline n=3 p=2^127-1 W=2^24", flush=True)
+    D = deal_elementwise(P127, 3, W, 0)
+    ref = pipeline_run(D, check_seed=0)
+    _, got = run_fused(D, 0)
+    check_fused(got, ref)
+    assert got["ok"]
+    del got, ref
+    torch.cuda.empty_cache()
+    k = tamper_index(0, W)
+    bump_share(D.f, D.x, 2, k)
+    ref = pipeline_run(D, check_seed=0)
+    _, got = run_fused(D, 0)
+    assert not ref["ok"] and not got["ok"]
+    assert got["sigma"] == ints_of_sigma(ref["sigma"])
+    assert np.array_equal(host(got["wpub"]), ref["wpub"])
