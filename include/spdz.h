@@ -160,6 +160,26 @@ spdz_status spdz_mul_fused(spdz_ctx *ctx, const spdz_shares *x, const spdz_share
 spdz_status spdz_mac_check(spdz_ctx *ctx, int *accepted, uint64_t *sigma_out);
 
 /* ---------------------------------------------------------------------- */
+/* Measurement (not part of the protocol)                                    */
+/* ---------------------------------------------------------------------- */
+
+/* Enable (1) or disable (0) kernel timing and clear the statistics.  While
+ * enabled, each call records HIP events on the context stream around its main
+ * kernel, named "beaver", "beaver_fused", "open", "linear", "reduce",
+ * "mac_finalize", "matmul_*" or "dag_level". */
+spdz_status spdz_timing_enable(spdz_ctx *ctx, int enable);
+
+/* Total event time (ms) and launch count of `kernel` since timing was
+ * enabled.  Waits for the recorded events. */
+spdz_status spdz_timing_get(spdz_ctx *ctx, const char *kernel, double *total_ms, int64_t *launches);
+
+/* Plain device copy of `words` 64-bit words (16-byte vector loads and
+ * non-temporal stores) on hip_stream: the bandwidth reference against which
+ * the element-wise kernels are compared.  dst and src are device pointers and
+ * must not overlap. */
+spdz_status spdz_copy_probe(uint64_t *dst, const uint64_t *src, int64_t words, void *hip_stream);
+
+/* ---------------------------------------------------------------------- */
 /* Fake preprocessing (trusted dealer; Sec. IV-A uses fake preprocessing).  */
 /* Not part of the online phase; used to build inputs on the device.        */
 /* ---------------------------------------------------------------------- */

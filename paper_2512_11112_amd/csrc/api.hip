@@ -127,6 +127,11 @@ spdz_status spdz_ctx_create(spdz_ctx **out, int n_parties, const uint64_t *p_lim
 spdz_status spdz_ctx_destroy(spdz_ctx *c) {
   if (!c) return SPDZ_OK;
   if (c->stream || c->d_acc) hipStreamSynchronize(c->stream);
+  for (auto &pd : c->pending) {
+    hipEventDestroy(pd.e0);
+    hipEventDestroy(pd.e1);
+  }
+  for (hipEvent_t e : c->event_pool) hipEventDestroy(e);
   if (c->d_acc) hipFree(c->d_acc);
   if (c->d_red) hipFree(c->d_red);
   if (c->d_sigma) hipFree(c->d_sigma);
@@ -241,6 +246,47 @@ spdz_status spdz_mac_check(spdz_ctx *c, int *accepted, uint64_t *sigma_out) {
   }
   *accepted = 1;
   return SPDZ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// measurement
+// ---------------------------------------------------------------------------
+static spdz_status drain_timing(spdz_ctx *c) {
+  for (auto &pd : c->pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(pd.e1) != hipSuccess || hipEventElapsedTime(&ms, pd.e0, pd.e1) != hipSuccess)
+      return SPDZ_E_HIP;
+    auto &st = c->kstats[pd.name];
+    st.first += ms;
+    st.second += 1;
+    c->event_pool.push_back(pd.e0);
+    c->event_pool.push_back(pd.e1);
+  }
+  c->pending.clear();
+  return SPDZ_OK;
+}
+
+spdz_status spdz_timing_enable(spdz_ctx *c, int enable) {
+  if (!c) return SPDZ_E_INVAL;
+  SPDZ_CHECK(drain_timing(c));
+  c->kstats.clear();
+  c->timing = enable != 0;
+  return SPDZ_OK;
+}
+
+spdz_status spdz_timing_get(spdz_ctx *c, const char *kernel, double *total_ms, int64_t *launches) {
+  if (!c || !kernel || !total_ms || !launches) return SPDZ_E_INVAL;
+  SPDZ_CHECK(drain_timing(c));
+  auto it = c->kstats.find(kernel);
+  *total_ms = it == c->kstats.end() ? 0.0 : it->second.first;
+  *launches = it == c->kstats.end() ? 0 : it->second.second;
+  return SPDZ_OK;
+}
+
+spdz_status spdz_copy_probe(uint64_t *dst, const uint64_t *src, int64_t words, void *hip_stream) {
+  if (!dst || !src || words < 0) return SPDZ_E_INVAL;
+  if (words == 0) return SPDZ_OK;
+  return launch_copy(dst, src, words, (hipStream_t)hip_stream);
 }
 
 // ---------------------------------------------------------------------------

@@ -4,7 +4,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
+#include <string>
 #include <type_traits>
+#include <vector>
 
 #include "../../include/spdz.h"
 #include "field.h"
@@ -46,6 +49,15 @@ struct spdz_ctx {
   spdz::u64 *d_sigma = nullptr; // [n][L]
   spdz::u64 *h_sigma = nullptr; // pinned host copy of d_sigma
   int grid_mult = 0;            // blocks per CU for streaming kernels (0 = from occupancy)
+  // kernel timing (spdz_timing_enable): HIP events around each main kernel
+  bool timing = false;
+  struct Pending {
+    const char *name;
+    hipEvent_t e0, e1;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> event_pool;
+  std::map<std::string, std::pair<double, int64_t>> kstats;
 };
 
 namespace spdz {
@@ -74,6 +86,35 @@ spdz_status visit(const spdz_ctx *c, Fn &&fn) {
 
 inline spdz_status hip_status(hipError_t e) { return e == hipSuccess ? SPDZ_OK : SPDZ_E_HIP; }
 
+// Records HIP events on the context stream around the kernel launched in its
+// scope when timing is enabled.
+struct KTimer {
+  spdz_ctx *c;
+  const char *name;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipEvent_t take() {
+    if (!c->event_pool.empty()) {
+      hipEvent_t e = c->event_pool.back();
+      c->event_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  KTimer(spdz_ctx *ctx, const char *nm) : c(ctx), name(nm) {
+    if (!c->timing) return;
+    e0 = take();
+    e1 = take();
+    if (e0) (void)hipEventRecord(e0, c->stream);
+  }
+  ~KTimer() {
+    if (!c->timing || !e0 || !e1) return;
+    (void)hipEventRecord(e1, c->stream);
+    c->pending.push_back({name, e0, e1});
+  }
+};
+
 // launchers (elementwise.hip)
 spdz_status launch_open(spdz_ctx *c, const spdz_shares *x, u64 *out_pub);
 spdz_status launch_beaver(spdz_ctx *c, const spdz_shares *x, const spdz_shares *y, const spdz_triple *t,
@@ -87,5 +128,6 @@ spdz_status launch_maccheck_finalize(spdz_ctx *c);
 spdz_status launch_deal_secret(spdz_ctx *c, u64 seed, u64 array_id, const u64 *values, spdz_shares *out,
                                u64 *values_out);
 spdz_status launch_deal_triple(spdz_ctx *c, u64 seed, u64 array_id, spdz_triple *t);
+spdz_status launch_copy(u64 *dst, const u64 *src, int64_t words, hipStream_t stream);
 
 }  // namespace spdz

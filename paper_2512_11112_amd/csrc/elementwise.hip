@@ -69,6 +69,56 @@ __device__ __forceinline__ void block_add_to_slot(typename F::E (&v)[K], u64 *sl
 }
 
 // --------------------------------------------------------------------------
+// public coefficients: the product is specialised per launch when the
+// coefficient is 0, 1, below 2^32, or p minus a value below 2^32 (the kind is
+// uniform across the grid, so the switch does not diverge)
+// --------------------------------------------------------------------------
+enum CoefKind : int { CK_ZERO = 0, CK_ONE = 1, CK_SMALL = 2, CK_NEGSMALL = 3, CK_GENERAL = 4 };
+
+template <class F>
+struct Coef {
+  typename F::E c;
+  u32 m;
+  int kind;
+};
+
+template <class F>
+Coef<F> classify(typename F::E c) {
+  Coef<F> k{c, 0, CK_GENERAL};
+  u64 w[F::L], nw[F::L];
+  F::to_words(c, w);
+  F::to_words(F::neg(c), nw);
+  bool small = w[0] < (1ull << 32), nsmall = nw[0] < (1ull << 32);
+  for (int l = 1; l < F::L; l++) {
+    small = small && w[l] == 0;
+    nsmall = nsmall && nw[l] == 0;
+  }
+  if (F::is_zero(c)) {
+    k.kind = CK_ZERO;
+  } else if (small && w[0] == 1) {
+    k.kind = CK_ONE;
+  } else if (small) {
+    k.kind = CK_SMALL;
+    k.m = (u32)w[0];
+  } else if (nsmall) {
+    k.kind = CK_NEGSMALL;
+    k.m = (u32)nw[0];
+  }
+  return k;
+}
+
+template <class F>
+__device__ __forceinline__ typename F::E cmul(const Coef<F> &k, typename F::E a) {
+  switch (k.kind) {
+    case CK_ZERO: return F::zero();
+    case CK_ONE: return a;
+    case CK_SMALL: return F::mul_small(a, k.m);
+    case CK_NEGSMALL: return F::neg(F::mul_small(a, k.m));
+    default: return F::mul(k.c, a);
+  }
+}
+
+// --------------------------------------------------------------------------
 // open
 // --------------------------------------------------------------------------
 template <class F, int N>
@@ -118,7 +168,9 @@ struct BeaverArgs {
   int64_t j0;  // log index of d_0; e_0 is at j0 + W, w_0 at j0 + 2 W
   u64 *acc;
   // fused part
-  typename F::E lin[4];
+  Coef<F> lin[3];
+  typename F::E lin3;       // public constant of w (added by party 0)
+  typename F::E alin3[N];   // alpha_i * lin3
   SV w;
   u64 *w_pub;
   u64 *red;
@@ -134,103 +186,87 @@ __global__ __launch_bounds__(BLOCK) void k_beaver(const BeaverArgs<F, N> A) {
   E rs[FUSED ? 2 * N : 1];  // ReduceAdd partials of z: values then MACs
 #pragma unroll
   for (int k = 0; k < (FUSED ? 2 * N : 1); k++) rs[k] = F::zero();
+  const bool do_w = FUSED && A.w.val != nullptr;
+  const bool open_w = do_w && A.w_pub != nullptr;
 
   for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < A.W; e += (int64_t)gridDim.x * BLOCK) {
+    // phase A: value shares -> opened d, e (every input word is loaded once)
     E xv[N], yv[N], av[N], bv[N];
-    E gd[N], ge[N];  // MAC shares of d and e
-    E xm[N], ym[N];  // kept for the fused linear op
-    E d = F::zero(), ee = F::zero();
 #pragma unroll
     for (int i = 0; i < N; i++) {
       xv[i] = F::load(A.x.val + i * A.x.ps, A.x.ls, e);
       av[i] = F::load(A.a.val + i * A.a.ps, A.a.ls, e);
       yv[i] = F::load(A.y.val + i * A.y.ps, A.y.ls, e);
       bv[i] = F::load(A.b.val + i * A.b.ps, A.b.ls, e);
-      xm[i] = F::load(A.x.mac + i * A.x.ps, A.x.ls, e);
-      ym[i] = F::load(A.y.mac + i * A.y.ps, A.y.ls, e);
     }
+    E d = F::zero(), ee = F::zero();
 #pragma unroll
     for (int i = 0; i < N; i++) {
       d = F::add(d, F::sub(xv[i], av[i]));
       ee = F::add(ee, F::sub(yv[i], bv[i]));
-      gd[i] = F::sub(xm[i], F::load(A.a.mac + i * A.a.ps, A.a.ls, e));
-      ge[i] = F::sub(ym[i], F::load(A.b.mac + i * A.b.ps, A.b.ls, e));
+    }
+    const E de = F::mul(d, ee);
+    // coefficients of the MAC check: d at log index j0 + e, e at j0 + W + e, w at j0 + 2W + e
+    const E rd = uniform_elem<F>(A.coef_state, (u64)(A.j0 + e));
+    const E re = uniform_elem<F>(A.coef_state, (u64)(A.j0 + A.W + e));
+    E rw = F::zero();
+    if (open_w) rw = uniform_elem<F>(A.coef_state, (u64)(A.j0 + 2 * A.W + e));
+    E wsum = F::zero();
+
+    // phase B: per party, MAC shares and c; recombine, linear op, MAC-check terms
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+      const E xm = F::load(A.x.mac + i * A.x.ps, A.x.ls, e);
+      const E ym = F::load(A.y.mac + i * A.y.ps, A.y.ls, e);
+      const E am = F::load(A.a.mac + i * A.a.ps, A.a.ls, e);
+      const E bm = F::load(A.b.mac + i * A.b.ps, A.b.ls, e);
+      const E cv = F::load(A.c.val + i * A.c.ps, A.c.ls, e);
+      const E cm = F::load(A.c.mac + i * A.c.ps, A.c.ls, e);
+      Wd t = F::wzero();
+      F::wadd(t, cv);
+      F::wmac(t, d, bv[i]);
+      F::wmac(t, ee, av[i]);
+      if (i == 0) F::wadd(t, de);
+      const E zv = F::wreduce(t);
+      t = F::wzero();
+      F::wadd(t, cm);
+      F::wmac(t, d, bm);
+      F::wmac(t, ee, am);
+      F::wmac(t, A.alpha[i], de);
+      const E zm = F::wreduce(t);
+      F::store(A.z.val + i * A.z.ps, A.z.ls, e, zv);
+      F::store(A.z.mac + i * A.z.ps, A.z.ls, e, zm);
+      Wd g = F::wzero();  // r_d gamma_i(d) + r_e gamma_i(e) [+ r_w gamma_i(w)]
+      F::wmac(g, rd, F::sub(xm, am));
+      F::wmac(g, re, F::sub(ym, bm));
+      if constexpr (FUSED) {
+        if (do_w) {
+          E wv = F::add(F::add(cmul<F>(A.lin[0], zv), cmul<F>(A.lin[1], xv[i])), cmul<F>(A.lin[2], yv[i]));
+          if (i == 0) wv = F::add(wv, A.lin3);
+          const E wm =
+              F::add(F::add(F::add(cmul<F>(A.lin[0], zm), cmul<F>(A.lin[1], xm)), cmul<F>(A.lin[2], ym)), A.alin3[i]);
+          F::store(A.w.val + i * A.w.ps, A.w.ls, e, wv);
+          F::store(A.w.mac + i * A.w.ps, A.w.ls, e, wm);
+          wsum = F::add(wsum, wv);
+          if (open_w) F::wmac(g, rw, wm);
+        }
+        if (A.red) {
+          rs[i] = F::add(rs[i], zv);
+          rs[N + i] = F::add(rs[N + i], zm);
+        }
+      }
+      mc[1 + i] = F::add(mc[1 + i], F::wreduce(g));
     }
     if (A.d_pub) F::store(A.d_pub, A.W, e, d);
     if (A.e_pub) F::store(A.e_pub, A.W, e, ee);
-    const E de = F::mul(d, ee);
-
-    E zv[N], zm[N];
-#pragma unroll
-    for (int i = 0; i < N; i++) {
-      Wd wv = F::wzero(), wm = F::wzero();
-      F::wadd(wv, F::load(A.c.val + i * A.c.ps, A.c.ls, e));
-      F::wmac(wv, d, F::load(A.b.val + i * A.b.ps, A.b.ls, e) /* reload: keeps register use down */);
-      F::wmac(wv, ee, av[i]);
-      if (i == 0) F::wadd(wv, de);
-      F::wadd(wm, F::load(A.c.mac + i * A.c.ps, A.c.ls, e));
-      F::wmac(wm, d, F::load(A.b.mac + i * A.b.ps, A.b.ls, e));
-      F::wmac(wm, ee, F::load(A.a.mac + i * A.a.ps, A.a.ls, e));
-      F::wmac(wm, A.alpha[i], de);
-      zv[i] = F::wreduce(wv);
-      zm[i] = F::wreduce(wm);
-      F::store(A.z.val + i * A.z.ps, A.z.ls, e, zv[i]);
-      F::store(A.z.mac + i * A.z.ps, A.z.ls, e, zm[i]);
+    Wd ga = F::wzero();
+    F::wmac(ga, rd, d);
+    F::wmac(ga, re, ee);
+    if (open_w) {
+      F::store(A.w_pub, A.W, e, wsum);
+      F::wmac(ga, rw, wsum);
     }
-
-    // MAC-check partials for d (log index j0 + e) and e (j0 + W + e)
-    const E rd = uniform_elem<F>(A.coef_state, (u64)(A.j0 + e));
-    const E re = uniform_elem<F>(A.coef_state, (u64)(A.j0 + A.W + e));
-    {
-      Wd t = F::wzero();
-      F::wmac(t, rd, d);
-      F::wmac(t, re, ee);
-      mc[0] = F::add(mc[0], F::wreduce(t));
-    }
-#pragma unroll
-    for (int i = 0; i < N; i++) {
-      Wd t = F::wzero();
-      F::wmac(t, rd, gd[i]);
-      F::wmac(t, re, ge[i]);
-      mc[1 + i] = F::add(mc[1 + i], F::wreduce(t));
-    }
-
-    if constexpr (FUSED) {
-      if (A.w.val) {
-        E wsum = F::zero();
-        E wm[N];
-#pragma unroll
-        for (int i = 0; i < N; i++) {
-          Wd tv = F::wzero(), tm = F::wzero();
-          F::wmac(tv, A.lin[0], zv[i]);
-          F::wmac(tv, A.lin[1], xv[i]);
-          F::wmac(tv, A.lin[2], yv[i]);
-          E wv = F::wreduce(tv);
-          if (i == 0) wv = F::add(wv, A.lin[3]);
-          F::wmac(tm, A.lin[0], zm[i]);
-          F::wmac(tm, A.lin[1], xm[i]);
-          F::wmac(tm, A.lin[2], ym[i]);
-          wm[i] = F::add(F::wreduce(tm), F::mul(A.alpha[i], A.lin[3]));
-          F::store(A.w.val + i * A.w.ps, A.w.ls, e, wv);
-          F::store(A.w.mac + i * A.w.ps, A.w.ls, e, wm[i]);
-          wsum = F::add(wsum, wv);
-        }
-        if (A.w_pub) {
-          F::store(A.w_pub, A.W, e, wsum);
-          const E rw = uniform_elem<F>(A.coef_state, (u64)(A.j0 + 2 * A.W + e));
-          mc[0] = F::add(mc[0], F::mul(rw, wsum));
-#pragma unroll
-          for (int i = 0; i < N; i++) mc[1 + i] = F::add(mc[1 + i], F::mul(rw, wm[i]));
-        }
-      }
-      if (A.red) {
-#pragma unroll
-        for (int i = 0; i < N; i++) {
-          rs[i] = F::add(rs[i], zv[i]);
-          rs[N + i] = F::add(rs[N + i], zm[i]);
-        }
-      }
-    }
+    mc[0] = F::add(mc[0], F::wreduce(ga));
   }
   block_add_to_slot<F, N + 1>(mc, A.acc + (size_t)blockIdx.x * (N + 1) * F::L);
   if constexpr (FUSED) {
@@ -246,10 +282,10 @@ constexpr int MAX_TERMS = 8;
 template <class F, int N>
 struct LinArgs {
   SV t[MAX_TERMS];
-  typename F::E coef[MAX_TERMS];
+  Coef<F> coef[MAX_TERMS];
   int nt;
   typename F::E c0;
-  typename F::E alpha[N];
+  typename F::E ac0[N];  // alpha_i * c0
   SV out;
   int64_t W;
 };
@@ -262,15 +298,15 @@ __global__ __launch_bounds__(BLOCK) void k_linear(const LinArgs<F, N> A) {
 #pragma unroll
     for (int i = 0; i < N; i++) {
       ov[i] = i == 0 ? A.c0 : F::zero();
-      om[i] = F::mul(A.alpha[i], A.c0);
+      om[i] = A.ac0[i];
     }
     for (int k = 0; k < A.nt; k++) {
       const SV s = A.t[k];
-      const E c = A.coef[k];
+      const Coef<F> c = A.coef[k];
 #pragma unroll
       for (int i = 0; i < N; i++) {
-        ov[i] = F::add(ov[i], F::mul(c, F::load_cached(s.val + i * s.ps, s.ls, e)));
-        om[i] = F::add(om[i], F::mul(c, F::load_cached(s.mac + i * s.ps, s.ls, e)));
+        ov[i] = F::add(ov[i], cmul<F>(c, F::load_cached(s.val + i * s.ps, s.ls, e)));
+        om[i] = F::add(om[i], cmul<F>(c, F::load_cached(s.mac + i * s.ps, s.ls, e)));
       }
     }
 #pragma unroll
@@ -433,6 +469,19 @@ __global__ __launch_bounds__(BLOCK) void k_deal_triple(const DealTripleArgs<F, N
   }
 }
 
+// --------------------------------------------------------------------------
+// plain copy (bandwidth reference): 16-byte vector loads and stores
+// --------------------------------------------------------------------------
+typedef u64 u64x2 __attribute__((ext_vector_type(2)));
+__global__ __launch_bounds__(BLOCK) void k_copy(const u64 *__restrict__ src, u64 *__restrict__ dst, int64_t words) {
+  const int64_t pairs = words / 2;
+  const u64x2 *s2 = reinterpret_cast<const u64x2 *>(src);
+  u64x2 *d2 = reinterpret_cast<u64x2 *>(dst);
+  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < pairs; i += (int64_t)gridDim.x * BLOCK)
+    __builtin_nontemporal_store(__builtin_nontemporal_load(s2 + i), d2 + i);
+  if ((words & 1) && blockIdx.x == 0 && threadIdx.x == 0) dst[words - 1] = src[words - 1];
+}
+
 // ==========================================================================
 // host launchers
 // ==========================================================================
@@ -502,6 +551,18 @@ typename F::E alpha_sum(const spdz_ctx *c) {
 
 }  // namespace
 
+spdz_status launch_copy(u64 *dst, const u64 *src, int64_t words, hipStream_t stream) {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return SPDZ_E_HIP;
+  int64_t g = (int64_t)cus * occupancy_blocks((const void *)k_copy);
+  int64_t need = (words / 2 + BLOCK - 1) / BLOCK;
+  if (g > need) g = need;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)g), dim3(BLOCK), 0, stream, src, dst, words);
+  return hip_status(hipGetLastError());
+}
+
 spdz_status launch_open(spdz_ctx *c, const spdz_shares *x, u64 *out_pub) {
   return visit(c, [&](auto f, auto nn) -> spdz_status {
     using F = decltype(f);
@@ -515,6 +576,7 @@ spdz_status launch_open(spdz_ctx *c, const spdz_shares *x, u64 *out_pub) {
     a.acc = c->d_acc;
     const void *k = (const void *)k_open<F, N>;
     int g = grid_for(c, k, a.W);
+    KTimer tm(c, "open");
     hipLaunchKernelGGL((k_open<F, N>), dim3(g), dim3(BLOCK), 0, c->stream, a);
     spdz_status s = hip_status(hipGetLastError());
     if (s == SPDZ_OK) {
@@ -546,7 +608,9 @@ spdz_status launch_beaver(spdz_ctx *c, const spdz_shares *x, const spdz_shares *
     A.coef_state = coef_state(c);
     A.j0 = c->log_count;
     A.acc = c->d_acc;
-    for (int k = 0; k < 4; k++) A.lin[k] = lin ? F::from_words(lin + k * F::L) : F::zero();
+    for (int k = 0; k < 3; k++) A.lin[k] = classify<F>(lin ? F::from_words(lin + k * F::L) : F::zero());
+    A.lin3 = lin ? F::from_words(lin + 3 * F::L) : F::zero();
+    for (int i = 0; i < N; i++) A.alin3[i] = F::mul(A.alpha[i], A.lin3);
     A.w = w ? sv_of(w) : SV{nullptr, nullptr, 0, 0};
     A.w_pub = w ? w_pub : nullptr;
     A.red = s ? c->d_red : nullptr;
@@ -554,10 +618,12 @@ spdz_status launch_beaver(spdz_ctx *c, const spdz_shares *x, const spdz_shares *
     if (fused) {
       const void *k = (const void *)k_beaver<F, N, true>;
       g = grid_for(c, k, A.W);
+      KTimer tm(c, "beaver_fused");
       hipLaunchKernelGGL((k_beaver<F, N, true>), dim3(g), dim3(BLOCK), 0, c->stream, A);
     } else {
       const void *k = (const void *)k_beaver<F, N, false>;
       g = grid_for(c, k, A.W);
+      KTimer tm(c, "beaver");
       hipLaunchKernelGGL((k_beaver<F, N, false>), dim3(g), dim3(BLOCK), 0, c->stream, A);
     }
     spdz_status st = hip_status(hipGetLastError());
@@ -581,14 +647,17 @@ spdz_status launch_linear(spdz_ctx *c, int nt, const spdz_shares *terms, const u
     LinArgs<F, N> A;
     for (int k = 0; k < MAX_TERMS; k++) {
       A.t[k] = k < nt ? sv_of(&terms[k]) : SV{nullptr, nullptr, 0, 0};
-      A.coef[k] = k < nt ? F::from_words(coeffs + k * F::L) : F::zero();
+      A.coef[k] = classify<F>(k < nt ? F::from_words(coeffs + k * F::L) : F::zero());
     }
     A.nt = nt;
     A.c0 = c0 ? F::from_words(c0) : F::zero();
-    alpha_of<F, N>(c, A.alpha);
+    typename F::E alpha[N];
+    alpha_of<F, N>(c, alpha);
+    for (int i = 0; i < N; i++) A.ac0[i] = F::mul(alpha[i], A.c0);
     A.out = sv_of(out);
     A.W = out->len;
     int g = grid_for(c, (const void *)k_linear<F, N>, A.W);
+    KTimer tm(c, "linear");
     hipLaunchKernelGGL((k_linear<F, N>), dim3(g), dim3(BLOCK), 0, c->stream, A);
     return hip_status(hipGetLastError());
   });
@@ -599,6 +668,7 @@ spdz_status launch_reduce(spdz_ctx *c, const spdz_shares *x, spdz_shares *out) {
     using F = decltype(f);
     constexpr int N = decltype(nn)::value;
     int g = grid_for(c, (const void *)k_reduce<F, N>, x->len);
+    KTimer tm(c, "reduce");
     hipLaunchKernelGGL((k_reduce<F, N>), dim3(g), dim3(BLOCK), 0, c->stream, sv_of(x), x->len, c->d_red);
     spdz_status st = hip_status(hipGetLastError());
     if (st != SPDZ_OK) return st;
@@ -616,6 +686,7 @@ spdz_status launch_maccheck_finalize(spdz_ctx *c) {
     A.nslots = c->slots;
     alpha_of<F, N>(c, A.alpha);
     A.sigma = c->d_sigma;
+    KTimer tm(c, "mac_finalize");
     hipLaunchKernelGGL((k_mac_finalize<F, N>), dim3(1), dim3(BLOCK), 0, c->stream, A);
     return hip_status(hipGetLastError());
   });

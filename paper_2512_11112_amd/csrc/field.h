@@ -3,12 +3,20 @@
 // F61:  p = 2^61 - 1,  one 64-bit limb.
 // F127: p = 2^127 - 1, two 64-bit limbs (lo, hi).
 //
-// Both reduce with the Mersenne identity 2^k = 1 (mod 2^k - 1): a wide value
-// v is congruent to (v mod 2^k) + (v >> k).  64 x 64 -> 128-bit products come
-// from unsigned __int128, which gfx950 lowers to four v_mad_u64_u32.
-// Every function returns a canonical residue in [0, p) given canonical input;
-// the "wide" accumulators hold exact, unreduced sums of a bounded number of
-// products and are reduced once.
+// In registers a residue is kept "almost canonical": any value in [0, p],
+// where p itself stands for 0.  Because p = 2^k - 1 is all ones, this makes
+// every operation a few folds with no comparisons:
+//   fold(v)  = (v mod 2^k) + (v >> k)           (2^k = 1 mod p)
+//   sub(a,b) = add(a, b xor p)                  (p - b = b xor p for 0 <= b <= p)
+//   add      : a + b <= 2p, one fold gives a value <= p
+//   mul      : the double-width product, two folds
+// `canon` maps p to 0 (x + ((x + 1) >> k) mod 2^k) and is applied only to
+// values that leave the registers (stores, accumulator slots), so memory
+// always holds canonical residues in [0, p).
+//
+// 64 x 64 -> 128-bit products come from unsigned __int128, which gfx950
+// lowers to four v_mad_u64_u32.  "Wide" accumulators hold exact, unreduced
+// sums of a bounded number of products and are folded once.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -19,6 +27,8 @@ typedef uint64_t u64;
 typedef uint32_t u32;
 typedef unsigned __int128 u128;
 
+#define SPDZ_HD __host__ __device__ __forceinline__
+
 struct F61 {
   static constexpr int L = 1;
   static constexpr int BITS = 61;
@@ -26,36 +36,34 @@ struct F61 {
   struct E {
     u64 v;
   };
-  // exact sum of up to 32 products of residues (each < 2^122)
+  // exact sum of up to 32 products of values <= p (each < 2^122) plus residues
   struct Wide {
     u128 v;
   };
 
-  __host__ __device__ __forceinline__ static E zero() { return {0}; }
-  __device__ __forceinline__ static bool is_zero(E a) { return a.v == 0; }
-  __device__ __forceinline__ static bool eq(E a, E b) { return a.v == b.v; }
-  __device__ __forceinline__ static E add(E a, E b) {
-    u64 s = a.v + b.v;
-    return {s >= P ? s - P : s};
+  SPDZ_HD static E zero() { return {0}; }
+  SPDZ_HD static u64 fold(u64 s) { return (s & P) + (s >> 61); }
+  SPDZ_HD static E add(E a, E b) { return {fold(a.v + b.v)}; }  // a + b <= 2p -> <= p
+  SPDZ_HD static E neg(E a) { return {a.v ^ P}; }
+  SPDZ_HD static E sub(E a, E b) { return add(a, neg(b)); }
+  SPDZ_HD static E canon(E a) { return {(a.v + ((a.v + 1) >> 61)) & P}; }
+  SPDZ_HD static bool is_zero(E a) { return canon(a).v == 0; }
+  // any x < 2^128 -> <= p
+  SPDZ_HD static E reduce(u128 x) {
+    u128 t = (x & P) + (x >> 61);          // < 2^68
+    u64 s = (u64)(t & P) + (u64)(t >> 61);  // < 2^61 + 2^7 <= 2p
+    return {fold(s)};
   }
-  __device__ __forceinline__ static E sub(E a, E b) {
-    u64 s = a.v - b.v;
-    return {a.v >= b.v ? s : s + P};
+  SPDZ_HD static E mul(E a, E b) {
+    u128 pr = (u128)a.v * b.v;                   // <= p^2 < 2^122
+    u64 s = ((u64)pr & P) + (u64)(pr >> 61);     // <= 2p
+    return {fold(s)};
   }
-  // x < 2^128 -> canonical
-  __device__ __forceinline__ static E reduce(u128 x) {
-    u64 lo = (u64)x & P;
-    u128 t = x >> 61;                       // < 2^67
-    u64 t2 = ((u64)t & P) + (u64)(t >> 61);  // < 2^61 + 2^6
-    u64 s = lo + t2;                         // < 2^62 + 2^6
-    s = (s & P) + (s >> 61);                 // <= P + 1
-    return {s >= P ? s - P : s};
-  }
-  // product of two residues (< 2^122): one fold suffices
-  __device__ __forceinline__ static E mul(E a, E b) {
-    u128 pr = (u128)a.v * b.v;
-    u64 s = ((u64)pr & P) + (u64)(pr >> 61);  // (pr >> 61) < 2^61
-    return {s >= P ? s - P : s};
+  // product with a multiplier m < 2^32
+  SPDZ_HD static E mul_small(E a, u32 m) {
+    u128 pr = (u128)a.v * m;                     // < 2^93
+    u64 s = ((u64)pr & P) + (u64)(pr >> 61);     // < 2^61 + 2^32 <= 2p
+    return {fold(s)};
   }
   __device__ __forceinline__ static Wide wzero() { return {0}; }
   __device__ __forceinline__ static void wmac(Wide &w, E a, E b) { w.v += (u128)a.v * b.v; }
@@ -65,16 +73,14 @@ struct F61 {
   __device__ __forceinline__ static E load(const u64 *base, int64_t /*limb_stride*/, int64_t idx) {
     return {__builtin_nontemporal_load(base + idx)};
   }
-  __device__ __forceinline__ static E load_cached(const u64 *base, int64_t, int64_t idx) {
-    return {base[idx]};
-  }
+  __device__ __forceinline__ static E load_cached(const u64 *base, int64_t, int64_t idx) { return {base[idx]}; }
+  // stores the canonical residue
   __device__ __forceinline__ static void store(u64 *base, int64_t /*limb_stride*/, int64_t idx, E x) {
-    __builtin_nontemporal_store(x.v, base + idx);
+    __builtin_nontemporal_store(canon(x).v, base + idx);
   }
-  __host__ __device__ static E from_words(const u64 *w) { return {w[0]}; }
-  __host__ __device__ static void to_words(E x, u64 *w) { w[0] = x.v; }
+  SPDZ_HD static E from_words(const u64 *w) { return {w[0]}; }
+  SPDZ_HD static void to_words(E x, u64 *w) { w[0] = canon(x).v; }
 
-  // 32-bit lanes for cross-lane shuffles
   static constexpr int WORDS32 = 2;
   __device__ __forceinline__ static u32 word32(E a, int k) { return (u32)(a.v >> (32 * k)); }
   __device__ __forceinline__ static E from32(const u32 *w) { return {(u64)w[0] | ((u64)w[1] << 32)}; }
@@ -86,57 +92,64 @@ struct F127 {
   struct E {
     u64 lo, hi;
   };
-  // exact sum of up to 3 products (each < 2^254) plus a few residues, as 256 bits
+  // exact 256-bit sum of up to 3 products of values <= p (each < 2^254) plus a few residues
   struct Wide {
     u128 lo, hi;
   };
-  static constexpr u64 PHI = (1ull << 63) - 1;  // high limb of p; low limb is all ones
-  __device__ __forceinline__ static u128 P128() { return ((u128)PHI << 64) | ~0ull; }
-  __device__ __forceinline__ static u128 v(E a) { return ((u128)a.hi << 64) | a.lo; }
-  __device__ __forceinline__ static E mk(u128 x) { return {(u64)x, (u64)(x >> 64)}; }
+  static constexpr u64 PHI = (1ull << 63) - 1;  // high limb of p; the low limb is all ones
+  SPDZ_HD static u128 P128() { return ((u128)PHI << 64) | ~0ull; }
+  SPDZ_HD static u128 v(E a) { return ((u128)a.hi << 64) | a.lo; }
+  SPDZ_HD static E mk(u128 x) { return {(u64)x, (u64)(x >> 64)}; }
+  SPDZ_HD static u128 fold(u128 s) { return (s & P128()) + (s >> 127); }
 
-  __host__ __device__ __forceinline__ static E zero() { return {0, 0}; }
-  __device__ __forceinline__ static bool is_zero(E a) { return (a.lo | a.hi) == 0; }
-  __device__ __forceinline__ static bool eq(E a, E b) { return a.lo == b.lo && a.hi == b.hi; }
-  __device__ __forceinline__ static E add(E a, E b) {
-    u128 s = v(a) + v(b);  // < 2^128
-    u128 p = P128();
-    return mk(s >= p ? s - p : s);
+  SPDZ_HD static E zero() { return {0, 0}; }
+  SPDZ_HD static E add(E a, E b) { return mk(fold(v(a) + v(b))); }  // a + b <= 2p < 2^128
+  SPDZ_HD static E neg(E a) { return {~a.lo, a.hi ^ PHI}; }
+  SPDZ_HD static E sub(E a, E b) { return add(a, neg(b)); }
+  SPDZ_HD static E canon(E a) {
+    u128 x = v(a);
+    return mk((x + ((x + 1) >> 127)) & P128());
   }
-  __device__ __forceinline__ static E sub(E a, E b) {
-    u128 x = v(a), y = v(b);
-    u128 s = x - y;
-    return mk(x >= y ? s : s + P128());
+  SPDZ_HD static bool is_zero(E a) {
+    E c = canon(a);
+    return (c.lo | c.hi) == 0;
   }
-  // any x < 2^128 -> canonical
-  __device__ __forceinline__ static E reduce(u128 x) {
-    u128 p = P128();
-    u128 s = (x & p) + (x >> 127);  // <= p + 1
-    return mk(s >= p ? s - p : s);
+  // any x < 2^128 -> <= p
+  SPDZ_HD static u128 reduce128(u128 x) {
+    u128 f = fold(x);  // <= 2^127
+    return fold(f);    // <= p
   }
-  // 256-bit value hi * 2^128 + lo (any) -> canonical; 2^128 = 2 (mod p)
-  __device__ __forceinline__ static E reduce256(u128 lo, u128 hi) {
-    E h = reduce(hi);
-    E l = reduce(lo);
-    return add(add(h, h), l);
+  // 256-bit value hi 2^128 + lo -> <= p, using 2^128 = 2 (mod p)
+  SPDZ_HD static E reduce256(u128 lo, u128 hi) {
+    u128 h = reduce128(hi);
+    u128 l = reduce128(lo);
+    u128 h2 = fold(h + h);  // <= p
+    return mk(fold(h2 + l));
   }
-  __device__ __forceinline__ static void mul_wide(E a, E b, u128 &lo, u128 &hi) {
+  SPDZ_HD static void mul_wide(E a, E b, u128 &lo, u128 &hi) {
     u128 p00 = (u128)a.lo * b.lo;
     u128 p01 = (u128)a.lo * b.hi;
     u128 p10 = (u128)a.hi * b.lo;
     u128 p11 = (u128)a.hi * b.hi;
     u128 mid = (p00 >> 64) + (u64)p01 + (u64)p10;  // < 3 * 2^64
     lo = ((u128)(u64)mid << 64) | (u64)p00;
-    hi = (mid >> 64) + (p01 >> 64) + (p10 >> 64) + p11;  // < 2^126 for a, b < 2^127
+    hi = (mid >> 64) + (p01 >> 64) + (p10 >> 64) + p11;  // < 2^126 for a, b <= p
   }
-  __device__ __forceinline__ static E mul(E a, E b) {
+  SPDZ_HD static E mul(E a, E b) {
     u128 lo, hi;
     mul_wide(a, b, lo, hi);
-    // v = hi 2^128 + lo = (2 hi + (lo >> 127)) 2^127 + (lo mod 2^127), 2 hi + 1 <= 2^127
-    u128 p = P128();
-    u128 s = (lo & p) + ((hi << 1) | (lo >> 127));  // < 2^128
-    s = (s & p) + (s >> 127);                      // <= p + 1
-    return mk(s >= p ? s - p : s);
+    // v = (2 hi + (lo >> 127)) 2^127 + (lo mod 2^127); 2 hi + 1 <= p
+    u128 s = (lo & P128()) + ((hi << 1) | (lo >> 127));  // <= 2p
+    return mk(fold(s));
+  }
+  // product with a multiplier m < 2^32: a m < 2^159
+  SPDZ_HD static E mul_small(E a, u32 m) {
+    u128 t1 = (u128)a.lo * m;  // < 2^96
+    u128 t2 = (u128)a.hi * m;  // < 2^95
+    u128 lo = t1 + ((u128)(u64)t2 << 64);
+    u128 hi = (t2 >> 64) + (lo < t1);                    // < 2^32
+    u128 s = (lo & P128()) + ((hi << 1) | (lo >> 127));  // <= p + 2^33 <= 2p
+    return mk(fold(s));
   }
   __device__ __forceinline__ static Wide wzero() { return {0, 0}; }
   __device__ __forceinline__ static void wmac(Wide &w, E a, E b) {
@@ -160,20 +173,21 @@ struct F127 {
   __device__ __forceinline__ static E load_cached(const u64 *base, int64_t limb_stride, int64_t idx) {
     return {base[idx], base[limb_stride + idx]};
   }
+  // stores the canonical residue
   __device__ __forceinline__ static void store(u64 *base, int64_t limb_stride, int64_t idx, E x) {
-    __builtin_nontemporal_store(x.lo, base + idx);
-    __builtin_nontemporal_store(x.hi, base + limb_stride + idx);
+    E c = canon(x);
+    __builtin_nontemporal_store(c.lo, base + idx);
+    __builtin_nontemporal_store(c.hi, base + limb_stride + idx);
   }
-  __host__ __device__ static E from_words(const u64 *w) { return {w[0], w[1]}; }
-  __host__ __device__ static void to_words(E x, u64 *w) {
-    w[0] = x.lo;
-    w[1] = x.hi;
+  SPDZ_HD static E from_words(const u64 *w) { return {w[0], w[1]}; }
+  SPDZ_HD static void to_words(E x, u64 *w) {
+    E c = canon(x);
+    w[0] = c.lo;
+    w[1] = c.hi;
   }
 
   static constexpr int WORDS32 = 4;
-  __device__ __forceinline__ static u32 word32(E a, int k) {
-    return (u32)((k < 2 ? a.lo : a.hi) >> (32 * (k & 1)));
-  }
+  __device__ __forceinline__ static u32 word32(E a, int k) { return (u32)((k < 2 ? a.lo : a.hi) >> (32 * (k & 1))); }
   __device__ __forceinline__ static E from32(const u32 *w) {
     return {(u64)w[0] | ((u64)w[1] << 32), (u64)w[2] | ((u64)w[3] << 32)};
   }
@@ -189,12 +203,12 @@ struct F127 {
 // --------------------------------------------------------------------------
 constexpr u64 GOLDEN = 0x9E3779B97F4A7C15ull;
 
-__host__ __device__ __forceinline__ u64 mix64(u64 z) {
+SPDZ_HD u64 mix64(u64 z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
   return z ^ (z >> 31);
 }
-__host__ __device__ __forceinline__ u64 sm_out(u64 state, u64 i) { return mix64(state + (i + 1) * GOLDEN); }
+SPDZ_HD u64 sm_out(u64 state, u64 i) { return mix64(state + (i + 1) * GOLDEN); }
 
 template <class F>
 __device__ __forceinline__ typename F::E uniform_elem(u64 state, u64 e);

@@ -68,6 +68,10 @@ def lib() -> ctypes.CDLL:
             "spdz_deal_secret": (i32, [vp, ctypes.c_uint64, ctypes.c_uint64, vp,
                                        ctypes.POINTER(Shares), vp]),
             "spdz_deal_triple": (i32, [vp, ctypes.c_uint64, ctypes.c_uint64, ctypes.POINTER(Triple)]),
+            "spdz_timing_enable": (i32, [vp, i32]),
+            "spdz_timing_get": (i32, [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(i64)]),
+            "spdz_copy_probe": (i32, [vp, vp, i64, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -136,6 +140,14 @@ class TripleTensor:
 
     def desc(self) -> Triple:
         return Triple(self.a.desc(), self.b.desc(), self.c.desc())
+
+
+def spdz_copy_probe(dst: torch.Tensor, src: torch.Tensor, stream=None):
+    """Plain device copy of src into dst (int64 tensors of equal size)."""
+    assert dst.numel() == src.numel() and dst.is_contiguous() and src.is_contiguous()
+    st = (stream or torch.cuda.current_stream()).cuda_stream
+    _check(lib().spdz_copy_probe(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+                                 src.numel(), ctypes.c_void_p(st)), "spdz_copy_probe")
 
 
 def deal_alpha(p: int, n: int, seed: int) -> list:
@@ -249,6 +261,18 @@ class Context:
         s = _check(lib().spdz_mac_check(self._h, ctypes.byref(acc), sig), "spdz_mac_check")
         sigma = [sum(int(sig[i * self.L + l]) << (64 * l) for l in range(self.L)) for i in range(self.n)]
         return bool(acc.value) and s == SPDZ_OK, sigma
+
+    # -- measurement ------------------------------------------------------------
+    def spdz_timing_enable(self, enable: bool = True):
+        _check(lib().spdz_timing_enable(self._h, int(enable)), "spdz_timing_enable")
+
+    def spdz_timing_get(self, kernel: str):
+        """(total ms, launches) of a kernel since timing was enabled."""
+        ms = ctypes.c_double(0)
+        cnt = ctypes.c_int64(0)
+        _check(lib().spdz_timing_get(self._h, kernel.encode(), ctypes.byref(ms), ctypes.byref(cnt)),
+               "spdz_timing_get")
+        return ms.value, cnt.value
 
     # -- fake preprocessing ---------------------------------------------------
     def spdz_deal_secret(self, seed: int, array_id: int, out: ShareTensor,

@@ -233,3 +233,50 @@ def test_pipeline_full_size_p127_n3():
     assert not ref["ok"] and not got["ok"]
     assert got["sigma"] == ints_of_sigma(ref["sigma"])
     assert np.array_equal(host(got["wpub"]), ref["wpub"])
+
+
+# --------------------------------------------------------------------------
+# edge values: every input word is one of 0, 1, 2, p-2, p-1 (shares need not
+# be MAC-consistent, so the check rejects; every bit must still agree)
+# --------------------------------------------------------------------------
+def edge_shares(f, n, W, rng):
+    from oracle.fast import Shares, to_limbs
+    p = f.p
+    pool = [0, 1, 2, p - 2, p - 1]
+
+    def arr():
+        out = np.empty((n, f.L, W), dtype=np.uint64)
+        for i in range(n):
+            out[i] = to_limbs([pool[k] for k in rng.integers(0, len(pool), W)], f.L)
+        return out
+    return Shares(arr(), arr())
+
+
+@pytest.mark.parametrize("p,n", [(P61, 2), (P61, 3), (P127, 3), (P127, 2)])
+def test_edge_values_fused(p, n):
+    from oracle.pipelines import Dealt
+    rng = np.random.default_rng(p % 997 + n)
+    W = 20000
+    f = F.Field(p)
+    al = np.ascontiguousarray(F.to_limbs([p - 1, 1] + [2] * (n - 2), f.L).T)
+    D = Dealt(f, n, 0, al, None, edge_shares(f, n, W, rng), None, edge_shares(f, n, W, rng),
+              F.TripleArr(edge_shares(f, n, W, rng), edge_shares(f, n, W, rng), edge_shares(f, n, W, rng)))
+    lin = (p - 1, 3, p - 2, p - 1)
+    ref = pipeline_run(D, check_seed=9, lin=lin)
+    _, got = run_fused(D, 9, lin=lin)
+    check_fused(got, ref)
+    # plain product and a linear op with general coefficients on the same edge inputs
+    ref2 = beaver_run(D, check_seed=9)
+    from paper_2512_11112_amd.spdz import ShareTensor
+    ctx = make_ctx(D, 9)
+    z = ShareTensor.empty(n, f.L, W)
+    ctx.spdz_mul_batch(share_to_dev(D.x), share_to_dev(D.y), triple_to_dev(D.t), z)
+    ok, sigma = ctx.spdz_mac_check()
+    eq_shares(z, ref2["z"], "z")
+    assert ok == ref2["ok"] and sigma == ints_of_sigma(ref2["sigma"])
+    c = [p - 1, (p - 1) // 2 + 5, 2]
+    refl = f.linear(D.alpha, [D.x, D.y, D.t.c], c, p - 2)
+    ctx2 = make_ctx(D, 9)
+    o = ctx2.spdz_linear([share_to_dev(D.x), share_to_dev(D.y), share_to_dev(D.t.c)], c, p - 2)
+    torch.cuda.synchronize()
+    eq_shares(o, refl, "linear")
