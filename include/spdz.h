@@ -149,6 +149,28 @@ spdz_status spdz_mul_fused(spdz_ctx *ctx, const spdz_shares *x, const spdz_share
                            uint64_t *e_pub, const uint64_t *lin, spdz_shares *w,
                            uint64_t *w_pub, spdz_shares *s);
 
+/* Matrix-triple product (Sec. III-D, "MPC-specific optimization": one
+ * matrix triple (A, B, C = A B) per product, D = X - A and E = Y - B opened,
+ * Z = C + D B + A E + D E; here the opened matrices are called E and F):
+ *   E = open(X - A) [M x K], F = open(Y - B) [K x N],
+ *   Z_i    = C_i + E B_i + A_i F + [i = 0] E F
+ *   M(Z)_i = M(C)_i + E M(B)_i + M(A)_i F + alpha_i E F.
+ * Matrices are row-major: party i's matrix is the len = rows * cols words at
+ * val + i * party_stride (and mac + i * party_stride).  X and T->a are M x K,
+ * Y and T->b are K x N, T->c and Z are M x N.  Only p = 2^61 - 1 (L = 1);
+ * other moduli return SPDZ_E_UNSUPPORTED.
+ * E_pub (device [M][K]) and F_pub (device [K][N]) receive the opened matrices
+ * and may be NULL (library scratch is used).  Appends E (row-major) then F to
+ * the log.
+ * variant: 0 = VALU mod-p GEMM (64-bit products, 128-bit accumulation),
+ *          1 = exact int8-digit MFMA GEMM (K <= 8191, else SPDZ_E_SHAPE),
+ *         -1 = library choice (MFMA).
+ * Grows a library-owned workspace (about 24 (M K + K N + M N) bytes for the
+ * MFMA variant) on first use; the call is asynchronous. */
+spdz_status spdz_matmul_triple(spdz_ctx *ctx, int64_t M, int64_t K, int64_t N, const spdz_shares *X,
+                               const spdz_shares *Y, const spdz_triple *T, spdz_shares *Z,
+                               uint64_t *E_pub, uint64_t *F_pub, int variant);
+
 /* MAC check over every value in the log (Sec. II-A, "Security model"; the
  * check is the random-linear-combination check): with public coefficients
  * r_j drawn from check_seed and the check number,
@@ -194,6 +216,12 @@ spdz_status spdz_deal_alpha(const uint64_t *p_limbs, int n_limbs, int n_parties,
  * written to out (out->len elements). */
 spdz_status spdz_deal_secret(spdz_ctx *ctx, uint64_t seed, uint64_t array_id,
                              const uint64_t *values, spdz_shares *out, uint64_t *values_out);
+
+/* Deal a matrix triple: A [M][K] from array_id, B [K][N] from array_id + 1,
+ * C = A B mod p shared with array_id + 2 (p = 2^61 - 1 only; K <= 8191).
+ * Synchronous: allocates and frees a temporary buffer for the public values. */
+spdz_status spdz_deal_matrix_triple(spdz_ctx *ctx, uint64_t seed, uint64_t array_id, int64_t M, int64_t K,
+                                    int64_t N, spdz_triple *out);
 
 /* Deal a Beaver triple with ids array_id (a), +1 (b), +2 (c = a b). */
 spdz_status spdz_deal_triple(spdz_ctx *ctx, uint64_t seed, uint64_t array_id, spdz_triple *out);

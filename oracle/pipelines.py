@@ -70,3 +70,105 @@ def pipeline_run(D: Dealt, check_seed: int, lin=None, epoch: int = 0):
     log.add(spub, s.mac)
     ok, sigma = log.check(D.alpha)
     return dict(z=z, d=d, e=e, w=w, wpub=wpub, s=s, spub=spub, ok=ok, sigma=sigma)
+
+
+# ---------------------------------------------------------------------------
+# matrix triples (single-limb field); matrices are flattened row-major, shares
+# [n][1][rows*cols]
+# ---------------------------------------------------------------------------
+@dataclass
+class DealtMat:
+    f: F.Field
+    n: int
+    seed: int
+    M: int
+    K: int
+    N: int
+    alpha: np.ndarray
+    Xs: np.ndarray   # [1][M K] secret values
+    X: F.Shares
+    Ys: np.ndarray
+    Y: F.Shares
+    T: F.TripleArr
+
+
+def deal_matrices(p: int, n: int, M: int, K: int, N: int, seed: int) -> DealtMat:
+    from workloads import ARR_MA, ARR_MX, ARR_MY
+    f = F.Field(p)
+    assert f.L == 1
+    al = f.alpha_shares(n, seed)
+    Xs, X = f.deal_uniform_secret(n, seed, ARR_MX, M * K, al)
+    Ys, Y = f.deal_uniform_secret(n, seed, ARR_MY, K * N, al)
+    Av = f.deal_values(seed, ARR_MA, M * K)
+    Bv = f.deal_values(seed, ARR_MA + 1, K * N)
+    Cv = f.matmul(Av.reshape(M, K), Bv.reshape(K, N)).reshape(1, M * N)
+    T = F.TripleArr(f.deal_secret(n, seed, ARR_MA, Av, al), f.deal_secret(n, seed, ARR_MA + 1, Bv, al),
+                    f.deal_secret(n, seed, ARR_MA + 2, Cv, al))
+    return DealtMat(f, n, seed, M, K, N, al, Xs, X, Ys, Y, T)
+
+
+def open_difference(f: F.Field, x: F.Shares, a: F.Shares):
+    """Opened sum_i (x_i - a_i) and the MAC shares m(x)_i - m(a)_i."""
+    n = x.n
+    dv = np.stack([f.sub_public(x.val[i], a.val[i]) for i in range(n)])
+    dm = np.stack([f.sub_public(x.mac[i], a.mac[i]) for i in range(n)])
+    return f.open(dv), dm
+
+
+def matrix_triple_open(D: DealtMat, log: Optional["F.MacLog"] = None):
+    E, Em = open_difference(D.f, D.X, D.T.a)
+    Fo, Fm = open_difference(D.f, D.Y, D.T.b)
+    if log is not None:
+        log.add(E, Em)
+        log.add(Fo, Fm)
+    return E, Fo
+
+
+def matrix_triple_run(D: DealtMat, check_seed: int, epoch: int = 0):
+    """E = open(X - A), F = open(Y - B); Z_i = C_i + E B_i + A_i F + [i=0] E F,
+    M(Z)_i = M(C)_i + E M(B)_i + M(A)_i F + alpha_i E F; MAC check over [E, F]."""
+    f, n, M, K, N = D.f, D.n, D.M, D.K, D.N
+    log = F.MacLog(f, n, check_seed, epoch)
+    E, Fo = matrix_triple_open(D, log)
+    Em, Fmat = E.reshape(M, K), Fo.reshape(K, N)
+    EF = f.matmul(Em, Fmat).reshape(1, M * N)
+    Zv = np.empty((n, 1, M * N), dtype=np.uint64)
+    Zm = np.empty((n, 1, M * N), dtype=np.uint64)
+    for i in range(n):
+        EB = f.matmul(Em, D.T.b.val[i].reshape(K, N)).reshape(1, M * N)
+        AF = f.matmul(D.T.a.val[i].reshape(M, K), Fmat).reshape(1, M * N)
+        z = f.add_public(f.add_public(D.T.c.val[i], EB), AF)
+        if i == 0:
+            z = f.add_public(z, EF)
+        Zv[i] = z
+        EMB = f.matmul(Em, D.T.b.mac[i].reshape(K, N)).reshape(1, M * N)
+        MAF = f.matmul(D.T.a.mac[i].reshape(M, K), Fmat).reshape(1, M * N)
+        aEF = f.scale_public(int(D.alpha[i, 0]), EF)
+        Zm[i] = f.add_public(f.add_public(f.add_public(D.T.c.mac[i], EMB), MAF), aEF)
+    ok, sigma = log.check(D.alpha)
+    return dict(E=E, F=Fo, Z=F.Shares(Zv, Zm), ok=ok, sigma=sigma)
+
+
+def matrix_triple_entries(D: DealtMat, E: np.ndarray, Fo: np.ndarray, rows, cols):
+    """Z_i[r, c] and M(Z)_i[r, c] at the sampled positions, one dot product at a time."""
+    f, n, M, K, N = D.f, D.n, D.M, D.K, D.N
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    Em, Fmat = E.reshape(M, K), Fo.reshape(K, N)
+    ef = f.matmul_entries(Em, Fmat, rows, cols)
+    zv = np.empty((n, len(rows)), dtype=np.uint64)
+    zm = np.empty((n, len(rows)), dtype=np.uint64)
+    flat = rows * N + cols
+    for i in range(n):
+        eb = f.matmul_entries(Em, D.T.b.val[i].reshape(K, N), rows, cols)
+        af = f.matmul_entries(D.T.a.val[i].reshape(M, K), Fmat, rows, cols)
+        z = f.add_public(f.add_public(D.T.c.val[i][:, flat].copy(), eb.reshape(1, -1)), af.reshape(1, -1))
+        if i == 0:
+            z = f.add_public(z, ef.reshape(1, -1))
+        zv[i] = z[0]
+        emb = f.matmul_entries(Em, D.T.b.mac[i].reshape(K, N), rows, cols)
+        maf = f.matmul_entries(D.T.a.mac[i].reshape(M, K), Fmat, rows, cols)
+        aef = f.scale_public(int(D.alpha[i, 0]), ef.reshape(1, -1))
+        zm[i] = f.add_public(f.add_public(f.add_public(D.T.c.mac[i][:, flat].copy(), emb.reshape(1, -1)),
+                                          maf.reshape(1, -1)), aef)[0]
+    return zv, zm

@@ -135,6 +135,7 @@ spdz_status spdz_ctx_destroy(spdz_ctx *c) {
   if (c->d_acc) hipFree(c->d_acc);
   if (c->d_red) hipFree(c->d_red);
   if (c->d_sigma) hipFree(c->d_sigma);
+  if (c->ws) hipFree(c->ws);
   if (c->h_sigma) hipHostFree(c->h_sigma);
   delete c;
   return SPDZ_OK;
@@ -208,6 +209,28 @@ spdz_status spdz_reduce_add(spdz_ctx *c, const spdz_shares *x, spdz_shares *out)
   SPDZ_CHECK(check_sv(c, x, x->len));
   SPDZ_CHECK(check_sv(c, out, 1));
   return launch_reduce(c, x, out);
+}
+
+spdz_status spdz_matmul_triple(spdz_ctx *c, int64_t M, int64_t K, int64_t N, const spdz_shares *X,
+                               const spdz_shares *Y, const spdz_triple *T, spdz_shares *Z, uint64_t *E_pub,
+                               uint64_t *F_pub, int variant) {
+  SPDZ_LIVE(c);
+  if (!X || !Y || !T || !Z) return SPDZ_E_INVAL;
+  if (c->L != 1) return SPDZ_E_UNSUPPORTED;
+  if (M <= 0 || K <= 0 || N <= 0) return SPDZ_E_SHAPE;
+  if (variant == -1) variant = 1;
+  if (variant != 0 && variant != 1) return SPDZ_E_INVAL;
+  if (variant == 1 && K > MAX_MFMA_K) return SPDZ_E_SHAPE;
+  SPDZ_CHECK(check_sv(c, X, M * K));
+  SPDZ_CHECK(check_sv(c, &T->a, M * K));
+  SPDZ_CHECK(check_sv(c, Y, K * N));
+  SPDZ_CHECK(check_sv(c, &T->b, K * N));
+  SPDZ_CHECK(check_sv(c, &T->c, M * N));
+  SPDZ_CHECK(check_sv(c, Z, M * N));
+  if (overlaps(c, Z, X) || overlaps(c, Z, Y) || overlaps(c, Z, &T->a) || overlaps(c, Z, &T->b) ||
+      overlaps(c, Z, &T->c))
+    return SPDZ_E_INVAL;
+  return launch_matmul_triple(c, M, K, N, X, Y, T, Z, E_pub, F_pub, variant);
 }
 
 spdz_status spdz_mac_check(spdz_ctx *c, int *accepted, uint64_t *sigma_out) {
@@ -323,6 +346,30 @@ spdz_status spdz_deal_secret(spdz_ctx *c, uint64_t seed, uint64_t array_id, cons
   SPDZ_CHECK(check_sv(c, out, out->len));
   if (out->len == 0) return SPDZ_OK;
   return launch_deal_secret(c, seed, array_id, values, out, values_out);
+}
+
+spdz_status spdz_deal_matrix_triple(spdz_ctx *c, uint64_t seed, uint64_t array_id, int64_t M, int64_t K, int64_t N,
+                                    spdz_triple *t) {
+  SPDZ_LIVE(c);
+  if (!t) return SPDZ_E_INVAL;
+  if (c->L != 1) return SPDZ_E_UNSUPPORTED;
+  if (M <= 0 || K <= 0 || N <= 0 || K > MAX_MFMA_K) return SPDZ_E_SHAPE;
+  SPDZ_CHECK(check_sv(c, &t->a, M * K));
+  SPDZ_CHECK(check_sv(c, &t->b, K * N));
+  SPDZ_CHECK(check_sv(c, &t->c, M * N));
+  // public values of A, B and C = A B live in a temporary buffer; A and B come from
+  // the value streams of array_id and array_id + 1, C is shared with array_id + 2
+  u64 *tmp = nullptr;
+  const size_t words = (size_t)M * K + (size_t)K * N + (size_t)M * N;
+  if (hipMalloc((void **)&tmp, words * 8) != hipSuccess) return SPDZ_E_NOMEM;
+  u64 *av = tmp, *bv = tmp + (size_t)M * K, *cv = bv + (size_t)K * N;
+  spdz_status s = launch_deal_secret(c, seed, array_id, nullptr, &t->a, av);
+  if (s == SPDZ_OK) s = launch_deal_secret(c, seed, array_id + 1, nullptr, &t->b, bv);
+  if (s == SPDZ_OK) s = launch_public_matmul(c, M, K, N, av, bv, cv);
+  if (s == SPDZ_OK) s = launch_deal_secret(c, seed, array_id + 2, cv, &t->c, nullptr);
+  if (hipStreamSynchronize(c->stream) != hipSuccess && s == SPDZ_OK) s = SPDZ_E_HIP;
+  hipFree(tmp);
+  return s;
 }
 
 spdz_status spdz_deal_triple(spdz_ctx *c, uint64_t seed, uint64_t array_id, spdz_triple *t) {

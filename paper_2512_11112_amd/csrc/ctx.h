@@ -19,6 +19,7 @@ constexpr int MIN_PARTIES = 2;
 constexpr int BLOCK = 256;          // threads per block of the element-wise kernels
 constexpr int WAVES = BLOCK / 64;   // wave64
 constexpr int MAX_SLOTS = 4096;     // per-block accumulator slots (upper bound on grid size)
+constexpr int64_t MAX_MFMA_K = 8191; // int32 class sums stay exact for inner dimension 2K <= 16382
 
 // stream-id layout of the dealer and the MAC-check coefficients:
 // stream = tag << 56 | array_id << 8 | party
@@ -49,6 +50,9 @@ struct spdz_ctx {
   spdz::u64 *d_sigma = nullptr; // [n][L]
   spdz::u64 *h_sigma = nullptr; // pinned host copy of d_sigma
   int grid_mult = 0;            // blocks per CU for streaming kernels (0 = from occupancy)
+  // workspace of the matrix-triple product (digit planes, E F), grown on demand
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
   // kernel timing (spdz_timing_enable): HIP events around each main kernel
   bool timing = false;
   struct Pending {
@@ -86,6 +90,12 @@ spdz_status visit(const spdz_ctx *c, Fn &&fn) {
 
 inline spdz_status hip_status(hipError_t e) { return e == hipSuccess ? SPDZ_OK : SPDZ_E_HIP; }
 
+#define SPDZ_RET(expr)                    \
+  do {                                    \
+    spdz_status _st = (expr);             \
+    if (_st != SPDZ_OK) return _st;       \
+  } while (0)
+
 // Records HIP events on the context stream around the kernel launched in its
 // scope when timing is enabled.
 struct KTimer {
@@ -117,6 +127,8 @@ struct KTimer {
 
 // launchers (elementwise.hip)
 spdz_status launch_open(spdz_ctx *c, const spdz_shares *x, u64 *out_pub);
+// opens sum_i (x_i - sub_i) (the mask step of a Beaver product), logging it with MAC shares m(x)_i - m(sub)_i
+spdz_status launch_open_diff(spdz_ctx *c, const spdz_shares *x, const spdz_shares *sub, u64 *out_pub);
 spdz_status launch_beaver(spdz_ctx *c, const spdz_shares *x, const spdz_shares *y, const spdz_triple *t,
                           spdz_shares *z, u64 *d_pub, u64 *e_pub, const u64 *lin, spdz_shares *w, u64 *w_pub,
                           spdz_shares *s);
@@ -129,5 +141,10 @@ spdz_status launch_deal_secret(spdz_ctx *c, u64 seed, u64 array_id, const u64 *v
                                u64 *values_out);
 spdz_status launch_deal_triple(spdz_ctx *c, u64 seed, u64 array_id, spdz_triple *t);
 spdz_status launch_copy(u64 *dst, const u64 *src, int64_t words, hipStream_t stream);
+// matmul.hip
+spdz_status launch_matmul_triple(spdz_ctx *c, int64_t M, int64_t K, int64_t N, const spdz_shares *X,
+                                 const spdz_shares *Y, const spdz_triple *T, spdz_shares *Z, u64 *E_pub, u64 *F_pub,
+                                 int variant);
+spdz_status launch_public_matmul(spdz_ctx *c, int64_t M, int64_t K, int64_t N, const u64 *A, const u64 *B, u64 *C);
 
 }  // namespace spdz

@@ -124,6 +124,7 @@ __device__ __forceinline__ typename F::E cmul(const Coef<F> &k, typename F::E a)
 template <class F, int N>
 struct OpenArgs {
   SV x;
+  SV sub;  // if sub.val != nullptr the opened value is sum_i (x_i - sub_i), MAC shares m(x)_i - m(sub)_i
   u64 *out;
   int64_t W;
   u64 coef_state;
@@ -142,8 +143,13 @@ __global__ __launch_bounds__(BLOCK) void k_open(const OpenArgs<F, N> a) {
     E m[N];
 #pragma unroll
     for (int i = 0; i < N; i++) {
-      s = F::add(s, F::load(a.x.val + i * a.x.ps, a.x.ls, e));
+      E v = F::load(a.x.val + i * a.x.ps, a.x.ls, e);
       m[i] = F::load(a.x.mac + i * a.x.ps, a.x.ls, e);
+      if (a.sub.val) {
+        v = F::sub(v, F::load(a.sub.val + i * a.sub.ps, a.sub.ls, e));
+        m[i] = F::sub(m[i], F::load(a.sub.mac + i * a.sub.ps, a.sub.ls, e));
+      }
+      s = F::add(s, v);
     }
     F::store(a.out, a.W, e, s);
     const E r = uniform_elem<F>(a.coef_state, (u64)(a.j0 + e));
@@ -564,11 +570,16 @@ spdz_status launch_copy(u64 *dst, const u64 *src, int64_t words, hipStream_t str
 }
 
 spdz_status launch_open(spdz_ctx *c, const spdz_shares *x, u64 *out_pub) {
+  return launch_open_diff(c, x, nullptr, out_pub);
+}
+
+spdz_status launch_open_diff(spdz_ctx *c, const spdz_shares *x, const spdz_shares *sub, u64 *out_pub) {
   return visit(c, [&](auto f, auto nn) -> spdz_status {
     using F = decltype(f);
     constexpr int N = decltype(nn)::value;
     OpenArgs<F, N> a;
     a.x = sv_of(x);
+    a.sub = sub ? sv_of(sub) : SV{nullptr, nullptr, 0, 0};
     a.out = out_pub;
     a.W = x->len;
     a.coef_state = coef_state(c);

@@ -68,6 +68,10 @@ def lib() -> ctypes.CDLL:
             "spdz_deal_secret": (i32, [vp, ctypes.c_uint64, ctypes.c_uint64, vp,
                                        ctypes.POINTER(Shares), vp]),
             "spdz_deal_triple": (i32, [vp, ctypes.c_uint64, ctypes.c_uint64, ctypes.POINTER(Triple)]),
+            "spdz_matmul_triple": (i32, [vp, i64, i64, i64, ctypes.POINTER(Shares), ctypes.POINTER(Shares),
+                                         ctypes.POINTER(Triple), ctypes.POINTER(Shares), vp, vp, i32]),
+            "spdz_deal_matrix_triple": (i32, [vp, ctypes.c_uint64, ctypes.c_uint64, i64, i64, i64,
+                                              ctypes.POINTER(Triple)]),
             "spdz_timing_enable": (i32, [vp, i32]),
             "spdz_timing_get": (i32, [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(i64)]),
@@ -137,6 +141,12 @@ class TripleTensor:
     @staticmethod
     def empty(n, L, W, device="cuda") -> "TripleTensor":
         return TripleTensor(*(ShareTensor.empty(n, L, W, device) for _ in range(3)))
+
+    @staticmethod
+    def empty_matrix(n, M, K, N, device="cuda") -> "TripleTensor":
+        """A [M x K], B [K x N], C [M x N] (single-limb field)."""
+        return TripleTensor(ShareTensor.empty(n, 1, M * K, device), ShareTensor.empty(n, 1, K * N, device),
+                            ShareTensor.empty(n, 1, M * N, device))
 
     def desc(self) -> Triple:
         return Triple(self.a.desc(), self.b.desc(), self.c.desc())
@@ -254,6 +264,16 @@ class Context:
         _check(lib().spdz_reduce_add(self._h, ctypes.byref(dx), ctypes.byref(do)), "spdz_reduce_add")
         return out
 
+    def spdz_matmul_triple(self, M: int, K: int, N: int, X: ShareTensor, Y: ShareTensor,
+                           T: TripleTensor, Z: ShareTensor, E_pub: Optional[torch.Tensor] = None,
+                           F_pub: Optional[torch.Tensor] = None, variant: int = -1):
+        """Z = X Y with a matrix triple; matrices are [n][1][rows*cols] row-major."""
+        dx, dy, dt, dz = X.desc(), Y.desc(), T.desc(), Z.desc()
+        _check(lib().spdz_matmul_triple(self._h, M, K, N, ctypes.byref(dx), ctypes.byref(dy),
+                                        ctypes.byref(dt), ctypes.byref(dz), _ptr(E_pub), _ptr(F_pub),
+                                        variant), "spdz_matmul_triple")
+        return Z
+
     def spdz_mac_check(self):
         """(accepted, [sigma_i as ints])."""
         acc = ctypes.c_int(0)
@@ -282,6 +302,13 @@ class Context:
         _check(lib().spdz_deal_secret(self._h, ctypes.c_uint64(seed), ctypes.c_uint64(array_id),
                                       _ptr(values), ctypes.byref(d), _ptr(values_out)),
                "spdz_deal_secret")
+        return out
+
+    def spdz_deal_matrix_triple(self, seed: int, array_id: int, M: int, K: int, N: int,
+                                out: TripleTensor) -> TripleTensor:
+        d = out.desc()
+        _check(lib().spdz_deal_matrix_triple(self._h, ctypes.c_uint64(seed), ctypes.c_uint64(array_id),
+                                             M, K, N, ctypes.byref(d)), "spdz_deal_matrix_triple")
         return out
 
     def spdz_deal_triple(self, seed: int, array_id: int, out: TripleTensor) -> TripleTensor:

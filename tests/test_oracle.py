@@ -342,3 +342,29 @@ def test_matrix_beaver_closed_form(p, n):
     assert E == [[(X[r_][k] - A[r_][k]) % p for k in range(K)] for r_ in range(M)]
     ok, _ = R.mac_check(p, alpha, log, 5, 0)
     assert ok and len(log.values) == M * K + K * N
+
+
+# --------------------------------------------------------------------------
+# matrix triples through the tier-1 composition
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [2, 3])
+def test_matrix_triple_tier1_closed_form(n):
+    from oracle.pipelines import deal_matrices, matrix_triple_entries, matrix_triple_run
+    p, M, K, N = (1 << 61) - 1, 13, 21, 9
+    D = deal_matrices(p, n, M, K, N, 4)
+    r = matrix_triple_run(D, check_seed=4)
+    assert r["ok"]
+    X = D.Xs.reshape(M, K).astype(object)
+    Y = D.Ys.reshape(K, N).astype(object)
+    XY = (X @ Y) % p
+    a = sum(int(D.alpha[i, 0]) for i in range(n)) % p
+    Z = sum(r["Z"].val[i, 0].astype(object) for i in range(n)) % p
+    MZ = sum(r["Z"].mac[i, 0].astype(object) for i in range(n)) % p
+    assert (Z.reshape(M, N) == XY).all()
+    assert (MZ.reshape(M, N) == (a * XY) % p).all()
+    rows, cols = [0, 5, 12, 7], [0, 8, 3, 3]
+    zv, zm = matrix_triple_entries(D, r["E"], r["F"], rows, cols)
+    for q, (rr, cc) in enumerate(zip(rows, cols)):
+        for i in range(n):
+            assert zv[i, q] == r["Z"].val[i, 0, rr * N + cc]
+            assert zm[i, q] == r["Z"].mac[i, 0, rr * N + cc]
