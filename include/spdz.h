@@ -182,6 +182,128 @@ spdz_status spdz_matmul_triple(spdz_ctx *ctx, int64_t M, int64_t K, int64_t N, c
 spdz_status spdz_mac_check(spdz_ctx *ctx, int *accepted, uint64_t *sigma_out);
 
 /* ---------------------------------------------------------------------- */
+/* Batched DAG execution (p = 2^61 - 1)                                     */
+/* ---------------------------------------------------------------------- */
+/* The paper's runtime executes a data-flow graph whose vector nodes keep
+ * their lane width (AddBatch, MultBatch, ...; Sec. III-B "Vectorization is
+ * first-class") and reads inputs through views (Load(base, start, count),
+ * Sec. III-B; "Structured Data Movement", Sec. III-C), scheduled by the
+ * non-blocking loop of Sec. III-C (Algorithm 1) with heavy ops first and a
+ * CPU fall-back below MIN_KERNEL_SIZE (Sec. IV-A).  A spdz_dag holds a layered
+ * graph of element-wise ops and runs it level by level. */
+typedef struct spdz_dag spdz_dag;
+
+enum { SPDZ_OP_MUL = 0, SPDZ_OP_ADD = 1, SPDZ_OP_SMUL = 2 };
+enum { SPDZ_MODE_PER_OP = 0, SPDZ_MODE_PER_LEVEL = 1, SPDZ_MODE_GRAPH = 2 };
+enum { SPDZ_POLICY_STATIC = 0, SPDZ_POLICY_LEARNED = 1, SPDZ_POLICY_ALL_GPU = 2, SPDZ_POLICY_ALL_CPU = 3 };
+
+typedef struct {
+  int32_t kind;      /* SPDZ_OP_MUL (Beaver product), SPDZ_OP_ADD, SPDZ_OP_SMUL (times a public constant) */
+  int32_t level;     /* >= 1; ops are listed in non-decreasing level order */
+  int64_t width;     /* elements of the output (1 .. 2^30) */
+  int64_t src1, off1;/* operand 1: node id and view offset; element j reads src[(off + j) mod width(src)] */
+  int64_t src2, off2;/* operand 2 (MUL, ADD); ignored for SMUL */
+  uint64_t konst;    /* SMUL: the public multiplier (canonical) */
+} spdz_dag_op;
+
+/* Build a DAG: nodes 0 .. n_inputs-1 are inputs of the given widths, node
+ * n_inputs + k is the output of ops[k].  An operand must come from a strictly
+ * lower level (inputs are level 0).  Allocates device arenas for every node's
+ * shares ([n][width] values and MACs) and every Beaver op's triple.  Single-limb
+ * field only (SPDZ_E_UNSUPPORTED otherwise).  *out is library-owned. */
+spdz_status spdz_dag_create(spdz_ctx *ctx, int n_inputs, const int64_t *input_widths, int64_t n_ops,
+                            const spdz_dag_op *ops, spdz_dag **out);
+spdz_status spdz_dag_destroy(spdz_dag *dag);
+
+/* Device descriptor of a node's shares (fill inputs, read outputs) and of a Beaver op's triple. */
+spdz_status spdz_dag_node(spdz_dag *dag, int64_t node, spdz_shares *out);
+spdz_status spdz_dag_triple(spdz_dag *dag, int64_t op, spdz_triple *out);
+
+/* Values one run opens: d then e of every Beaver op, in op order. */
+int64_t spdz_dag_opened_count(const spdz_dag *dag);
+
+/* Fake preprocessing: input i is dealt as array input_array0 + i; the triple of
+ * Beaver op k as arrays triple_array0 + 3 k (+0 a, +1 b, +2 c).  Synchronous. */
+spdz_status spdz_dag_deal(spdz_dag *dag, uint64_t seed, uint64_t input_array0, uint64_t triple_array0);
+
+/* Run every op once.  mode: SPDZ_MODE_PER_OP (one launch per op),
+ * SPDZ_MODE_PER_LEVEL (one persistent fused launch per level), SPDZ_MODE_GRAPH
+ * (the per-level launches captured once into a hipGraph and replayed; when a
+ * policy sends ops to the CPU the run falls back to per-level launches).
+ * policy: SPDZ_POLICY_STATIC (width < threshold runs on the CPU back end),
+ * SPDZ_POLICY_LEARNED (the cost model of spdz_dag_set_cost_model decides),
+ * SPDZ_POLICY_ALL_GPU, SPDZ_POLICY_ALL_CPU.  Results do not depend on mode or
+ * policy.  The opened values are appended to the context's log (check them with
+ * spdz_mac_check).  Synchronous; *wall_ms (nullable) receives the wall time. */
+spdz_status spdz_dag_run(spdz_dag *dag, int mode, int policy, double *wall_ms);
+
+/* After a run with CPU-executed ops, copy their outputs to the device arenas
+ * (spdz_dag_node descriptors then hold every node's current value). */
+spdz_status spdz_dag_fetch_host_outputs(spdz_dag *dag);
+
+/* Launch shape of the level kernel: elements per work item (power of two,
+ * 64..2^20) and blocks per CU (1..64). */
+spdz_status spdz_dag_set_launch(spdz_dag *dag, int tile, int blocks_per_cu);
+
+/* Time every (tile, blocks per CU) candidate on the first max_levels levels
+ * (all ops on the GPU, per-level launches, MAC terms into scratch slots) and
+ * keep the fastest; its shape and time go to the nullable outputs. */
+spdz_status spdz_dag_autotune(spdz_dag *dag, int max_levels, int *tile, int *blocks_per_cu, double *best_ms);
+
+/* MIN_KERNEL_SIZE of the static policy (default 65535 = slice 262140 / 4). */
+spdz_status spdz_dag_set_threshold(spdz_dag *dag, int64_t min_kernel_size);
+
+/* Statistics of the last run: ops on each side, host/device copies, and the
+ * time spent in cost-model inference (ms). */
+spdz_status spdz_dag_last_stats(const spdz_dag *dag, int64_t *gpu_ops, int64_t *cpu_ops, int64_t *copies,
+                                double *predict_ms);
+
+/* ---------------------------------------------------------------------- */
+/* FP32 MLP cost model of the learned dispatcher                            */
+/* ---------------------------------------------------------------------- */
+/* Input features of an op (SPDZ_MLP_IN): one-hot kind (3), log2 width, party
+ * count, limbs, log2(1 + ops in its level).  Three hidden ReLU layers of 64,
+ * linear head of 2: predicted log2 ns on the CPU back end and on the GPU (per
+ * op, inside a fused level launch).  Parameters are one float array:
+ * W1 [64][7], b1 [64], W2 [64][64], b2 [64], W3 [64][64], b3 [64], W4 [2][64], b4 [2]. */
+#define SPDZ_MLP_IN 7
+#define SPDZ_MLP_HID 64
+#define SPDZ_MLP_OUT 2
+#define SPDZ_MLP_NPARAM 8962
+
+/* Y [B][2] = f(X [B][7]); if acts != NULL the three post-ReLU hidden
+ * activations are saved there ([3][B][64]) for spdz_mlp_backward.  Device pointers. */
+spdz_status spdz_mlp_forward(void *hip_stream, const float *W, const float *X, int64_t B, float *Y, float *acts);
+
+/* Gradient of sum_b <dY_b, Y_b> with respect to every parameter, summed over
+ * the batch, into dW [SPDZ_MLP_NPARAM] (overwritten).  Needs the activations
+ * of spdz_mlp_forward on the same X.  Device pointers. */
+spdz_status spdz_mlp_backward(void *hip_stream, const float *W, const float *X, const float *acts, const float *dY,
+                              int64_t B, float *dW);
+
+/* One Adam step (Kingma and Ba) with bias correction for step t >= 1. */
+spdz_status spdz_mlp_adam(void *hip_stream, float *W, const float *dW, float *m, float *v, int64_t t, float lr,
+                          float beta1, float beta2, float eps);
+
+/* Train W (device, in/out) on X [N][7], T [N][2] (device) by minibatch Adam on
+ * the mean squared error for `epochs` passes in a seeded shuffled order;
+ * loss_per_epoch (HOST [epochs], nullable) receives the full-set MSE after each
+ * epoch.  Synchronous. */
+spdz_status spdz_mlp_train(void *hip_stream, float *W, const float *X, const float *T, int64_t N, int epochs,
+                           int batch, float lr, uint64_t seed, float *loss_per_epoch);
+
+/* Use W (HOST, SPDZ_MLP_NPARAM floats) for SPDZ_POLICY_LEARNED: an op runs on
+ * the CPU iff 2^cpu + xfer < 2^gpu, where xfer = ns_per_byte * (bytes the op
+ * would move between host and device) + ns_per_copy * (copies). */
+spdz_status spdz_dag_set_cost_model(spdz_dag *dag, const float *W, double ns_per_byte, double ns_per_copy);
+
+/* Measure one level of q ops of `kind` and `width` (q clipped so the level
+ * holds at most 2^26 elements): per-op GPU time inside a fused launch and
+ * per-op CPU back-end time, in ns (median of reps).  q_used receives the clip. */
+spdz_status spdz_dag_time_level(spdz_ctx *ctx, int kind, int64_t width, int64_t q, int reps, double *gpu_ns,
+                                double *cpu_ns, int64_t *q_used);
+
+/* ---------------------------------------------------------------------- */
 /* Measurement (not part of the protocol)                                    */
 /* ---------------------------------------------------------------------- */
 

@@ -172,3 +172,65 @@ def matrix_triple_entries(D: DealtMat, E: np.ndarray, Fo: np.ndarray, rows, cols
         zm[i] = f.add_public(f.add_public(f.add_public(D.T.c.mac[i][:, flat].copy(), emb.reshape(1, -1)),
                                           maf.reshape(1, -1)), aef)[0]
     return zv, zm
+
+
+# ---------------------------------------------------------------------------
+# layered DAG (single-limb field): ops one at a time in op-id order
+# ---------------------------------------------------------------------------
+def dag_run(dag, seed: int, check_seed: int, epoch: int = 0, keep=None):
+    """Executes every op of `dag` (workloads.dag.Dag) on oracle-dealt inputs and triples.
+
+    Inputs are arrays ARR_DAG_IN0 + i, the triple of Beaver op k is dealt with
+    array id ARR_DAG_TRIPLE0 + 3 k.  Element j of an operand view reads
+    src[(off + j) mod width(src)].  Returns (outputs {node: Shares} for the
+    nodes in `keep` (all if None), ok, sigma).
+    """
+    from workloads import ARR_DAG_IN0
+    from workloads.dag import OP_ADD, OP_MUL, triple_array_id
+    f = F.Field(dag.p)
+    n = dag.n_parties
+    al = f.alpha_shares(n, seed)
+    nodes = {}
+    for i in range(2):
+        _, nodes[i] = f.deal_uniform_secret(n, seed, ARR_DAG_IN0 + i, dag.in_width, al)
+    log = F.MacLog(f, n, check_seed, epoch)
+    # last use of every node, to free memory early
+    last = {}
+    for k in range(dag.n_ops):
+        last[int(dag.src1[k])] = k
+        if dag.src2[k] >= 0:
+            last[int(dag.src2[k])] = k
+    out = {}
+
+    def view(node, off, w):
+        s = nodes[node]
+        idx = (off + np.arange(w, dtype=np.int64)) % s.width
+        return F.Shares(np.ascontiguousarray(s.val[:, :, idx]), np.ascontiguousarray(s.mac[:, :, idx]))
+
+    for k in range(dag.n_ops):
+        w = int(dag.width[k])
+        x = view(int(dag.src1[k]), int(dag.off1[k]), w)
+        kind = int(dag.kind[k])
+        if kind == OP_MUL:
+            y = view(int(dag.src2[k]), int(dag.off2[k]), w)
+            t = f.deal_triple(n, seed, triple_array_id(k), w, al)
+            z, d, e, dm, em = f.beaver(al, x, y, t)
+            log.add(d, dm)
+            log.add(e, em)
+        elif kind == OP_ADD:
+            y = view(int(dag.src2[k]), int(dag.off2[k]), w)
+            z = f.linear(al, [x, y], [1, 1])
+        else:
+            z = f.linear(al, [x], [int(dag.const[k])])
+        node = 2 + k
+        nodes[node] = z
+        if keep is None or node in keep:
+            out[node] = z
+        for src in (int(dag.src1[k]), int(dag.src2[k])):
+            if src >= 2 and last.get(src) == k and src not in out:
+                nodes.pop(src, None)
+    for i in range(2):
+        if keep is None or i in keep:
+            out[i] = nodes[i]
+    ok, sigma = log.check(al)
+    return out, ok, sigma

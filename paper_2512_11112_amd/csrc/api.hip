@@ -110,8 +110,8 @@ spdz_status spdz_ctx_create(spdz_ctx **out, int n_parties, const uint64_t *p_lim
   const size_t red_words = (size_t)MAX_SLOTS * 2 * n_parties * n_limbs;
   if (hipMalloc((void **)&c->d_acc, acc_words * 8) != hipSuccess ||
       hipMalloc((void **)&c->d_red, red_words * 8) != hipSuccess ||
-      hipMalloc((void **)&c->d_sigma, (size_t)n_parties * n_limbs * 8) != hipSuccess ||
-      hipHostMalloc((void **)&c->h_sigma, (size_t)n_parties * n_limbs * 8, hipHostMallocDefault) != hipSuccess) {
+      hipMalloc((void **)&c->d_sigma, (size_t)(n_parties + 1) * n_limbs * 8) != hipSuccess ||
+      hipHostMalloc((void **)&c->h_sigma, (size_t)(n_parties + 1) * n_limbs * 8, hipHostMallocDefault) != hipSuccess) {
     spdz_ctx_destroy(c);
     return SPDZ_E_NOMEM;
   }
@@ -238,28 +238,30 @@ spdz_status spdz_mac_check(spdz_ctx *c, int *accepted, uint64_t *sigma_out) {
   if (!accepted) return SPDZ_E_INVAL;
   *accepted = 0;
   SPDZ_CHECK(launch_maccheck_finalize(c));
-  const size_t bytes = (size_t)c->n * c->L * 8;
+  const size_t bytes = (size_t)(c->n + 1) * c->L * 8;
   if (hipMemcpyAsync(c->h_sigma, c->d_sigma, bytes, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess)
     return SPDZ_E_HIP;
-  if (sigma_out) memcpy(sigma_out, c->h_sigma, bytes);
-  // accept iff sum_i sigma_i = 0 mod p (host-side sum of n residues)
+  // a = sum_j r_j a_j and G_i = sum_j r_j gamma_i(a_j), device slots plus the CPU back end's sums;
+  // sigma_i = G_i - alpha_i a, accept iff sum_i sigma_i = 0
   bool zero;
-  if (c->L == 1) {
-    u64 s = 0;
+  auto finish = [&](auto f) {
+    using F = decltype(f);
+    typename F::E a = F::add(F::from_words(c->h_sigma), F::from_words(c->host_acc[0]));
+    typename F::E tot = F::zero();
     for (int i = 0; i < c->n; i++) {
-      s += c->h_sigma[i];
-      if (s >= F61::P) s -= F61::P;
+      typename F::E g = F::add(F::from_words(c->h_sigma + (1 + i) * F::L), F::from_words(c->host_acc[1 + i]));
+      typename F::E s = F::sub(g, F::mul(F::from_words(c->alpha[i]), a));
+      if (sigma_out) F::to_words(s, sigma_out + i * F::L);
+      tot = F::add(tot, s);
     }
-    zero = s == 0;
-  } else {
-    u128 p = ((u128)F127::PHI << 64) | ~0ull, s = 0;
-    for (int i = 0; i < c->n; i++) {
-      s += ((u128)c->h_sigma[2 * i + 1] << 64) | c->h_sigma[2 * i];
-      if (s >= p) s -= p;
-    }
-    zero = s == 0;
-  }
+    zero = F::is_zero(tot);
+  };
+  if (c->L == 1)
+    finish(F61{});
+  else
+    finish(F127{});
+  memset(c->host_acc, 0, sizeof(c->host_acc));
   c->epoch += 1;
   c->log_count = 0;
   c->slots = 0;

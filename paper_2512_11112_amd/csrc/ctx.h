@@ -49,6 +49,8 @@ struct spdz_ctx {
   spdz::u64 *d_red = nullptr;   // ReduceAdd partial sums [MAX_SLOTS][2 n][L]
   spdz::u64 *d_sigma = nullptr; // [n][L]
   spdz::u64 *h_sigma = nullptr; // pinned host copy of d_sigma
+  // MAC-check sums contributed by ops that ran on the CPU back end ([0] = A, [1 + i] = G_i), canonical
+  spdz::u64 host_acc[spdz::MAX_PARTIES + 1][2] = {};
   int grid_mult = 0;            // blocks per CU for streaming kernels (0 = from occupancy)
   // workspace of the matrix-triple product (digit planes, E F), grown on demand
   void *ws = nullptr;

@@ -16,57 +16,10 @@
 // launch has finished; no atomics are needed.
 #include <unordered_map>
 
+#include "blockred.h"
 #include "ctx.h"
 
 namespace spdz {
-
-// --------------------------------------------------------------------------
-// block-level reduction of K residues per thread
-// --------------------------------------------------------------------------
-template <class F>
-__device__ __forceinline__ typename F::E shfl_xor_e(typename F::E a, int mask) {
-  u32 w[F::WORDS32];
-#pragma unroll
-  for (int k = 0; k < F::WORDS32; k++) w[k] = (u32)__shfl_xor((int)F::word32(a, k), mask, 64);
-  return F::from32(w);
-}
-
-// Sum v[k] over the block; the total of component k is returned in thread k
-// (k < K), other threads get zero.  Contains __syncthreads(): call from every
-// thread of the block.
-template <class F, int K>
-__device__ typename F::E block_sum(typename F::E (&v)[K]) {
-  using E = typename F::E;
-  __shared__ E sh[WAVES][K];
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-#pragma unroll
-    for (int k = 0; k < K; k++) v[k] = F::add(v[k], shfl_xor_e<F>(v[k], off));
-  }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __syncthreads();  // sh may be in use by a previous call
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < K; k++) sh[wave][k] = v[k];
-  }
-  __syncthreads();
-  E s = F::zero();
-  if (threadIdx.x < K) {
-#pragma unroll
-    for (int w = 0; w < WAVES; w++) s = F::add(s, sh[w][threadIdx.x]);
-  }
-  return s;
-}
-
-// add the block total of v into slot (K residues of L words)
-template <class F, int K>
-__device__ __forceinline__ void block_add_to_slot(typename F::E (&v)[K], u64 *slot) {
-  typename F::E s = block_sum<F, K>(v);
-  if (threadIdx.x < K) {
-    u64 *p = slot + threadIdx.x * F::L;
-    F::to_words(F::add(F::from_words(p), s), p);
-  }
-}
 
 // --------------------------------------------------------------------------
 // public coefficients: the product is specialised per launch when the
@@ -376,8 +329,7 @@ template <class F, int N>
 struct FinArgs {
   u64 *acc;
   int nslots;
-  typename F::E alpha[N];
-  u64 *sigma;
+  u64 *sigma;  // receives the N + 1 totals
 };
 
 template <class F, int N>
@@ -395,15 +347,9 @@ __global__ __launch_bounds__(BLOCK) void k_mac_finalize(const FinArgs<F, N> A) {
       for (int l = 0; l < F::L; l++) p[k * F::L + l] = 0;
     }
   }
+  // totals of the device slots: [0] = sum r a, [1 + i] = sum r gamma_i
   E t = block_sum<F, N + 1>(s);
-  __shared__ E tot[N + 1];
-  if (threadIdx.x <= N) tot[threadIdx.x] = t;
-  __syncthreads();
-  if (threadIdx.x < N) {
-    const int i = threadIdx.x;
-    E sig = F::sub(tot[1 + i], F::mul(A.alpha[i], tot[0]));
-    F::to_words(sig, A.sigma + i * F::L);
-  }
+  if (threadIdx.x <= N) F::to_words(t, A.sigma + threadIdx.x * F::L);
 }
 
 // --------------------------------------------------------------------------
@@ -695,7 +641,6 @@ spdz_status launch_maccheck_finalize(spdz_ctx *c) {
     FinArgs<F, N> A;
     A.acc = c->d_acc;
     A.nslots = c->slots;
-    alpha_of<F, N>(c, A.alpha);
     A.sigma = c->d_sigma;
     KTimer tm(c, "mac_finalize");
     hipLaunchKernelGGL((k_mac_finalize<F, N>), dim3(1), dim3(BLOCK), 0, c->stream, A);

@@ -211,10 +211,10 @@ SPDZ_HD u64 mix64(u64 z) {
 SPDZ_HD u64 sm_out(u64 state, u64 i) { return mix64(state + (i + 1) * GOLDEN); }
 
 template <class F>
-__device__ __forceinline__ typename F::E uniform_elem(u64 state, u64 e);
+SPDZ_HD typename F::E uniform_elem(u64 state, u64 e);
 
 template <>
-__device__ __forceinline__ F61::E uniform_elem<F61>(u64 state, u64 e) {
+SPDZ_HD F61::E uniform_elem<F61>(u64 state, u64 e) {
   const u64 base = e * 32u;
   for (int k = 0; k < 16; k++) {
     u64 u = sm_out(state, base + k) & F61::P;
@@ -224,7 +224,7 @@ __device__ __forceinline__ F61::E uniform_elem<F61>(u64 state, u64 e) {
 }
 
 template <>
-__device__ __forceinline__ F127::E uniform_elem<F127>(u64 state, u64 e) {
+SPDZ_HD F127::E uniform_elem<F127>(u64 state, u64 e) {
   const u64 base = e * 32u;
   for (int k = 0; k < 16; k++) {
     u64 lo = sm_out(state, base + 2 * k);

@@ -72,6 +72,28 @@ def lib() -> ctypes.CDLL:
                                          ctypes.POINTER(Triple), ctypes.POINTER(Shares), vp, vp, i32]),
             "spdz_deal_matrix_triple": (i32, [vp, ctypes.c_uint64, ctypes.c_uint64, i64, i64, i64,
                                               ctypes.POINTER(Triple)]),
+            "spdz_dag_create": (i32, [vp, i32, ctypes.POINTER(ctypes.c_int64), i64, vp, ctypes.POINTER(vp)]),
+            "spdz_dag_destroy": (i32, [vp]),
+            "spdz_dag_node": (i32, [vp, i64, ctypes.POINTER(Shares)]),
+            "spdz_dag_triple": (i32, [vp, i64, ctypes.POINTER(Triple)]),
+            "spdz_dag_opened_count": (i64, [vp]),
+            "spdz_dag_deal": (i32, [vp, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64]),
+            "spdz_dag_run": (i32, [vp, i32, i32, ctypes.POINTER(ctypes.c_double)]),
+            "spdz_dag_fetch_host_outputs": (i32, [vp]),
+            "spdz_dag_set_launch": (i32, [vp, i32, i32]),
+            "spdz_dag_autotune": (i32, [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                        ctypes.POINTER(ctypes.c_double)]),
+            "spdz_dag_set_threshold": (i32, [vp, i64]),
+            "spdz_dag_last_stats": (i32, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                          ctypes.POINTER(ctypes.c_double)]),
+            "spdz_dag_set_cost_model": (i32, [vp, vp, ctypes.c_double, ctypes.c_double]),
+            "spdz_dag_time_level": (i32, [vp, i32, i64, i64, i32, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]),
+            "spdz_mlp_forward": (i32, [vp, vp, vp, i64, vp, vp]),
+            "spdz_mlp_backward": (i32, [vp, vp, vp, vp, vp, i64, vp]),
+            "spdz_mlp_adam": (i32, [vp, vp, vp, vp, vp, i64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                    ctypes.c_float]),
+            "spdz_mlp_train": (i32, [vp, vp, vp, vp, i64, i32, i32, ctypes.c_float, ctypes.c_uint64, vp]),
             "spdz_timing_enable": (i32, [vp, i32]),
             "spdz_timing_get": (i32, [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(i64)]),
@@ -316,3 +338,150 @@ class Context:
         _check(lib().spdz_deal_triple(self._h, ctypes.c_uint64(seed), ctypes.c_uint64(array_id),
                                       ctypes.byref(d)), "spdz_deal_triple")
         return out
+
+
+# ---------------------------------------------------------------------------
+# DAG execution
+# ---------------------------------------------------------------------------
+MODE_PER_OP, MODE_PER_LEVEL, MODE_GRAPH = 0, 1, 2
+POLICY_STATIC, POLICY_LEARNED, POLICY_ALL_GPU, POLICY_ALL_CPU = 0, 1, 2, 3
+
+DAG_OP_DTYPE = None
+
+
+def dag_op_dtype():
+    import numpy as np
+    global DAG_OP_DTYPE
+    if DAG_OP_DTYPE is None:
+        DAG_OP_DTYPE = np.dtype([("kind", np.int32), ("level", np.int32), ("width", np.int64),
+                                 ("src1", np.int64), ("off1", np.int64), ("src2", np.int64),
+                                 ("off2", np.int64), ("konst", np.uint64)])
+    return DAG_OP_DTYPE
+
+
+class Dag:
+    """A spdz_dag built from an op table (numpy array of dag_op_dtype())."""
+
+    def __init__(self, ctx: Context, input_widths, ops):
+        import numpy as np
+        self.ctx = ctx
+        ops = np.ascontiguousarray(ops, dtype=dag_op_dtype())
+        self._ops = ops
+        iw = (ctypes.c_int64 * len(input_widths))(*input_widths)
+        h = ctypes.c_void_p()
+        _check(lib().spdz_dag_create(ctx._h, len(input_widths), iw, len(ops), ops.ctypes.data_as(ctypes.c_void_p),
+                                     ctypes.byref(h)), "spdz_dag_create")
+        self._h = h
+        self.n_inputs = len(input_widths)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().spdz_dag_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def opened_count(self) -> int:
+        return int(lib().spdz_dag_opened_count(self._h))
+
+    def deal(self, seed: int, input_array0: int, triple_array0: int):
+        _check(lib().spdz_dag_deal(self._h, ctypes.c_uint64(seed), ctypes.c_uint64(input_array0),
+                                   ctypes.c_uint64(triple_array0)), "spdz_dag_deal")
+
+    def run(self, mode: int = MODE_PER_LEVEL, policy: int = POLICY_ALL_GPU) -> float:
+        ms = ctypes.c_double(0)
+        _check(lib().spdz_dag_run(self._h, mode, policy, ctypes.byref(ms)), "spdz_dag_run")
+        return ms.value
+
+    def fetch_host_outputs(self):
+        _check(lib().spdz_dag_fetch_host_outputs(self._h), "spdz_dag_fetch_host_outputs")
+
+    def node(self, k: int) -> ShareTensor:
+        """Copy of node k's shares into fresh tensors [n][1][width]."""
+        d = Shares()
+        _check(lib().spdz_dag_node(self._h, k, ctypes.byref(d)), "spdz_dag_node")
+        n = self.ctx.n
+        out = ShareTensor.empty(n, 1, d.len)
+        st = ctypes.c_void_p(self.ctx.stream.cuda_stream)
+        _check(lib().spdz_copy_probe(ctypes.c_void_p(out.val.data_ptr()), ctypes.c_void_p(d.val), n * d.len, st),
+               "spdz_copy_probe")
+        _check(lib().spdz_copy_probe(ctypes.c_void_p(out.mac.data_ptr()), ctypes.c_void_p(d.mac), n * d.len, st),
+               "spdz_copy_probe")
+        return out
+
+    def set_launch(self, tile: int, blocks_per_cu: int):
+        _check(lib().spdz_dag_set_launch(self._h, tile, blocks_per_cu), "spdz_dag_set_launch")
+
+    def autotune(self, max_levels: int = 20):
+        t, b = ctypes.c_int(0), ctypes.c_int(0)
+        ms = ctypes.c_double(0)
+        _check(lib().spdz_dag_autotune(self._h, max_levels, ctypes.byref(t), ctypes.byref(b), ctypes.byref(ms)),
+               "spdz_dag_autotune")
+        return t.value, b.value, ms.value
+
+    def set_threshold(self, thr: int):
+        _check(lib().spdz_dag_set_threshold(self._h, thr), "spdz_dag_set_threshold")
+
+    def last_stats(self):
+        g, c, cp = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+        pm = ctypes.c_double(0)
+        _check(lib().spdz_dag_last_stats(self._h, ctypes.byref(g), ctypes.byref(c), ctypes.byref(cp),
+                                         ctypes.byref(pm)), "spdz_dag_last_stats")
+        return dict(gpu_ops=g.value, cpu_ops=c.value, copies=cp.value, predict_ms=pm.value)
+
+    def set_cost_model(self, weights, ns_per_byte: float, ns_per_copy: float):
+        import numpy as np
+        w = np.ascontiguousarray(weights, dtype=np.float32)
+        assert w.size == MLP_NPARAM
+        _check(lib().spdz_dag_set_cost_model(self._h, w.ctypes.data_as(ctypes.c_void_p), ns_per_byte, ns_per_copy),
+               "spdz_dag_set_cost_model")
+
+
+def dag_time_level(ctx: Context, kind: int, width: int, q: int, reps: int = 3):
+    """(gpu ns per op, cpu ns per op, q used) for one level of q ops."""
+    g, c = ctypes.c_double(0), ctypes.c_double(0)
+    qu = ctypes.c_int64(0)
+    _check(lib().spdz_dag_time_level(ctx._h, kind, width, q, reps, ctypes.byref(g), ctypes.byref(c),
+                                     ctypes.byref(qu)), "spdz_dag_time_level")
+    return g.value, c.value, qu.value
+
+
+# ---------------------------------------------------------------------------
+# cost-model MLP (device tensors float32)
+# ---------------------------------------------------------------------------
+MLP_IN, MLP_HID, MLP_OUT, MLP_NPARAM = 7, 64, 2, 8962
+
+
+def _st(stream):
+    return ctypes.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
+
+
+def mlp_forward(W: torch.Tensor, X: torch.Tensor, acts: bool = False, stream=None):
+    B = X.shape[0]
+    Y = torch.empty((B, MLP_OUT), dtype=torch.float32, device="cuda")
+    A = torch.empty((3, B, MLP_HID), dtype=torch.float32, device="cuda") if acts else None
+    _check(lib().spdz_mlp_forward(_st(stream), _ptr(W), _ptr(X), B, _ptr(Y), _ptr(A)), "spdz_mlp_forward")
+    return (Y, A) if acts else Y
+
+
+def mlp_backward(W, X, A, dY, stream=None):
+    dW = torch.empty(MLP_NPARAM, dtype=torch.float32, device="cuda")
+    _check(lib().spdz_mlp_backward(_st(stream), _ptr(W), _ptr(X), _ptr(A), _ptr(dY), X.shape[0], _ptr(dW)),
+           "spdz_mlp_backward")
+    return dW
+
+
+def mlp_adam(W, dW, m, v, t: int, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+    _check(lib().spdz_mlp_adam(_st(stream), _ptr(W), _ptr(dW), _ptr(m), _ptr(v), t, lr, b1, b2, eps), "spdz_mlp_adam")
+
+
+def mlp_train(W, X, T, epochs: int, batch: int, lr: float, seed: int, stream=None):
+    import numpy as np
+    loss = np.zeros(epochs, dtype=np.float32)
+    _check(lib().spdz_mlp_train(_st(stream), _ptr(W), _ptr(X), _ptr(T), X.shape[0], epochs, batch, lr,
+                                ctypes.c_uint64(seed), loss.ctypes.data_as(ctypes.c_void_p)), "spdz_mlp_train")
+    return loss

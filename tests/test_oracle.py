@@ -368,3 +368,54 @@ def test_matrix_triple_tier1_closed_form(n):
         for i in range(n):
             assert zv[i, q] == r["Z"].val[i, 0, rr * N + cc]
             assert zm[i, q] == r["Z"].mac[i, 0, rr * N + cc]
+
+
+# --------------------------------------------------------------------------
+# DAG executor of the oracle against plain evaluation
+# --------------------------------------------------------------------------
+
+def plain_eval(dag, in_values):
+    """Plain (unshared) evaluation with Python integers: the value every node must reconstruct to."""
+    p = dag.p
+    vals = [list(map(int, v)) for v in in_values]
+    for k in range(dag.n_ops):
+        w = int(dag.width[k])
+        s1 = vals[int(dag.src1[k])]
+        x = [s1[(int(dag.off1[k]) + j) % len(s1)] for j in range(w)]
+        if dag.kind[k] == 2:
+            c = int(dag.const[k])
+            vals.append([(c * a) % p for a in x])
+            continue
+        s2 = vals[int(dag.src2[k])]
+        y = [s2[(int(dag.off2[k]) + j) % len(s2)] for j in range(w)]
+        if dag.kind[k] == 0:
+            vals.append([(a * b) % p for a, b in zip(x, y)])
+        else:
+            vals.append([(a + b) % p for a, b in zip(x, y)])
+    return vals
+
+def test_dag_structure_and_oracle_executor():
+    from oracle.pipelines import dag_run
+    from workloads import ARR_DAG_IN0
+    from workloads.dag import OP_MUL, make_dag
+    p = P61
+    dag = make_dag(3, p, n_parties=2, depth=6, ops_per_level=12, median=20, sigma=1.0, wmax=300, in_width=50)
+    assert dag.n_ops == 72 and set(np.unique(dag.level)) == set(range(1, 7))
+    # operand 1 of every op comes from the previous level; operand 2 from any earlier level
+    lev = np.concatenate(([0, 0], dag.level))
+    assert (lev[dag.src1] == dag.level - 1).all()
+    has2 = dag.src2 >= 0
+    assert (lev[dag.src2[has2]] < dag.level[has2]).all()
+    out, ok, sigma = dag_run(dag, seed=2, check_seed=2)
+    assert ok
+    f = F.Field(p)
+    ins = [F.from_limbs(f.deal_values(2, ARR_DAG_IN0 + i, dag.in_width)) for i in range(2)]
+    want = plain_eval(dag, ins)
+    al = f.alpha_shares(2, 2)
+    a = sum(int(x) for x in al[:, 0]) % p
+    for node, sh in out.items():
+        v = F.from_limbs(f.open(sh.val))
+        assert v == want[node]
+        m = F.from_limbs(f.open(sh.mac))
+        assert m == [(a * x) % p for x in want[node]]
+    assert dag.n_opened() == 2 * int(dag.width[dag.kind == OP_MUL].sum())

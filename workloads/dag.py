@@ -131,3 +131,23 @@ def triple_array_id(op: int) -> int:
     """Array id of the Beaver triple (a, b, c) consumed by op `op` (+0, +1, +2)."""
     from . import ARR_DAG_TRIPLE0
     return ARR_DAG_TRIPLE0 + 3 * op
+
+
+OP_TABLE_DTYPE = np.dtype([("kind", np.int32), ("level", np.int32), ("width", np.int64),
+                           ("src1", np.int64), ("off1", np.int64), ("src2", np.int64),
+                           ("off2", np.int64), ("konst", np.uint64)])
+
+
+def to_op_table(dag: Dag) -> np.ndarray:
+    """The op table in the C layout of spdz_dag_op (smul operand 2 is unused: src2 = 0)."""
+    t = np.zeros(dag.n_ops, dtype=OP_TABLE_DTYPE)
+    t["kind"] = dag.kind
+    t["level"] = dag.level
+    t["width"] = dag.width
+    t["src1"] = dag.src1
+    t["off1"] = dag.off1
+    t["src2"] = np.where(dag.src2 >= 0, dag.src2, 0)
+    t["off2"] = dag.off2
+    t["konst"] = dag.const
+    return t
+
