@@ -83,6 +83,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 22)
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--suite", choices=["pipeline", "matmul", "dag", "dispatch"], default="pipeline",
+                    help="pipeline: the headline step (default); matmul: matrix triples at N=1024, 4096; "
+                         "dag: the 100k-op layered DAG per op / per level / hipGraph; dispatch: learned vs "
+                         "static CPU-GPU dispatch on 20 held-out DAG seeds")
+    ap.add_argument("--seeds", type=int, default=20, help="held-out DAG seeds of the dispatch suite")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the build simulates all parties on one device "
@@ -92,6 +97,11 @@ def main():
     import torch
     from paper_2512_11112_amd import spdz as S
     from workloads import ARR_A, ARR_X, ARR_Y, P61, P127, SEEDS_TIMING
+
+    if args.suite != "pipeline":
+        fn = {"matmul": suite_matmul, "dag": suite_dag, "dispatch": suite_dispatch}[args.suite]
+        print(json.dumps(fn(args)), flush=True)
+        return
 
     p, n, W, seed = P127, 3, args.width, SEEDS_TIMING[0]
     L = S.n_limbs(p)
@@ -218,6 +228,192 @@ def extras(torch, S):
         del x, y, z, t
         torch.cuda.empty_cache()
     return res
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _median(xs):
+    xs = sorted(xs)
+    return xs[len(xs) // 2]
+
+
+def suite_matmul(args):
+    """Matrix-triple products at 2 parties over 2^61-1: 9 N^3 mod-p multiply-adds per product."""
+    import torch
+    from paper_2512_11112_amd import spdz as S
+    from workloads import ARR_MA, ARR_MX, ARR_MY, P61, SEEDS_TIMING
+    n, p, seed = 2, P61, SEEDS_TIMING[0]
+    res = {}
+    for N in (1024, 4096):
+        ctx = S.Context(n, p, S.deal_alpha(p, n, seed), seed)
+        X, Y, Z = (S.ShareTensor.empty(n, 1, N * N) for _ in range(3))
+        T = S.TripleTensor.empty_matrix(n, N, N, N)
+        ctx.spdz_deal_secret(seed, ARR_MX, X)
+        ctx.spdz_deal_secret(seed, ARR_MY, Y)
+        ctx.spdz_deal_matrix_triple(seed, ARR_MA, N, N, N, T)
+        for variant, name in ((1, "mfma"), (0, "valu")):
+            reps = 5 if not (N == 4096 and variant == 0) else 2
+            ctx.spdz_matmul_triple(N, N, N, X, Y, T, Z, variant=variant)
+            ok, _ = ctx.spdz_mac_check()
+            assert ok
+            torch.cuda.synchronize()
+            ctx.spdz_timing_enable(True)
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                ctx.spdz_matmul_triple(N, N, N, X, Y, T, Z, variant=variant)
+                ok, _ = ctx.spdz_mac_check()
+                assert ok
+                ts.append((time.perf_counter() - t0) * 1e3)
+            kms, kc = ctx.spdz_timing_get("matmul_" + name)
+            ctx.spdz_timing_enable(False)
+            ms = _median(ts)
+            gemm_ms = kms / reps
+            macs = 9 * N ** 3
+            res[f"N{N}_{name}"] = {"step_ms": ms, "gemm_ms": gemm_ms, "modp_mac_per_s": macs / (ms * 1e-3),
+                                   "gemm_modp_mac_per_s": macs / (gemm_ms * 1e-3),
+                                   "int8_tops_equiv": (macs * 64 * 2 / (gemm_ms * 1e-3) / 1e12) if variant == 1 else None}
+            log(f"matmul N={N} {name}: {ms:.2f} ms/step, GEMMs {gemm_ms:.2f} ms")
+        ctx.close()
+        del X, Y, Z, T
+        torch.cuda.empty_cache()
+    best = res["N4096_mfma"]
+    return {"metric": "matrix-triple mod-p multiply-adds per second (2 parties, p=2^61-1, N=4096)",
+            "value": best["modp_mac_per_s"], "unit": "modp_mac/s", "higher_is_better": True, "n_gpus": 1,
+            "dtype": "u64 (int8 digits on MFMA)", "data": "synthetic",
+            "config": {"workload": "matrix_triple_n2_p61_N1024_N4096", "parties": 2, "modulus": "2^61-1"},
+            "roofline": {"bound": "mfma", "achieved": best["int8_tops_equiv"], "peak": 5000.0, "unit": "TOPS (int8)",
+                         "frac": best["int8_tops_equiv"] / 5000.0, "traffic": None},
+            "mfma_over_valu_N4096": res["N4096_valu"]["gemm_ms"] / res["N4096_mfma"]["gemm_ms"],
+            "mfma_over_valu_N1024": res["N1024_valu"]["gemm_ms"] / res["N1024_mfma"]["gemm_ms"],
+            "results": res}
+
+
+def dag_alg_bytes(dag):
+    import numpy as np
+    n = dag.n_parties
+    per = np.where(dag.kind == 0, 12 * n * 8, np.where(dag.kind == 1, 6 * n * 8, 4 * n * 8))
+    return int((per * dag.width).sum())
+
+
+def build_dag(S, dag, seed):
+    from workloads import ARR_DAG_IN0, ARR_DAG_TRIPLE0
+    from workloads.dag import to_op_table
+    p, n = dag.p, dag.n_parties
+    ctx = S.Context(n, p, S.deal_alpha(p, n, seed), seed)
+    g = S.Dag(ctx, [dag.in_width, dag.in_width], to_op_table(dag))
+    g.deal(seed, ARR_DAG_IN0, ARR_DAG_TRIPLE0)
+    return ctx, g
+
+
+def timed_run(ctx, g, mode, policy):
+    t0 = time.perf_counter()
+    g.run(mode, policy)
+    ok, _ = ctx.spdz_mac_check()
+    if not ok:
+        raise RuntimeError("MAC check rejected an honest DAG run")
+    return (time.perf_counter() - t0) * 1e3
+
+
+def suite_dag(args):
+    """100k-op layered DAG (depth 200, 60/30/10 % mul/add/smul, lognormal widths), all ops on the GPU."""
+    from paper_2512_11112_amd import spdz as S
+    from workloads import P61, SEEDS_TIMING
+    from workloads.dag import make_dag
+    seed = SEEDS_TIMING[0]
+    dag = make_dag(seed, P61)
+    ctx, g = build_dag(S, dag, seed)
+    tile, bpc, tune_ms = g.autotune(max_levels=20)
+    log(f"autotune: tile {tile}, {bpc} blocks/CU ({tune_ms:.2f} ms for 20 levels)")
+    res = {}
+    for mode, name, reps in ((S.MODE_GRAPH, "graph", 7), (S.MODE_PER_LEVEL, "per_level", 7), (S.MODE_PER_OP, "per_op", 3)):
+        timed_run(ctx, g, mode, S.POLICY_ALL_GPU)
+        ts = [timed_run(ctx, g, mode, S.POLICY_ALL_GPU) for _ in range(reps)]
+        res[name] = _median(ts)
+        log(f"dag {name}: {res[name]:.2f} ms")
+    B = dag_alg_bytes(dag)
+    return {"metric": "end-to-end DAG time incl. MAC-check verdict (100k ops, depth 200, 2 parties, p=2^61-1)",
+            "value": res["graph"], "unit": "ms", "higher_is_better": False, "n_gpus": 1, "dtype": "u64",
+            "data": "synthetic", "config": {"workload": f"dag_100k_depth200_seed{seed}", "parties": 2,
+                                            "modulus": "2^61-1", "elements": dag.total_elements()},
+            "per_mode_ms": res, "speedup_graph_vs_per_op": res["per_op"] / res["graph"],
+            "speedup_graph_vs_per_level": res["per_level"] / res["graph"],
+            "autotune": {"tile": tile, "blocks_per_cu": bpc},
+            "roofline": {"bound": "hbm", "achieved": B / (res["graph"] * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": B / (res["graph"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "alg_bytes": B, "traffic": None}}
+
+
+def suite_dispatch(args):
+    """Learned (MLP cost model) vs static-threshold CPU/GPU dispatch on held-out DAG seeds."""
+    import numpy as np
+    from paper_2512_11112_amd import costmodel as CM
+    from paper_2512_11112_amd import spdz as S
+    from workloads import P61, SEEDS_HELDOUT
+    from workloads.dag import make_dag
+    t0 = time.perf_counter()
+    sw = CM.sweep(progress=log)
+    W, loss = CM.train(sw)
+    pred = CM.predict(W, sw.X)
+    rmse = float(np.sqrt(np.mean((pred - sw.T) ** 2)))
+    npb, npc = CM.transfer_costs()
+    log(f"cost model: {len(sw.rows)} timings, final MSE {loss[-1]:.4f} (log2 ns), transfer {npb:.4f} ns/B + "
+        f"{npc:.0f} ns/copy, {time.perf_counter() - t0:.1f} s")
+    seeds = list(SEEDS_HELDOUT)[:args.seeds]
+    per_seed = []
+    for i, seed in enumerate(seeds):
+        dag = make_dag(seed, P61)
+        ctx, g = build_dag(S, dag, seed)
+        g.set_cost_model(W, npb, npc)
+        g.set_threshold(65535)
+        rec = {"seed": seed}
+        for name, policy, mode in (("static", S.POLICY_STATIC, S.MODE_PER_LEVEL),
+                                   ("learned", S.POLICY_LEARNED, S.MODE_GRAPH)):
+            timed_run(ctx, g, mode, policy)           # warm-up (first touch of host mirrors, graph capture)
+            rec[name + "_ms"] = timed_run(ctx, g, mode, policy)
+            st = g.last_stats()
+            rec[name + "_cpu_ops"] = st["cpu_ops"]
+            if name == "learned":
+                rec["predict_ms"] = st["predict_ms"]
+            if i == 0:   # outputs must not depend on the policy
+                g.fetch_host_outputs()
+                rec.setdefault("_nodes", {})[name] = [S_to_np(g.node(k)) for k in (2, dag.n_ops // 2, dag.n_ops + 1)]
+        if i == 0:
+            a, b = rec.pop("_nodes").values()
+            rec["bit_exact_static_vs_learned"] = all(np.array_equal(x, y) for u, v in zip(a, b) for x, y in zip(u, v))
+        per_seed.append(rec)
+        log(f"seed {seed}: static {rec['static_ms']:.1f} ms ({rec['static_cpu_ops']} CPU ops), "
+            f"learned {rec['learned_ms']:.1f} ms ({rec['learned_cpu_ops']} CPU ops)")
+        g.close()
+        ctx.close()
+    # best single threshold on the first held-out seed
+    dag = make_dag(seeds[0], P61)
+    ctx, g = build_dag(S, dag, seeds[0])
+    sweep_thr = {}
+    for thr in (0, 1 << 8, 1 << 12, 1 << 16, 1 << 20, 1 << 21):
+        g.set_threshold(thr)
+        timed_run(ctx, g, S.MODE_PER_LEVEL, S.POLICY_STATIC)
+        sweep_thr[thr] = timed_run(ctx, g, S.MODE_PER_LEVEL, S.POLICY_STATIC)
+        log(f"threshold {thr}: {sweep_thr[thr]:.1f} ms")
+    best_thr = min(sweep_thr, key=sweep_thr.get)
+    learned = [r["learned_ms"] for r in per_seed]
+    static = [r["static_ms"] for r in per_seed]
+    return {"metric": "end-to-end DAG time, learned vs static dispatch (mean over held-out seeds)",
+            "value": float(np.mean(learned)), "unit": "ms", "higher_is_better": False, "n_gpus": 1,
+            "dtype": "u64 shares, fp32 cost model", "data": "synthetic",
+            "config": {"workload": "dag_100k_depth200_heldout_seeds", "seeds": seeds, "parties": 2},
+            "static_mean_ms": float(np.mean(static)), "speedup_learned_vs_static": float(np.mean(static) / np.mean(learned)),
+            "learned_wins_on_seeds": int(sum(l < s for l, s in zip(learned, static))),
+            "best_static_threshold": best_thr, "best_static_threshold_ms": sweep_thr[best_thr],
+            "threshold_sweep_ms": sweep_thr, "cost_model": {"timings": len(sw.rows), "final_mse_log2ns": float(loss[-1]),
+                                                              "rmse_log2ns": rmse, "ns_per_byte": npb, "ns_per_copy": npc},
+            "per_seed": per_seed}
+
+
+def S_to_np(t):
+    return (t.val.cpu().numpy(), t.mac.cpu().numpy())
 
 
 if __name__ == "__main__":

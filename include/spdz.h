@@ -294,7 +294,9 @@ spdz_status spdz_mlp_train(void *hip_stream, float *W, const float *X, const flo
 
 /* Use W (HOST, SPDZ_MLP_NPARAM floats) for SPDZ_POLICY_LEARNED: an op runs on
  * the CPU iff 2^cpu + xfer < 2^gpu, where xfer = ns_per_byte * (bytes the op
- * would move between host and device) + ns_per_copy * (copies). */
+ * would move between host and device) + ns_per_copy * (copies).  The first
+ * learned run evaluates the model for every op in one batched GPU launch; the
+ * decisions are kept until the model changes. */
 spdz_status spdz_dag_set_cost_model(spdz_dag *dag, const float *W, double ns_per_byte, double ns_per_copy);
 
 /* Measure one level of q ops of `kind` and `width` (q clipped so the level

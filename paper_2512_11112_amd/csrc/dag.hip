@@ -204,6 +204,7 @@ struct spdz_dag {
   std::vector<float> cost_model;  // MLP weights (learned policy)
   float *d_model = nullptr, *d_feat = nullptr, *d_pred = nullptr;
   double ns_per_byte = 0.0, ns_per_copy = 0.0;
+  std::vector<uint8_t> learned_on_gpu;  // decisions of the current model (they depend only on the ops and the model)
   double last_predict_ms = 0.0;
   // host mirrors for the CPU back end (pinned), residency per node: bit 0 device, bit 1 host
   u64 *h_nval = nullptr, *h_nmac = nullptr, *h_tval = nullptr, *h_tmac = nullptr;
@@ -982,6 +983,11 @@ static void op_features(const spdz_dag *g, int64_t k, float *f) {
 spdz_status dag_decide_learned(spdz_dag *g, std::vector<uint8_t> &on_gpu) {
   if (g->cost_model.empty()) return SPDZ_E_INVAL;
   const auto t0 = std::chrono::steady_clock::now();
+  if ((int64_t)g->learned_on_gpu.size() == g->n_ops) {
+    on_gpu = g->learned_on_gpu;
+    g->last_predict_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return SPDZ_OK;
+  }
   const int64_t B = g->n_ops;
   if (B == 0) return SPDZ_OK;
   if (!g->d_feat) {
@@ -1010,6 +1016,7 @@ spdz_status dag_decide_learned(spdz_dag *g, std::vector<uint8_t> &on_gpu) {
     const double xfer = g->ns_per_byte * 8 * words + g->ns_per_copy * copies;
     on_gpu[k] = !(cpu + xfer < gpu);
   }
+  g->learned_on_gpu = on_gpu;
   g->last_predict_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return SPDZ_OK;
 }
@@ -1023,6 +1030,7 @@ spdz_status spdz_dag_set_cost_model(spdz_dag *g, const float *W, double ns_per_b
   SPDZ_RET(ensure_stream(g));
   if (!g->d_model && hipMalloc((void **)&g->d_model, SPDZ_MLP_NPARAM * sizeof(float)) != hipSuccess) return SPDZ_E_NOMEM;
   g->cost_model.assign(W, W + SPDZ_MLP_NPARAM);
+  g->learned_on_gpu.clear();
   g->ns_per_byte = ns_per_byte;
   g->ns_per_copy = ns_per_copy;
   SPDZ_RET(hip_status(hipMemcpyAsync(g->d_model, g->cost_model.data(), SPDZ_MLP_NPARAM * sizeof(float),

@@ -419,3 +419,74 @@ def test_dag_structure_and_oracle_executor():
         m = F.from_limbs(f.open(sh.mac))
         assert m == [(a * x) % p for x in want[node]]
     assert dag.n_opened() == 2 * int(dag.width[dag.kind == OP_MUL].sum())
+
+
+# --------------------------------------------------------------------------
+# cost-model MLP reference (float64)
+# --------------------------------------------------------------------------
+def _torch_mlp(W):
+    import torch
+    layers = []
+    from oracle.mlp_ref import unpack
+    for li, (w, b) in enumerate(unpack(W)):
+        lin = torch.nn.Linear(w.shape[1], w.shape[0]).double()
+        with torch.no_grad():
+            lin.weight.copy_(torch.from_numpy(w))
+            lin.bias.copy_(torch.from_numpy(b))
+        layers.append(lin)
+        if li < 3:
+            layers.append(torch.nn.ReLU())
+    return torch.nn.Sequential(*layers)
+
+
+def test_mlp_reference_against_torch_autograd():
+    import torch
+    from oracle import mlp_ref as M
+    rng = np.random.default_rng(3)
+    W = M.init(1).astype(np.float64) + 0.01 * rng.standard_normal(M.NPARAM)
+    X = rng.standard_normal((33, 7))
+    dY = rng.standard_normal((33, 2))
+    Y, acts = M.forward(W, X)
+    net = _torch_mlp(W)
+    Xt = torch.from_numpy(X)
+    Yt = net(Xt)
+    assert np.allclose(Y, Yt.detach().numpy(), rtol=1e-12, atol=1e-12)
+    (Yt * torch.from_numpy(dY)).sum().backward()
+    g_torch = np.concatenate([np.concatenate([l.weight.grad.numpy().ravel(), l.bias.grad.numpy()])
+                              for l in net if isinstance(l, torch.nn.Linear)])
+    assert np.allclose(M.backward(W, X, acts, dY), g_torch, rtol=1e-10, atol=1e-10)
+
+
+def test_mlp_reference_finite_differences():
+    from oracle import mlp_ref as M
+    rng = np.random.default_rng(4)
+    W = M.init(2).astype(np.float64)
+    X = rng.standard_normal((9, 7))
+    dY = rng.standard_normal((9, 2))
+    _, acts = M.forward(W, X)
+    g = M.backward(W, X, acts, dY)
+    f = lambda w: float((M.forward(w, X)[0] * dY).sum())
+    idx = rng.choice(M.NPARAM, 60, replace=False)
+    h = 1e-6
+    for i in idx:
+        e = np.zeros(M.NPARAM)
+        e[i] = h
+        fd = (f(W + e) - f(W - e)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, g[i])
+
+
+def test_mlp_adam_against_torch():
+    import torch
+    from oracle import mlp_ref as M
+    rng = np.random.default_rng(5)
+    W = rng.standard_normal(50)
+    p = torch.nn.Parameter(torch.from_numpy(W.copy()))
+    opt = torch.optim.Adam([p], lr=1e-3, betas=(0.9, 0.999), eps=1e-8)
+    m = np.zeros(50)
+    v = np.zeros(50)
+    for t in range(1, 6):
+        g = rng.standard_normal(50)
+        p.grad = torch.from_numpy(g.copy())
+        opt.step()
+        W, m, v = M.adam(W, g, m, v, t)
+    assert np.allclose(W, p.detach().numpy(), rtol=1e-12, atol=1e-12)
