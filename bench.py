@@ -36,7 +36,7 @@ def beaver_bytes_per_elem(n: int, L: int) -> int:
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "beaver_fused_n3_p127_w16777216_traffic.md")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2512_11112_amd", "csrc", f) for f in ("elementwise.hip", "field.h")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2512_11112_amd", "csrc", f) for f in ("beaver.h", "coef.h", "blockred.h", "field.h", "field127r.h")]
 
 
 def kernel_source_hash() -> str:

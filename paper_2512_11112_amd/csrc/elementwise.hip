@@ -2,6 +2,8 @@
 // and fused with a linear op, an open and a ReduceAdd), linear combination,
 // ReduceAdd, the MAC-check finalisation, and the device dealer.
 //
+// (The Beaver product kernel is in beaver.h.)
+//
 // Layout: structure-of-arrays, limb-planar shares (see spdz.h).  Every kernel
 // is a grid-stride loop over elements with one element per thread per
 // iteration, all parties of that element handled by the same thread; the
@@ -17,59 +19,9 @@
 #include <unordered_map>
 
 #include "blockred.h"
-#include "ctx.h"
+#include "coef.h"
 
 namespace spdz {
-
-// --------------------------------------------------------------------------
-// public coefficients: the product is specialised per launch when the
-// coefficient is 0, 1, below 2^32, or p minus a value below 2^32 (the kind is
-// uniform across the grid, so the switch does not diverge)
-// --------------------------------------------------------------------------
-enum CoefKind : int { CK_ZERO = 0, CK_ONE = 1, CK_SMALL = 2, CK_NEGSMALL = 3, CK_GENERAL = 4 };
-
-template <class F>
-struct Coef {
-  typename F::E c;
-  u32 m;
-  int kind;
-};
-
-template <class F>
-Coef<F> classify(typename F::E c) {
-  Coef<F> k{c, 0, CK_GENERAL};
-  u64 w[F::L], nw[F::L];
-  F::to_words(c, w);
-  F::to_words(F::neg(c), nw);
-  bool small = w[0] < (1ull << 32), nsmall = nw[0] < (1ull << 32);
-  for (int l = 1; l < F::L; l++) {
-    small = small && w[l] == 0;
-    nsmall = nsmall && nw[l] == 0;
-  }
-  if (F::is_zero(c)) {
-    k.kind = CK_ZERO;
-  } else if (small && w[0] == 1) {
-    k.kind = CK_ONE;
-  } else if (small) {
-    k.kind = CK_SMALL;
-    k.m = (u32)w[0];
-  } else if (nsmall) {
-    k.kind = CK_NEGSMALL;
-    k.m = (u32)nw[0];
-  }
-  return k;
-}
-
-template <class F>
-__device__ __forceinline__ typename F::E cmul(const Coef<F> &k, typename F::E a) {
-  switch (k.kind) {
-    case CK_ZERO: return F::zero();
-    case CK_ONE: return a;
-    case CK_SMALL: return F::mul_small(a, k.m);
-    case CK_NEGSMALL: return F::neg(F::mul_small(a, k.m));
-    default: return F::mul(k.c, a);
-  }
-}
 
 // --------------------------------------------------------------------------
 // open
@@ -111,126 +63,6 @@ __global__ __launch_bounds__(BLOCK) void k_open(const OpenArgs<F, N> a) {
     for (int i = 0; i < N; i++) mc[1 + i] = F::add(mc[1 + i], F::mul(r, m[i]));
   }
   block_add_to_slot<F, N + 1>(mc, a.acc + (size_t)blockIdx.x * (N + 1) * F::L);
-}
-
-// --------------------------------------------------------------------------
-// Beaver product, optionally fused with w = lin0 z + lin1 x + lin2 y + lin3,
-// open(w) and ReduceAdd(z)
-// --------------------------------------------------------------------------
-template <class F, int N>
-struct BeaverArgs {
-  SV x, y, a, b, c, z;
-  u64 *d_pub, *e_pub;
-  int64_t W;
-  typename F::E alpha[N];
-  u64 coef_state;
-  int64_t j0;  // log index of d_0; e_0 is at j0 + W, w_0 at j0 + 2 W
-  u64 *acc;
-  // fused part
-  Coef<F> lin[3];
-  typename F::E lin3;       // public constant of w (added by party 0)
-  typename F::E alin3[N];   // alpha_i * lin3
-  SV w;
-  u64 *w_pub;
-  u64 *red;
-};
-
-template <class F, int N, bool FUSED>
-__global__ __launch_bounds__(BLOCK) void k_beaver(const BeaverArgs<F, N> A) {
-  using E = typename F::E;
-  using Wd = typename F::Wide;
-  E mc[N + 1];  // MAC-check partials: [0] = sum r a, [1 + i] = sum r gamma_i
-#pragma unroll
-  for (int k = 0; k <= N; k++) mc[k] = F::zero();
-  E rs[FUSED ? 2 * N : 1];  // ReduceAdd partials of z: values then MACs
-#pragma unroll
-  for (int k = 0; k < (FUSED ? 2 * N : 1); k++) rs[k] = F::zero();
-  const bool do_w = FUSED && A.w.val != nullptr;
-  const bool open_w = do_w && A.w_pub != nullptr;
-
-  for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < A.W; e += (int64_t)gridDim.x * BLOCK) {
-    // phase A: value shares -> opened d, e (every input word is loaded once)
-    E xv[N], yv[N], av[N], bv[N];
-#pragma unroll
-    for (int i = 0; i < N; i++) {
-      xv[i] = F::load(A.x.val + i * A.x.ps, A.x.ls, e);
-      av[i] = F::load(A.a.val + i * A.a.ps, A.a.ls, e);
-      yv[i] = F::load(A.y.val + i * A.y.ps, A.y.ls, e);
-      bv[i] = F::load(A.b.val + i * A.b.ps, A.b.ls, e);
-    }
-    E d = F::zero(), ee = F::zero();
-#pragma unroll
-    for (int i = 0; i < N; i++) {
-      d = F::add(d, F::sub(xv[i], av[i]));
-      ee = F::add(ee, F::sub(yv[i], bv[i]));
-    }
-    const E de = F::mul(d, ee);
-    // coefficients of the MAC check: d at log index j0 + e, e at j0 + W + e, w at j0 + 2W + e
-    const E rd = uniform_elem<F>(A.coef_state, (u64)(A.j0 + e));
-    const E re = uniform_elem<F>(A.coef_state, (u64)(A.j0 + A.W + e));
-    E rw = F::zero();
-    if (open_w) rw = uniform_elem<F>(A.coef_state, (u64)(A.j0 + 2 * A.W + e));
-    E wsum = F::zero();
-
-    // phase B: per party, MAC shares and c; recombine, linear op, MAC-check terms
-#pragma unroll
-    for (int i = 0; i < N; i++) {
-      const E xm = F::load(A.x.mac + i * A.x.ps, A.x.ls, e);
-      const E ym = F::load(A.y.mac + i * A.y.ps, A.y.ls, e);
-      const E am = F::load(A.a.mac + i * A.a.ps, A.a.ls, e);
-      const E bm = F::load(A.b.mac + i * A.b.ps, A.b.ls, e);
-      const E cv = F::load(A.c.val + i * A.c.ps, A.c.ls, e);
-      const E cm = F::load(A.c.mac + i * A.c.ps, A.c.ls, e);
-      Wd t = F::wzero();
-      F::wadd(t, cv);
-      F::wmac(t, d, bv[i]);
-      F::wmac(t, ee, av[i]);
-      if (i == 0) F::wadd(t, de);
-      const E zv = F::wreduce(t);
-      t = F::wzero();
-      F::wadd(t, cm);
-      F::wmac(t, d, bm);
-      F::wmac(t, ee, am);
-      F::wmac(t, A.alpha[i], de);
-      const E zm = F::wreduce(t);
-      F::store(A.z.val + i * A.z.ps, A.z.ls, e, zv);
-      F::store(A.z.mac + i * A.z.ps, A.z.ls, e, zm);
-      Wd g = F::wzero();  // r_d gamma_i(d) + r_e gamma_i(e) [+ r_w gamma_i(w)]
-      F::wmac(g, rd, F::sub(xm, am));
-      F::wmac(g, re, F::sub(ym, bm));
-      if constexpr (FUSED) {
-        if (do_w) {
-          E wv = F::add(F::add(cmul<F>(A.lin[0], zv), cmul<F>(A.lin[1], xv[i])), cmul<F>(A.lin[2], yv[i]));
-          if (i == 0) wv = F::add(wv, A.lin3);
-          const E wm =
-              F::add(F::add(F::add(cmul<F>(A.lin[0], zm), cmul<F>(A.lin[1], xm)), cmul<F>(A.lin[2], ym)), A.alin3[i]);
-          F::store(A.w.val + i * A.w.ps, A.w.ls, e, wv);
-          F::store(A.w.mac + i * A.w.ps, A.w.ls, e, wm);
-          wsum = F::add(wsum, wv);
-          if (open_w) F::wmac(g, rw, wm);
-        }
-        if (A.red) {
-          rs[i] = F::add(rs[i], zv);
-          rs[N + i] = F::add(rs[N + i], zm);
-        }
-      }
-      mc[1 + i] = F::add(mc[1 + i], F::wreduce(g));
-    }
-    if (A.d_pub) F::store(A.d_pub, A.W, e, d);
-    if (A.e_pub) F::store(A.e_pub, A.W, e, ee);
-    Wd ga = F::wzero();
-    F::wmac(ga, rd, d);
-    F::wmac(ga, re, ee);
-    if (open_w) {
-      F::store(A.w_pub, A.W, e, wsum);
-      F::wmac(ga, rw, wsum);
-    }
-    mc[0] = F::add(mc[0], F::wreduce(ga));
-  }
-  block_add_to_slot<F, N + 1>(mc, A.acc + (size_t)blockIdx.x * (N + 1) * F::L);
-  if constexpr (FUSED) {
-    if (A.red) block_add_to_slot<F, 2 * N>(rs, A.red + (size_t)blockIdx.x * 2 * N * F::L);
-  }
 }
 
 // --------------------------------------------------------------------------
@@ -437,8 +269,6 @@ __global__ __launch_bounds__(BLOCK) void k_copy(const u64 *__restrict__ src, u64
 // ==========================================================================
 // host launchers
 // ==========================================================================
-namespace {
-
 int occupancy_blocks(const void *kernel) {
   static std::unordered_map<const void *, int> cache;
   auto it = cache.find(kernel);
@@ -460,14 +290,11 @@ int grid_for(const spdz_ctx *c, const void *kernel, int64_t W) {
   return (int)g;
 }
 
+namespace {
+
 template <class F>
 typename F::E elem_of(const u64 *w) {
   return F::from_words(w);
-}
-
-template <class F, int N>
-void alpha_of(const spdz_ctx *c, typename F::E (&out)[N]) {
-  for (int i = 0; i < N; i++) out[i] = F::from_words(c->alpha[i]);
 }
 
 template <class F, int N>
@@ -544,55 +371,16 @@ spdz_status launch_open_diff(spdz_ctx *c, const spdz_shares *x, const spdz_share
   });
 }
 
+template <class F>
+spdz_status launch_beaver_field(spdz_ctx *c, const spdz_shares *x, const spdz_shares *y, const spdz_triple *t,
+                                spdz_shares *z, u64 *d_pub, u64 *e_pub, const u64 *lin, spdz_shares *w, u64 *w_pub,
+                                spdz_shares *s);
+
 spdz_status launch_beaver(spdz_ctx *c, const spdz_shares *x, const spdz_shares *y, const spdz_triple *t,
                           spdz_shares *z, u64 *d_pub, u64 *e_pub, const u64 *lin, spdz_shares *w, u64 *w_pub,
                           spdz_shares *s) {
-  const bool fused = (w != nullptr) || (s != nullptr);
-  return visit(c, [&](auto f, auto nn) -> spdz_status {
-    using F = decltype(f);
-    constexpr int N = decltype(nn)::value;
-    BeaverArgs<F, N> A;
-    A.x = sv_of(x);
-    A.y = sv_of(y);
-    A.a = sv_of(&t->a);
-    A.b = sv_of(&t->b);
-    A.c = sv_of(&t->c);
-    A.z = sv_of(z);
-    A.d_pub = d_pub;
-    A.e_pub = e_pub;
-    A.W = x->len;
-    alpha_of<F, N>(c, A.alpha);
-    A.coef_state = coef_state(c);
-    A.j0 = c->log_count;
-    A.acc = c->d_acc;
-    for (int k = 0; k < 3; k++) A.lin[k] = classify<F>(lin ? F::from_words(lin + k * F::L) : F::zero());
-    A.lin3 = lin ? F::from_words(lin + 3 * F::L) : F::zero();
-    for (int i = 0; i < N; i++) A.alin3[i] = F::mul(A.alpha[i], A.lin3);
-    A.w = w ? sv_of(w) : SV{nullptr, nullptr, 0, 0};
-    A.w_pub = w ? w_pub : nullptr;
-    A.red = s ? c->d_red : nullptr;
-    int g;
-    if (fused) {
-      const void *k = (const void *)k_beaver<F, N, true>;
-      g = grid_for(c, k, A.W);
-      KTimer tm(c, "beaver_fused");
-      hipLaunchKernelGGL((k_beaver<F, N, true>), dim3(g), dim3(BLOCK), 0, c->stream, A);
-    } else {
-      const void *k = (const void *)k_beaver<F, N, false>;
-      g = grid_for(c, k, A.W);
-      KTimer tm(c, "beaver");
-      hipLaunchKernelGGL((k_beaver<F, N, false>), dim3(g), dim3(BLOCK), 0, c->stream, A);
-    }
-    spdz_status st = hip_status(hipGetLastError());
-    if (st != SPDZ_OK) return st;
-    c->log_count += 2 * A.W + (A.w_pub ? A.W : 0);
-    if (g > c->slots) c->slots = g;
-    if (s) {
-      hipLaunchKernelGGL((k_reduce_finalize<F, N>), dim3(1), dim3(BLOCK), 0, c->stream, c->d_red, g, sv_of(s));
-      st = hip_status(hipGetLastError());
-    }
-    return st;
-  });
+  return c->L == 1 ? launch_beaver_field<F61>(c, x, y, t, z, d_pub, e_pub, lin, w, w_pub, s)
+                   : launch_beaver_field<F127>(c, x, y, t, z, d_pub, e_pub, lin, w, w_pub, s);
 }
 
 spdz_status launch_linear(spdz_ctx *c, int nt, const spdz_shares *terms, const u64 *coeffs, const u64 *c0,
@@ -629,7 +417,15 @@ spdz_status launch_reduce(spdz_ctx *c, const spdz_shares *x, spdz_shares *out) {
     hipLaunchKernelGGL((k_reduce<F, N>), dim3(g), dim3(BLOCK), 0, c->stream, sv_of(x), x->len, c->d_red);
     spdz_status st = hip_status(hipGetLastError());
     if (st != SPDZ_OK) return st;
-    hipLaunchKernelGGL((k_reduce_finalize<F, N>), dim3(1), dim3(BLOCK), 0, c->stream, c->d_red, g, sv_of(out));
+    return launch_reduce_finalize(c, g, out);
+  });
+}
+
+spdz_status launch_reduce_finalize(spdz_ctx *c, int grid, spdz_shares *out) {
+  return visit(c, [&](auto f, auto nn) -> spdz_status {
+    using F = decltype(f);
+    constexpr int N = decltype(nn)::value;
+    hipLaunchKernelGGL((k_reduce_finalize<F, N>), dim3(1), dim3(BLOCK), 0, c->stream, c->d_red, grid, sv_of(out));
     return hip_status(hipGetLastError());
   });
 }

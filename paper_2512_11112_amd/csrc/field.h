@@ -29,6 +29,22 @@ typedef unsigned __int128 u128;
 
 #define SPDZ_HD __host__ __device__ __forceinline__
 
+// 32-bit offset addressing: base + zero-extended 32-bit byte offset.  With a
+// wave-uniform base this is the global "saddr" form (64-bit base in scalar
+// registers, 32-bit offset per lane), so an access costs no 64-bit address
+// arithmetic.  The empty asm makes the offset opaque so that the compiler keeps
+// the zero-extension visible to instruction selection.
+__device__ __forceinline__ u32 opaque_offset(u32 off) {
+  asm volatile("" : "+v"(off));
+  return off;
+}
+__device__ __forceinline__ u64 off_load(const u64 *base, u32 boff) {
+  return __builtin_nontemporal_load((const u64 *)((const char *)base + boff));
+}
+__device__ __forceinline__ void off_store(u64 *base, u32 boff, u64 v) {
+  __builtin_nontemporal_store(v, (u64 *)((char *)base + boff));
+}
+
 struct F61 {
   static constexpr int L = 1;
   static constexpr int BITS = 61;
@@ -48,6 +64,11 @@ struct F61 {
   SPDZ_HD static E sub(E a, E b) { return add(a, neg(b)); }
   SPDZ_HD static E canon(E a) { return {(a.v + ((a.v + 1) >> 61)) & P}; }
   SPDZ_HD static bool is_zero(E a) { return canon(a).v == 0; }
+  // lazy forms of the register format interface (already cheap here)
+  SPDZ_HD static E add_lazy(E a, E b) { return add(a, b); }
+  SPDZ_HD static E sub_lazy(E a, E b) { return sub(a, b); }
+  SPDZ_HD static E neg_lazy(E a) { return neg(a); }
+  SPDZ_HD static E norm(E a) { return a; }
   // any x < 2^128 -> <= p
   SPDZ_HD static E reduce(u128 x) {
     u128 t = (x & P) + (x >> 61);          // < 2^68
@@ -78,6 +99,9 @@ struct F61 {
   __device__ __forceinline__ static void store(u64 *base, int64_t /*limb_stride*/, int64_t idx, E x) {
     __builtin_nontemporal_store(canon(x).v, base + idx);
   }
+  // 32-bit offset forms: off[k] is the byte offset of limb k
+  __device__ __forceinline__ static E oload(const u64 *base, const u32 *off) { return {off_load(base, off[0])}; }
+  __device__ __forceinline__ static void ostore(u64 *base, const u32 *off, E x) { off_store(base, off[0], canon(x).v); }
   SPDZ_HD static E from_words(const u64 *w) { return {w[0]}; }
   SPDZ_HD static void to_words(E x, u64 *w) { w[0] = canon(x).v; }
 
@@ -178,6 +202,14 @@ struct F127 {
     E c = canon(x);
     __builtin_nontemporal_store(c.lo, base + idx);
     __builtin_nontemporal_store(c.hi, base + limb_stride + idx);
+  }
+  __device__ __forceinline__ static E oload(const u64 *base, const u32 *off) {
+    return {off_load(base, off[0]), off_load(base, off[1])};
+  }
+  __device__ __forceinline__ static void ostore(u64 *base, const u32 *off, E x) {
+    E c = canon(x);
+    off_store(base, off[0], c.lo);
+    off_store(base, off[1], c.hi);
   }
   SPDZ_HD static E from_words(const u64 *w) { return {w[0], w[1]}; }
   SPDZ_HD static void to_words(E x, u64 *w) {

@@ -187,59 +187,84 @@ __device__ __forceinline__ u64 rot61(u64 x, int t) {
 __global__ __launch_bounds__(256, 1) void k_gemm_mfma(const GemmArgs A) {
   const GemmJob &J = A.job[blockIdx.z];
   const int64_t r0 = (int64_t)blockIdx.y * TILE, c0 = (int64_t)blockIdx.x * TILE;
-  __shared__ __attribute__((aligned(16))) int8_t As[NDIG][TILE][LDS_ROW];
-  __shared__ __attribute__((aligned(16))) int8_t Bs[NDIG][TILE][LDS_ROW];
+  // two LDS stages: step s is staged in buffer s & 1 while step s + 1 is in flight from HBM
+  __shared__ __attribute__((aligned(16))) int8_t As[2][NDIG][TILE][LDS_ROW];
+  __shared__ __attribute__((aligned(16))) int8_t Bs[2][NDIG][TILE][LDS_ROW];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   v16i acc[2 * NDIG - 1];
 #pragma unroll
   for (int s = 0; s < 2 * NDIG - 1; s++) acc[s] = (v16i){0};
   const int64_t Mp = A.Mp, Np = A.Np, Kp = A.Kp;
-  for (int pr = 0; pr < J.npairs; pr++) {
-    const int8_t *Lp = (const int8_t *)J.L[pr];
-    const int8_t *Rp = (const int8_t *)J.R[pr];
-    for (int64_t k0 = 0; k0 < Kp; k0 += MFMA_K) {
-      // stage 8 planes x 64 rows x 32 bytes of each operand: 1024 16-byte chunks each
+  const int64_t ksteps = Kp / MFMA_K, nsteps = J.npairs * ksteps;
+  // this thread's four 16-byte chunks of each operand tile (plane d, row, half): offsets
+  // into the digit planes at k = 0 and into one LDS stage
+  int64_t goa[4], gob[4];
+  int lo[4];
 #pragma unroll
-      for (int q = 0; q < 4; q++) {
-        const int idx = t + q * 256;
-        const int d = idx >> 7, rem = idx & 127, row = rem >> 1, half = rem & 1;
-        const v4i va = *reinterpret_cast<const v4i *>(Lp + ((int64_t)d * Mp + r0 + row) * Kp + k0 + half * 16);
-        const v4i vb = *reinterpret_cast<const v4i *>(Rp + ((int64_t)d * Np + c0 + row) * Kp + k0 + half * 16);
-        *reinterpret_cast<v4i *>(&As[d][row][half * 16]) = va;
-        *reinterpret_cast<v4i *>(&Bs[d][row][half * 16]) = vb;
-      }
-      __syncthreads();
-      v4i a[NDIG], b[NDIG];
-      const int kg = (lane >> 5) * 16;
+  for (int q = 0; q < 4; q++) {
+    const int idx = t + q * 256;
+    const int d = idx >> 7, row = (idx & 127) >> 1, half = idx & 1;
+    goa[q] = ((int64_t)d * Mp + r0 + row) * Kp + half * 16;
+    gob[q] = ((int64_t)d * Np + c0 + row) * Kp + half * 16;
+    lo[q] = (d * TILE + row) * LDS_ROW + half * 16;
+  }
+  auto fetch = [&](int64_t step, v4i (&ra)[4], v4i (&rb)[4]) {
+    const int pr = (int)(step / ksteps);
+    const int64_t k0 = (step % ksteps) * MFMA_K;
+    const int8_t *Lp = (const int8_t *)J.L[pr] + k0;
+    const int8_t *Rp = (const int8_t *)J.R[pr] + k0;
 #pragma unroll
-      for (int d = 0; d < NDIG; d++) {
-        a[d] = *reinterpret_cast<const v4i *>(&As[d][wr * 32 + (lane & 31)][kg]);
-        b[d] = *reinterpret_cast<const v4i *>(&Bs[d][wc * 32 + (lane & 31)][kg]);
-      }
+    for (int q = 0; q < 4; q++) {
+      ra[q] = *reinterpret_cast<const v4i *>(Lp + goa[q]);
+      rb[q] = *reinterpret_cast<const v4i *>(Rp + gob[q]);
+    }
+  };
+  v4i ra[4], rb[4];
+  fetch(0, ra, rb);
+  const int kg = (lane >> 5) * 16;
+  const int arow = ((wr * 32 + (lane & 31)) * LDS_ROW) + kg, brow = ((wc * 32 + (lane & 31)) * LDS_ROW) + kg;
+  for (int64_t step = 0; step < nsteps; step++) {
+    const int buf = (int)(step & 1);
+    int8_t *as = &As[buf][0][0][0], *bs = &Bs[buf][0][0][0];
 #pragma unroll
-      for (int dk = 0; dk < NDIG; dk++)
+    for (int q = 0; q < 4; q++) {
+      *reinterpret_cast<v4i *>(as + lo[q]) = ra[q];
+      *reinterpret_cast<v4i *>(bs + lo[q]) = rb[q];
+    }
+    __syncthreads();
+    if (step + 1 < nsteps) fetch(step + 1, ra, rb);  // in flight during this step's MFMAs
+    v4i b[NDIG];
 #pragma unroll
-        for (int dl = 0; dl < NDIG; dl++)
-          acc[dk + dl] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[dk], b[dl], acc[dk + dl], 0, 0, 0);
-      __syncthreads();
+    for (int d = 0; d < NDIG; d++) b[d] = *reinterpret_cast<const v4i *>(bs + d * TILE * LDS_ROW + brow);
+#pragma unroll
+    for (int dk = 0; dk < NDIG; dk++) {
+      const v4i a = *reinterpret_cast<const v4i *>(as + dk * TILE * LDS_ROW + arow);
+#pragma unroll
+      for (int dl = 0; dl < NDIG; dl++)
+        acc[dk + dl] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b[dl], acc[dk + dl], 0, 0, 0);
     }
   }
-  // recombine the shift classes mod p and apply the epilogue
+  // recombine the shift classes mod p (one class at a time, 16 running sums) and apply the epilogue
   const int64_t M = A.M, N = A.N;
+  u64 x[16];
+#pragma unroll
+  for (int r = 0; r < 16; r++) x[r] = 0;
+#pragma unroll
+  for (int s = 0; s < 2 * NDIG - 1; s++) {
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+      const int cs = acc[s][r];
+      const u64 m = cs < 0 ? (u64)((int64_t)cs + (int64_t)F61::P) : (u64)cs;  // |cs| < 2^31
+      x[r] = F61::add(F61::E{x[r]}, F61::E{rot61(m, (8 * s) % 61)}).v;
+    }
+  }
 #pragma unroll
   for (int r = 0; r < 16; r++) {
     const int row = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
     const int col = lane & 31;
     const int64_t gr = r0 + wr * 32 + row, gc = c0 + wc * 32 + col;
-    F61::E x = F61::zero();
-#pragma unroll
-    for (int s = 0; s < 2 * NDIG - 1; s++) {
-      const int cs = acc[s][r];
-      const u64 m = cs < 0 ? (u64)((int64_t)cs + (int64_t)F61::P) : (u64)cs;  // |cs| < 2^31
-      x = F61::add(x, F61::E{rot61(m, (8 * s) % 61)});
-    }
-    if (gr < M && gc < N) J.out[gr * N + gc] = epilogue_add(x.v, J, gr * N + gc);
+    if (gr < M && gc < N) J.out[gr * N + gc] = epilogue_add(x[r], J, gr * N + gc);
   }
 }
 

@@ -175,6 +175,54 @@ def test_fused_general_coefficients():
     check_fused(got, ref)
 
 
+def wide_window(s: F.Shares, gap_words: int):
+    """The same shares in a layout whose party planes lie gap_words apart."""
+    from paper_2512_11112_amd.spdz import ShareTensor
+    n, L, W = s.val.shape
+
+    def place(a):
+        big = torch.zeros((n - 1) * gap_words + L * W, dtype=torch.int64, device="cuda")
+        v = big.as_strided((n, L, W), (gap_words, W, 1))
+        v.copy_(dev(a))
+        return v
+    return ShareTensor(place(s.val), place(s.mac))
+
+
+@pytest.mark.parametrize("p,n,fused", [(P127, 2, True), (P61, 3, False)])
+def test_wide_window_layout(p, n, fused):
+    """x's party planes more than 4 GiB apart: addressing beyond 32-bit offsets."""
+    from paper_2512_11112_amd.spdz import ShareTensor
+    W = 4099
+    print(f"case p-bits={p.bit_length()} n={n} fused={fused}", flush=True)
+    D = deal_elementwise(p, n, W, 9)
+    gap = (1 << 29) + 3  # (n - 1) * gap * 8 bytes >= 4 GiB
+    xw = wide_window(D.x, gap)
+    ctx = make_ctx(D, 9)
+    L = D.f.L
+    z = ShareTensor.empty(n, L, W)
+    dp, ep = ctx.new_public(W), ctx.new_public(W)
+    if fused:
+        ref = pipeline_run(D, check_seed=9)
+        w, s = ShareTensor.empty(n, L, W), ShareTensor.empty(n, L, 1)
+        wp = ctx.new_public(W)
+        ctx.spdz_mul_fused(xw, share_to_dev(D.y), triple_to_dev(D.t), z, dp, ep,
+                           lin=(1, 3, p - 1, 0), w=w, w_pub=wp, s=s)
+        sp = ctx.spdz_open(s)
+        ok, sigma = ctx.spdz_mac_check()
+        got = dict(z=z, w=w, s=s, d=dp, e=ep, wpub=wp, spub=sp, ok=ok, sigma=sigma)
+        check_fused(got, ref)
+    else:
+        ref = beaver_run(D, check_seed=9)
+        ctx.spdz_mul_batch(xw, share_to_dev(D.y), triple_to_dev(D.t), z, dp, ep)
+        ok, sigma = ctx.spdz_mac_check()
+        eq_shares(z, ref["z"], "z")
+        assert np.array_equal(host(dp), ref["d"]) and np.array_equal(host(ep), ref["e"])
+        assert ok == ref["ok"] and sigma == ints_of_sigma(ref["sigma"])
+    assert ok
+    del xw
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("p,n,W", [(P127, 3, 50000), (P61, 2, 50000)])
 def test_tampered_share_is_rejected(p, n, W):
     """Party n-1's value share of one element of x bumped by one: the check must reject."""
