@@ -7,6 +7,16 @@
 
 namespace spdz {
 
+// f(integral_constant<int, I>) for I = 0 .. N-1: each call sees its index as a
+// constant, so per-party arrays stay in registers however large the body is
+template <int I, int N, class Fn>
+__device__ __forceinline__ void static_for(Fn &&f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
 // --------------------------------------------------------------------------
 // Beaver product, optionally fused with w = lin0 z + lin1 x + lin2 y + lin3,
 // open(w) and ReduceAdd(z)
@@ -35,12 +45,19 @@ struct BeaverArgs {
 //   sums of up to N <= 8 lazy differences stay < 2^32 and are normalised before they
 //   multiply; Wide accumulators take at most three products whose operands are
 //   normalised or a single lazy difference (< 2^28.6), i.e. folded columns
-//   < 37 (2 * 2^55.6 + 2^54) < 2^63; running sums are normalised every 16 iterations.
-// OFF32 selects 32-bit offset addressing (every share array with the same
-// party and limb strides, each inside a 4 GiB window of its base); otherwise
-// 64-bit addresses.
-template <class F, int N, bool FUSED, bool OFF32>
+//   < 37 (2 * 2^55.6 + 2^54) < 2^63; w and its MAC are three coefficient products
+//   (limbs < 2^29) plus a normalised constant, < 2^31, normalised before use;
+//   running sums are normalised every 16 iterations.
+// Kernel modes.  BM_GENERIC: 64-bit addresses, linear coefficients dispatched by
+// kind at run time.  BM_SIMPLE and BM_GENERAL: 32-bit offset addressing (every
+// share array with the same party and limb strides, each inside a 4 GiB window
+// of its base) and straight-line coefficient code: every coefficient in
+// {0, +-1, ..., +-4} (a limb-wise multiply and a sign), or full products.
+enum BeaverMode : int { BM_GENERIC = 0, BM_SIMPLE = 1, BM_GENERAL = 2 };
+
+template <class F, int N, bool FUSED, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_beaver(const BeaverArgs<F, N> A) {
+  constexpr bool OFF32 = MODE != BM_GENERIC;
   using AR = Arith<F>;
   using R = typename AR::type;
   using E = typename R::E;
@@ -75,6 +92,11 @@ __global__ __launch_bounds__(BLOCK) void k_beaver(const BeaverArgs<F, N> A) {
       if constexpr (OFF32) R::ostore(plane, off[i], v);
       else R::store(plane + i * s.ps, s.ls, e, v);
     };
+    auto lmul = [&](const Coef<F> &k, E a) -> E {  // public coefficient times a normalised value: limbs < 2^29
+      if constexpr (MODE == BM_SIMPLE) return R::mul_signed_tiny(a, k.tm, k.tsmask);
+      else if constexpr (MODE == BM_GENERAL) return R::mul(AR::in(k.c), a);
+      else return cmul_r<F, R>(k, a);
+    };
     auto st_pub = [&](u64 *pub, E v) {
       if constexpr (OFF32) R::ostore(pub, poff, v);
       else R::store(pub, A.W, e, v);
@@ -98,8 +120,8 @@ __global__ __launch_bounds__(BLOCK) void k_beaver(const BeaverArgs<F, N> A) {
       d = R::norm(d);
       ee = R::norm(ee);
       de = R::mul(d, ee);
-#pragma unroll
-      for (int i = 0; i < N; i++) {
+      static_for<0, N>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
         Wd t = R::wzero();
         R::wadd(t, ld(A.c, A.c.val, i));
         R::wmac(t, d, bv[i]);
@@ -109,16 +131,16 @@ __global__ __launch_bounds__(BLOCK) void k_beaver(const BeaverArgs<F, N> A) {
         st(A.z, A.z.val, i, zv);
         if constexpr (FUSED) {
           if (do_w) {
-            E wv = R::add_lazy(R::add_lazy(cmul_r<F, R>(A.lin[0], zv), cmul_r<F, R>(A.lin[1], xv[i])),
-                               cmul_r<F, R>(A.lin[2], yv[i]));
+            E wv = R::add_lazy(R::add_lazy(lmul(A.lin[0], zv), lmul(A.lin[1], xv[i])),
+                               lmul(A.lin[2], yv[i]));
             if (i == 0) wv = R::add_lazy(wv, AR::in(A.lin3));
             wv = R::norm(wv);
             st(A.w, A.w.val, i, wv);
             wsum = R::add_lazy(wsum, wv);
           }
-          if (A.red) rs[i] = R::add_lazy(rs[i], zv);
+          rs[i] = R::add_lazy(rs[i], zv);  // kept unconditionally; written out only for a ReduceAdd
         }
-      }
+      });
     }
     wsum = R::norm(wsum);
     if (A.d_pub) st_pub(A.d_pub, d);
@@ -139,8 +161,8 @@ __global__ __launch_bounds__(BLOCK) void k_beaver(const BeaverArgs<F, N> A) {
     }
 
     // phase B: per party, MAC shares; recombined MAC, MAC of w, MAC-check terms
-#pragma unroll
-    for (int i = 0; i < N; i++) {
+    static_for<0, N>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
       const E xm = ld(A.x, A.x.mac, i);
       const E ym = ld(A.y, A.y.mac, i);
       const E am = ld(A.a, A.a.mac, i);
@@ -157,17 +179,18 @@ __global__ __launch_bounds__(BLOCK) void k_beaver(const BeaverArgs<F, N> A) {
       R::wmac(g, re, R::sub_lazy(ym, bm));
       if constexpr (FUSED) {
         if (do_w) {
-          E wm = R::add_lazy(R::add_lazy(R::add_lazy(cmul_r<F, R>(A.lin[0], zm), cmul_r<F, R>(A.lin[1], xm)),
-                                         cmul_r<F, R>(A.lin[2], ym)),
+          E wm = R::add_lazy(R::add_lazy(R::add_lazy(lmul(A.lin[0], zm),
+                                                     lmul(A.lin[1], xm)),
+                                         lmul(A.lin[2], ym)),
                              AR::in(A.alin3[i]));
           wm = R::norm(wm);
           st(A.w, A.w.mac, i, wm);
           if (open_w) R::wmac(g, rw, wm);
         }
-        if (A.red) rs[N + i] = R::add_lazy(rs[N + i], zm);
+        rs[N + i] = R::add_lazy(rs[N + i], zm);
       }
       mc[1 + i] = R::add_lazy(mc[1 + i], R::wreduce(g));
-    }
+    });
     if ((++iter & 15) == 0) {  // running sums: at most 16 normalised terms since the last normalisation
 #pragma unroll
       for (int k = 0; k <= N; k++) mc[k] = R::norm(mc[k]);
@@ -236,17 +259,19 @@ spdz_status launch_beaver_field(spdz_ctx *c, const spdz_shares *x, const spdz_sh
     A.ls8 = o32 ? (u32)(x->limb_stride * 8) : 0;
     A.w8 = o32 ? (u32)(A.W * 8) : 0;
     int g;
-    auto go = [&](auto kern, const char *name) {
-      g = grid_for(c, (const void *)kern, A.W);
+    auto go = [&](auto kern, const char *name, int threads, int elems) {
+      g = grid_for(c, (const void *)kern, A.W, threads, elems);
       KTimer tm(c, name);
-      hipLaunchKernelGGL(kern, dim3(g), dim3(BLOCK), 0, c->stream, A);
+      hipLaunchKernelGGL(kern, dim3(g), dim3(threads), 0, c->stream, A);
     };
+    const bool simple = A.lin[0].tiny && A.lin[1].tiny && A.lin[2].tiny;
     if (fused) {
-      if (o32) go(k_beaver<F, N, true, true>, "beaver_fused");
-      else go(k_beaver<F, N, true, false>, "beaver_fused");
+      if (!o32) go(k_beaver<F, N, true, BM_GENERIC>, "beaver_fused", BLOCK, BLOCK);
+      else if (simple) go(k_beaver<F, N, true, BM_SIMPLE>, "beaver_fused", BLOCK, BLOCK);
+      else go(k_beaver<F, N, true, BM_GENERAL>, "beaver_fused", BLOCK, BLOCK);
     } else {
-      if (o32) go(k_beaver<F, N, false, true>, "beaver");
-      else go(k_beaver<F, N, false, false>, "beaver");
+      if (!o32) go(k_beaver<F, N, false, BM_GENERIC>, "beaver", BLOCK, BLOCK);
+      else go(k_beaver<F, N, false, BM_SIMPLE>, "beaver", BLOCK, BLOCK);
     }
     spdz_status st = hip_status(hipGetLastError());
     if (st != SPDZ_OK) return st;

@@ -269,21 +269,20 @@ __global__ __launch_bounds__(BLOCK) void k_copy(const u64 *__restrict__ src, u64
 // ==========================================================================
 // host launchers
 // ==========================================================================
-int occupancy_blocks(const void *kernel) {
+int occupancy_blocks(const void *kernel, int block_threads) {
   static std::unordered_map<const void *, int> cache;
   auto it = cache.find(kernel);
   if (it != cache.end()) return it->second;
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, BLOCK, 0) != hipSuccess || nb < 1) nb = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, block_threads, 0) != hipSuccess || nb < 1) nb = 1;
   cache[kernel] = nb;
   return nb;
 }
 
-// persistent grid: resident capacity of the GPU, no more blocks than work, at most MAX_SLOTS
-int grid_for(const spdz_ctx *c, const void *kernel, int64_t W) {
-  int64_t per_cu = c->grid_mult > 0 ? c->grid_mult : occupancy_blocks(kernel);
+int grid_for(const spdz_ctx *c, const void *kernel, int64_t W, int block_threads, int block_elems) {
+  int64_t per_cu = c->grid_mult > 0 ? c->grid_mult : occupancy_blocks(kernel, block_threads);
   int64_t g = (int64_t)c->num_cus * per_cu;
-  int64_t need = (W + BLOCK - 1) / BLOCK;
+  int64_t need = (W + block_elems - 1) / block_elems;
   if (g > need) g = need;
   if (g > MAX_SLOTS) g = MAX_SLOTS;
   if (g < 1) g = 1;

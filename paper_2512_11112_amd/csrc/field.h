@@ -68,6 +68,12 @@ struct F61 {
   SPDZ_HD static E add_lazy(E a, E b) { return add(a, b); }
   SPDZ_HD static E sub_lazy(E a, E b) { return sub(a, b); }
   SPDZ_HD static E neg_lazy(E a) { return neg(a); }
+  SPDZ_HD static E mul_tiny(E a, u32 m) { return mul_small(a, m); }
+  SPDZ_HD static E neg_tiny(E a, u32 m) { return neg(mul_small(a, m)); }
+  SPDZ_HD static E mul_signed_tiny(E a, u32 m, u32 smask) {
+    const E t = mul_small(a, m);
+    return smask ? neg(t) : t;
+  }
   SPDZ_HD static E norm(E a) { return a; }
   // any x < 2^128 -> <= p
   SPDZ_HD static E reduce(u128 x) {

@@ -94,7 +94,51 @@ struct F127R {
     return r;
   }
   SPDZ_HD static E neg_lazy(E a) { return sub_lazy(zero(), a); }
-  SPDZ_HD static E norm(E a) { return normalize(a.l[0], a.l[1], a.l[2], a.l[3], a.l[4]); }
+  // m a and -m a for 2 <= m <= 4 and a normalised, limb by limb: limbs < 2^29
+  // (the negation subtracts from 8p, whose limbs 8(2^26 - 1), 8(2^23 - 1) exceed m a's)
+  SPDZ_HD static E mul_tiny(E a, u32 m) {
+    E r;
+#pragma unroll
+    for (int k = 0; k < 5; k++) r.l[k] = a.l[k] * m;
+    return r;
+  }
+  SPDZ_HD static E neg_tiny(E a, u32 m) {
+    E r;
+#pragma unroll
+    for (int k = 0; k < 4; k++) r.l[k] = 8u * M26 - a.l[k] * m;
+    r.l[4] = 8u * M23 - a.l[4] * m;
+    return r;
+  }
+  // normalises a lazy value whose limbs are below 2^32 - 2^7, in 32-bit arithmetic
+  // (every carry is below 2^6, so no partial sum leaves 32 bits)
+  SPDZ_HD static E norm(E a) {
+    E r;
+    u32 t = a.l[0];
+    r.l[0] = t & M26;
+    t = a.l[1] + (t >> 26);
+    r.l[1] = t & M26;
+    t = a.l[2] + (t >> 26);
+    r.l[2] = t & M26;
+    t = a.l[3] + (t >> 26);
+    r.l[3] = t & M26;
+    t = a.l[4] + (t >> 26);
+    r.l[4] = t & M23;
+    t = r.l[0] + (t >> 23);  // weight 2^127 = 1; < 2^26 + 2^9
+    r.l[0] = t & M26;
+    r.l[1] += t >> 26;  // < 2^26 + 1
+    return r;
+  }
+  // s m a for a public m in [0, 4] and a sign s (smask = 0 for +, ~0 for -), a
+  // normalised: t = m a limb by limb (< 2^29), and -t is 8p - t = (t xor ~0) + 8p + 1
+  // per limb (8p's limbs 8(2^26 - 1), 8(2^23 - 1) exceed t's).  Limbs < 2^29.
+  SPDZ_HD static E mul_signed_tiny(E a, u32 m, u32 smask) {
+    const u32 k0 = smask & (8u * M26 + 1), k4 = smask & (8u * M23 + 1);
+    E r;
+#pragma unroll
+    for (int k = 0; k < 4; k++) r.l[k] = ((a.l[k] * m) ^ smask) + k0;
+    r.l[4] = ((a.l[4] * m) ^ smask) + k4;
+    return r;
+  }
   SPDZ_HD static Wide wzero() { return Wide{{0, 0, 0, 0, 0, 0, 0, 0, 0}}; }
   // with normalised operands (limbs < 2^27) up to 13 products fit (folded columns < 37 * 13 * 2^54 < 2^63)
   SPDZ_HD static void wmac(Wide &w, E a, E b) {
