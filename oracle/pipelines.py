@@ -234,3 +234,114 @@ def dag_run(dag, seed: int, check_seed: int, epoch: int = 0, keep=None):
             out[i] = nodes[i]
     ok, sigma = log.check(al)
     return out, ok, sigma
+
+
+# ---------------------------------------------------------------------------
+# private linear layer y = W x + b with one matrix-vector triple per row tile
+# (Sec. III-D "Data slicing" and "MPC-specific optimization"): tile t holds rows
+# [t R, min((t+1) R, dout)) of W; its triple is A_t (rows x din), B_t (din),
+# C_t = A_t B_t.  Per tile, in order, D_t = open(W_t - A_t) (row-major) and
+# E_t = open(x - B_t) are opened; Z_t = C_t + D_t B_t + A_t E_t + D_t E_t
+# (party 0 adds the public D_t E_t, every party alpha_i D_t E_t to its MAC
+# share), y_t = Z_t + b_t.  The MAC check covers every D_t and E_t.
+# ---------------------------------------------------------------------------
+@dataclass
+class DealtLayer:
+    f: F.Field
+    n: int
+    seed: int
+    dout: int
+    din: int
+    tile_rows: int
+    alpha: np.ndarray
+    Wv: np.ndarray
+    W: F.Shares
+    xv: np.ndarray
+    x: F.Shares
+    bv: np.ndarray
+    b: F.Shares
+    T: F.TripleArr   # a: dout*din, b: n_tiles*din, c: dout
+
+    @property
+    def n_tiles(self) -> int:
+        return -(-self.dout // self.tile_rows)
+
+    def tile(self, t: int):
+        r0 = t * self.tile_rows
+        return r0, min(r0 + self.tile_rows, self.dout)
+
+    def log_base(self, t: int) -> int:
+        """Opened-log index of D_t[0, 0]: every earlier tile opened rows * din + din values."""
+        return t * (self.tile_rows + 1) * self.din
+
+
+def _cols(sh: F.Shares, lo: int, hi: int) -> F.Shares:
+    return F.Shares(np.ascontiguousarray(sh.val[:, :, lo:hi]), np.ascontiguousarray(sh.mac[:, :, lo:hi]))
+
+
+def deal_linear_layer(p: int, n: int, dout: int, din: int, tile_rows: int, seed: int) -> DealtLayer:
+    from workloads import ARR_LA, ARR_LB, ARR_LB_T, ARR_LC, ARR_LW, ARR_LX
+    f = F.Field(p)
+    assert f.L == 1
+    al = f.alpha_shares(n, seed)
+    Wv, W = f.deal_uniform_secret(n, seed, ARR_LW, dout * din, al)
+    xv, x = f.deal_uniform_secret(n, seed, ARR_LX, din, al)
+    bv, b = f.deal_uniform_secret(n, seed, ARR_LB, dout, al)
+    n_tiles = -(-dout // tile_rows)
+    Av = f.deal_values(seed, ARR_LA, dout * din)
+    Bv = f.deal_values(seed, ARR_LB_T, n_tiles * din)
+    Cv = np.empty((1, dout), dtype=np.uint64)
+    for t in range(n_tiles):
+        r0, r1 = t * tile_rows, min((t + 1) * tile_rows, dout)
+        Cv[:, r0:r1] = f.matmul(Av[:, r0 * din:r1 * din].reshape(r1 - r0, din),
+                                Bv[:, t * din:(t + 1) * din].reshape(din, 1)).reshape(1, r1 - r0)
+    T = F.TripleArr(f.deal_secret(n, seed, ARR_LA, Av, al), f.deal_secret(n, seed, ARR_LB_T, Bv, al),
+                    f.deal_secret(n, seed, ARR_LC, Cv, al))
+    return DealtLayer(f, n, seed, dout, din, tile_rows, al, Wv, W, xv, x, bv, b, T)
+
+
+def linear_layer_tile(D: DealtLayer, t: int, log: Optional["F.MacLog"] = None):
+    """Tile t: opened D_t, E_t and the output rows y_t (value and MAC shares)."""
+    f, n, din = D.f, D.n, D.din
+    r0, r1 = D.tile(t)
+    rows = r1 - r0
+    Dt, Dm = open_difference(f, _cols(D.W, r0 * din, r1 * din), _cols(D.T.a, r0 * din, r1 * din))
+    Et, Em = open_difference(f, D.x, _cols(D.T.b, t * din, (t + 1) * din))
+    if log is not None:
+        log.add(Dt, Dm)
+        log.add(Et, Em)
+    Dmat, Ecol = Dt.reshape(rows, din), Et.reshape(din, 1)
+    DE = f.matmul(Dmat, Ecol).reshape(1, rows)
+    yv = np.empty((n, 1, rows), dtype=np.uint64)
+    ym = np.empty((n, 1, rows), dtype=np.uint64)
+    for i in range(n):
+        Bi = D.T.b.val[i][:, t * din:(t + 1) * din].reshape(din, 1)
+        BMi = D.T.b.mac[i][:, t * din:(t + 1) * din].reshape(din, 1)
+        Ai = D.T.a.val[i][:, r0 * din:r1 * din].reshape(rows, din)
+        AMi = D.T.a.mac[i][:, r0 * din:r1 * din].reshape(rows, din)
+        z = f.add_public(f.add_public(D.T.c.val[i][:, r0:r1].copy(), f.matmul(Dmat, Bi).reshape(1, rows)),
+                         f.matmul(Ai, Ecol).reshape(1, rows))
+        if i == 0:
+            z = f.add_public(z, DE)
+        yv[i] = f.add_public(z, D.b.val[i][:, r0:r1].copy())
+        zm = f.add_public(f.add_public(D.T.c.mac[i][:, r0:r1].copy(), f.matmul(Dmat, BMi).reshape(1, rows)),
+                          f.matmul(AMi, Ecol).reshape(1, rows))
+        zm = f.add_public(zm, f.scale_public(int(D.alpha[i, 0]), DE))
+        ym[i] = f.add_public(zm, D.b.mac[i][:, r0:r1].copy())
+    return Dt, Et, F.Shares(yv, ym)
+
+
+def linear_layer_run(D: DealtLayer, check_seed: int, epoch: int = 0):
+    """The whole layer, tile by tile, then the MAC check over every opened value."""
+    f, n = D.f, D.n
+    log = F.MacLog(f, n, check_seed, epoch)
+    Ds, Es, yv, ym = [], [], [], []
+    for t in range(D.n_tiles):
+        Dt, Et, yt = linear_layer_tile(D, t, log)
+        Ds.append(Dt)
+        Es.append(Et)
+        yv.append(yt.val)
+        ym.append(yt.mac)
+    ok, sigma = log.check(D.alpha)
+    return dict(D=np.concatenate(Ds, axis=1), E=np.concatenate(Es, axis=1),
+                y=F.Shares(np.concatenate(yv, axis=2), np.concatenate(ym, axis=2)), ok=ok, sigma=sigma)

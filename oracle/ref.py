@@ -327,3 +327,45 @@ def matrix_beaver(p: int, alpha_sh, X: SharedMat, Y: SharedMat, A: SharedMat,
         Zm.append(add(C.mac[i], matmul_mod(p, E, B.mac[i]), matmul_mod(p, A.mac[i], F),
                       scal(alpha_sh[i], EF)))
     return SharedMat(Zv, Zm), E, F
+
+
+def linear_layer(p: int, alpha_sh, n: int, seed: int, dout: int, din: int, tile_rows: int,
+                 log: Optional[OpenLog] = None):
+    """Private y = W x + b with one matrix-vector triple per tile of `tile_rows` rows
+    (Sec. III-D): every input dealt from its own array id, tile t's triple
+    (A_t rows x din, B_t din x 1, C_t = A_t B_t); per tile the matrix Beaver
+    product of (W_t, x) opens D_t then E_t, and y_t = Z_t + b_t.
+    Returns (Wv, xv, bv, y shares, y MAC shares) with y as [party][row]."""
+    from workloads import ARR_LA, ARR_LB, ARR_LB_T, ARR_LC, ARR_LW, ARR_LX
+    Wv, Wsh = deal_uniform_secret(p, n, seed, ARR_LW, dout * din, alpha_sh)
+    xv, xsh = deal_uniform_secret(p, n, seed, ARR_LX, din, alpha_sh)
+    bv, bsh = deal_uniform_secret(p, n, seed, ARR_LB, dout, alpha_sh)
+    n_tiles = -(-dout // tile_rows)
+    Av = deal_values(p, seed, ARR_LA, dout * din)
+    Bv = deal_values(p, seed, ARR_LB_T, n_tiles * din)
+    Cv = []
+    for t in range(n_tiles):
+        r0, r1 = t * tile_rows, min((t + 1) * tile_rows, dout)
+        At = [Av[r * din:(r + 1) * din] for r in range(r0, r1)]
+        Bt = [[v] for v in Bv[t * din:(t + 1) * din]]
+        Cv += [row[0] for row in matmul_mod(p, At, Bt)]
+    Ash = deal_secret(p, n, seed, ARR_LA, Av, alpha_sh)
+    Bsh = deal_secret(p, n, seed, ARR_LB_T, Bv, alpha_sh)
+    Csh = deal_secret(p, n, seed, ARR_LC, Cv, alpha_sh)
+
+    def mat(sh: Shared, lo: int, rows: int, cols: int) -> SharedMat:
+        cut = lambda v: [v[lo + r * cols:lo + (r + 1) * cols] for r in range(rows)]
+        return SharedMat([cut(v) for v in sh.val], [cut(m) for m in sh.mac])
+
+    yv = [[] for _ in range(n)]
+    ym = [[] for _ in range(n)]
+    for t in range(n_tiles):
+        r0, r1 = t * tile_rows, min((t + 1) * tile_rows, dout)
+        rows = r1 - r0
+        Z, _, _ = matrix_beaver(p, alpha_sh, mat(Wsh, r0 * din, rows, din), mat(xsh, 0, din, 1),
+                                mat(Ash, r0 * din, rows, din), mat(Bsh, t * din, din, 1),
+                                mat(Csh, r0, rows, 1), log)
+        for i in range(n):
+            yv[i] += [(Z.val[i][r][0] + bsh.val[i][r0 + r]) % p for r in range(rows)]
+            ym[i] += [(Z.mac[i][r][0] + bsh.mac[i][r0 + r]) % p for r in range(rows)]
+    return Wv, xv, bv, yv, ym

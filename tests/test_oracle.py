@@ -84,7 +84,7 @@ def test_tier1_mulmod_and_reduction(p):
 # --------------------------------------------------------------------------
 # dealer
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("p,n", [(P_TINY, 2), (P_TINY, 3), (P61, 2), (P61, 5), (P127, 3)])
+@pytest.mark.parametrize("p,n", [(P_TINY, 2), (P_TINY, 3), (P61, 2), (P61, 5), (P127, 3), (P_PAPER, 2)])
 def test_dealer_invariants_and_tiers_agree(p, n):
     W = 64
     alpha = R.alpha_shares(p, n, 11)
@@ -192,7 +192,7 @@ def _pipeline_ref(p, n, W, seed, tamper=None):
                 wpub=wpub, spub=spub, ok=ok, sigma=sigma, log=log)
 
 
-@pytest.mark.parametrize("p,n", [(P_TINY, 3), (P61, 2), (P127, 3), ((1 << 89) - 1, 4)])
+@pytest.mark.parametrize("p,n", [(P_TINY, 3), (P61, 2), (P127, 3), ((1 << 89) - 1, 4), (P_PAPER, 2)])
 def test_pipeline_closed_forms(p, n):
     W = 40
     r = _pipeline_ref(p, n, W, 3)
@@ -208,7 +208,7 @@ def test_pipeline_closed_forms(p, n):
     assert r["ok"] and len(r["log"].values) == 3 * W + 1
 
 
-@pytest.mark.parametrize("p,n", [(P61, 2), (P127, 3), (P_TINY, 3)])
+@pytest.mark.parametrize("p,n", [(P61, 2), (P127, 3), (P_TINY, 3), (P_PAPER, 2)])
 def test_tamper_closed_form(p, n):
     """Bumping x_{n-1}[k] by one: z stays MAC-consistent (z = (x+1) y), d and w do not.
 
@@ -236,7 +236,7 @@ def test_alpha_zero_cannot_detect():
     assert sum(r["alpha"]) % p == 0 and r["ok"]
 
 
-@pytest.mark.parametrize("p,n", [(P61, 2), (P127, 3), (P_TINY, 2)])
+@pytest.mark.parametrize("p,n", [(P61, 2), (P127, 3), (P_TINY, 2), (P_PAPER, 3)])
 def test_pipeline_tiers_agree(p, n):
     W, seed = 50, 8
     for tamper in (None, 13):
@@ -490,3 +490,71 @@ def test_mlp_adam_against_torch():
         opt.step()
         W, m, v = M.adam(W, g, m, v, t)
     assert np.allclose(W, p.detach().numpy(), rtol=1e-12, atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# private linear layer y = W x + b with matrix-vector triples per row tile
+# --------------------------------------------------------------------------
+LAYER_CASES = [(P_TINY, 2, 7, 5, 3), (P_PAPER, 2, 37, 64, 8), (P_PAPER, 3, 20, 33, 20), (P61, 2, 9, 16, 4)]
+
+
+def _ints(a):
+    return [int(v) for v in np.asarray(a).reshape(-1)]
+
+
+@pytest.mark.parametrize("p,n,dout,din,tr", LAYER_CASES)
+def test_linear_layer_closed_forms(p, n, dout, din, tr):
+    """Reconstructed y is W x + b (Python integers), its MAC is alpha y, the check accepts."""
+    from oracle.pipelines import deal_linear_layer, linear_layer_run
+    D = deal_linear_layer(p, n, dout, din, tr, 3)
+    res = linear_layer_run(D, check_seed=3)
+    W, x, b = _ints(D.Wv), _ints(D.xv), _ints(D.bv)
+    alpha = sum(_ints(D.alpha[:, 0])) % p
+    for r in range(dout):
+        want = (sum(W[r * din + k] * x[k] for k in range(din)) + b[r]) % p
+        got = sum(int(res["y"].val[i, 0, r]) for i in range(n)) % p
+        assert got == want
+        gotm = sum(int(res["y"].mac[i, 0, r]) for i in range(n)) % p
+        assert gotm == alpha * want % p
+    assert res["ok"] and sum(_ints(res["sigma"][:, 0])) % p == 0
+    # opened values: D = W - A and E_t = x - B_t, in tile order
+    assert res["D"].shape[1] == dout * din and res["E"].shape[1] == D.n_tiles * din
+
+
+@pytest.mark.parametrize("p,n,dout,din,tr", [(P_TINY, 2, 7, 5, 3), (P_PAPER, 3, 6, 9, 4)])
+def test_linear_layer_tiers_agree(p, n, dout, din, tr):
+    from oracle.pipelines import deal_linear_layer, linear_layer_run
+    D = deal_linear_layer(p, n, dout, din, tr, 4)
+    res = linear_layer_run(D, check_seed=4)
+    al = _ints(D.alpha[:, 0])
+    log = R.OpenLog()
+    Wv, xv, bv, yv, ym = R.linear_layer(p, al, n, 4, dout, din, tr, log)
+    assert Wv == _ints(D.Wv) and xv == _ints(D.xv) and bv == _ints(D.bv)
+    for i in range(n):
+        assert yv[i] == _ints(res["y"].val[i]) and ym[i] == _ints(res["y"].mac[i])
+    ok, sig = R.mac_check(p, al, log, 4, 0)
+    assert ok == res["ok"] and sig == _ints(res["sigma"][:, 0])
+    # the tier-0 log holds, per tile, D_t then E_t
+    opened = []
+    for t in range(D.n_tiles):
+        r0, r1 = D.tile(t)
+        opened += _ints(res["D"][:, r0 * din:r1 * din]) + _ints(res["E"][:, t * din:(t + 1) * din])
+    assert log.values == opened
+
+
+@pytest.mark.parametrize("p,n", [(P_PAPER, 2), (P_TINY, 3)])
+def test_linear_layer_tamper_closed_form(p, n):
+    """Party n-1's share of one W element bumped by one: D there is off by one, so
+    sum_i sigma_i = -alpha r_j at that element's log index j."""
+    from oracle.pipelines import bump_share, deal_linear_layer, linear_layer_run
+    dout, din, tr = 11, 6, 4
+    D = deal_linear_layer(p, n, dout, din, tr, 5)
+    r, k = 9, 4
+    bump_share(D.f, D.W, n - 1, r * din + k)
+    res = linear_layer_run(D, check_seed=5)
+    t = r // tr
+    j = D.log_base(t) + (r - t * tr) * din + k
+    rj = R.mac_coefficients(p, 5, 0, j + 1)[j]
+    alpha = sum(_ints(D.alpha[:, 0])) % p
+    assert sum(_ints(res["sigma"][:, 0])) % p == (-alpha * rj) % p
+    assert res["ok"] == (alpha * rj % p == 0)

@@ -42,6 +42,8 @@ ARR_MX, ARR_MY, ARR_MA, ARR_MB, ARR_MC = 8, 9, 10, 11, 12
 # DAG workload: the two level-0 inputs, then 3 ids (a, b, c) per Beaver op
 ARR_DAG_IN0, ARR_DAG_IN1 = 16, 17
 ARR_DAG_TRIPLE0 = 32
+# linear-layer workload: W, x, b, then the matrix-vector triples (A, B, C)
+ARR_LW, ARR_LX, ARR_LB, ARR_LA, ARR_LB_T, ARR_LC = 20, 21, 22, 23, 24, 25
 
 SEED_PARITY = 0
 SEEDS_TIMING = (1, 2, 3, 4, 5)
@@ -98,6 +100,37 @@ class MatmulConfig:
 
 MATMUL_1024 = MatmulConfig("matrix_triple_n2_p61_N1024", 2, P61, 1024)
 MATMUL_4096 = MatmulConfig("matrix_triple_n2_p61_N4096", 2, P61, 4096)
+
+
+@dataclass(frozen=True)
+class LayerConfig:
+    """The paper's private linear layer y = W x + b (Sec. III-D, IV-A): W is dout x din,
+    row-major; W is cut into tiles of `tile_rows` consecutive rows, tile_rows =
+    max(1, slice // din) for a slice size counted in elements of W."""
+    name: str
+    n: int
+    p: int
+    din: int
+    dout: int
+    slice: int
+    seed: int = SEED_PARITY
+
+    @property
+    def tile_rows(self) -> int:
+        return max(1, self.slice // self.din)
+
+    @property
+    def n_tiles(self) -> int:
+        return -(-self.dout // self.tile_rows)
+
+
+def layer_config(dim: int, slice_size: int = 524280, n: int = 2) -> LayerConfig:
+    return LayerConfig(f"linear_layer_n{n}_p32_d{dim}_s{slice_size}", n, P_PAPER, dim, dim, slice_size)
+
+
+# the paper's input-size sweep (Sec. IV-E: 2 parties, slice 524280) and slice sweep at 8192 (Sec. IV-D)
+LAYER_DIMS = (2048, 4096, 8192)
+LAYER_SLICES = (131070, 262140, 524280, 1048560)
 
 
 def tamper_index(seed: int, width: int) -> int:
