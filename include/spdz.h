@@ -149,6 +149,28 @@ spdz_status spdz_mul_fused(spdz_ctx *ctx, const spdz_shares *x, const spdz_share
                            uint64_t *e_pub, const uint64_t *lin, spdz_shares *w,
                            uint64_t *w_pub, spdz_shares *s);
 
+/* Private linear layer y = W x + b (Sec. III-D, "Data slicing" and
+ * "MPC-specific optimization"): W is cut into tiles of tile_rows consecutive
+ * rows (the last tile may be shorter), and tile t is multiplied by x with its
+ * own matrix-vector triple (A_t, B_t, C_t = A_t B_t):
+ *   D_t = open(W_t - A_t) [rows_t x din],  E_t = open(x - B_t) [din],
+ *   Z_t,i    = C_t,i + D_t B_t,i + A_t,i E_t + [i = 0] D_t E_t
+ *   M(Z_t)_i = M(C_t)_i + D_t M(B_t)_i + M(A_t)_i E_t + alpha_i D_t E_t,
+ *   y_t = Z_t + b_t (values and MAC shares).
+ * Layout (one limb, per party at val/mac + i * party_stride):
+ *   W and T->a: dout * din words, row-major (element r * din + k);
+ *   x: din;  b, T->c, y: dout;  T->b: n_tiles * din with B_t at t * din,
+ *   n_tiles = ceil(dout / tile_rows); C_t occupies the tile's rows of T->c.
+ * Log order: tile by tile, D_t (row-major) then E_t, i.e. dout * din +
+ * n_tiles * din values.  D_pub (device [dout * din]) and E_pub (device
+ * [n_tiles * din]) receive the opened values and may be NULL (E then lives in
+ * the library workspace, grown on first use).  y must not overlap the inputs.
+ * Single-limb fields only (2^32 - 5, the paper's field, and 2^61 - 1); a
+ * two-limb context returns SPDZ_E_UNSUPPORTED.  Asynchronous. */
+spdz_status spdz_linear_layer(spdz_ctx *ctx, int64_t dout, int64_t din, int64_t tile_rows, const spdz_shares *W,
+                              const spdz_shares *x, const spdz_shares *b, const spdz_triple *T, spdz_shares *y,
+                              uint64_t *D_pub, uint64_t *E_pub);
+
 /* Matrix-triple product (Sec. III-D, "MPC-specific optimization": one
  * matrix triple (A, B, C = A B) per product, D = X - A and E = Y - B opened,
  * Z = C + D B + A E + D E; here the opened matrices are called E and F):
@@ -346,6 +368,14 @@ spdz_status spdz_deal_secret(spdz_ctx *ctx, uint64_t seed, uint64_t array_id,
  * Synchronous: allocates and frees a temporary buffer for the public values. */
 spdz_status spdz_deal_matrix_triple(spdz_ctx *ctx, uint64_t seed, uint64_t array_id, int64_t M, int64_t K,
                                     int64_t N, spdz_triple *out);
+
+/* Deal the matrix-vector triples of a linear layer (the layout of
+ * spdz_linear_layer's T): A [dout * din] from array_id, B [n_tiles * din] from
+ * array_id + 1, C_t = A_t B_t per tile of tile_rows rows, shared with
+ * array_id + 2.  Single-limb fields only.  Synchronous: allocates and frees a
+ * temporary buffer for the public values. */
+spdz_status spdz_deal_matvec_triple(spdz_ctx *ctx, uint64_t seed, uint64_t array_id, int64_t dout, int64_t din,
+                                    int64_t tile_rows, spdz_triple *out);
 
 /* Deal a Beaver triple with ids array_id (a), +1 (b), +2 (c = a b). */
 spdz_status spdz_deal_triple(spdz_ctx *ctx, uint64_t seed, uint64_t array_id, spdz_triple *out);

@@ -11,10 +11,21 @@ using namespace spdz;
 
 namespace {
 
-bool supported_modulus(const u64 *p, int L) {
-  if (L == 1) return p[0] == F61::P;
-  if (L == 2) return p[0] == ~0ull && p[1] == F127::PHI;
-  return false;
+// field id of a supported modulus, -1 otherwise
+int field_of(const u64 *p, int L) {
+  if (L == 1 && p[0] == F61::P) return FID_61;
+  if (L == 1 && p[0] == F32::P) return FID_32;
+  if (L == 2 && p[0] == ~0ull && p[1] == F127::PHI) return FID_127;
+  return -1;
+}
+
+// canonical (below p) multi-limb value
+bool canonical(const u64 *v, int fid) {
+  switch (fid) {
+    case FID_61: return v[0] < F61::P;
+    case FID_32: return v[0] < F32::P;
+    default: return v[1] < F127::PHI || (v[1] == F127::PHI && v[0] != ~0ull);
+  }
 }
 
 // every element of a descriptor must stay inside the caller's buffers; only
@@ -81,18 +92,17 @@ spdz_status spdz_ctx_create(spdz_ctx **out, int n_parties, const uint64_t *p_lim
   if (!out || !p_limbs || !alpha_shares) return SPDZ_E_INVAL;
   *out = nullptr;
   if (n_parties < MIN_PARTIES || n_parties > MAX_PARTIES) return SPDZ_E_UNSUPPORTED;
-  if (!supported_modulus(p_limbs, n_limbs)) return SPDZ_E_MODULUS;
+  const int fid = field_of(p_limbs, n_limbs);
+  if (fid < 0) return SPDZ_E_MODULUS;
   spdz_ctx *c = new (std::nothrow) spdz_ctx();
   if (!c) return SPDZ_E_NOMEM;
   c->n = n_parties;
   c->L = n_limbs;
+  c->fid = fid;
   for (int l = 0; l < n_limbs; l++) c->p[l] = p_limbs[l];
   for (int i = 0; i < n_parties; i++) {
     for (int l = 0; l < n_limbs; l++) c->alpha[i][l] = alpha_shares[i * n_limbs + l];
-    // alpha_i must be canonical
-    bool ok = n_limbs == 1 ? c->alpha[i][0] < F61::P
-                           : (c->alpha[i][1] < F127::PHI || (c->alpha[i][1] == F127::PHI && c->alpha[i][0] != ~0ull));
-    if (!ok) {
+    if (!canonical(c->alpha[i], fid)) {  // alpha_i must be canonical
       delete c;
       return SPDZ_E_INVAL;
     }
@@ -183,8 +193,10 @@ spdz_status spdz_mul_fused(spdz_ctx *c, const spdz_shares *x, const spdz_shares 
   SPDZ_CHECK(check_mul_operands(c, x, y, t, z));
   if (w) {
     if (!lin) return SPDZ_E_INVAL;
+    for (int k = 0; k < 4; k++)
+      if (!canonical(lin + k * c->L, c->fid)) return SPDZ_E_INVAL;
     SPDZ_CHECK(check_sv(c, w, x->len));
-    if (x->len > 0 && overlaps(c, w, x) || overlaps(c, w, y) || overlaps(c, w, z)) return SPDZ_E_INVAL;
+    if (x->len > 0 && (overlaps(c, w, x) || overlaps(c, w, y) || overlaps(c, w, z))) return SPDZ_E_INVAL;
   } else if (w_pub) {
     return SPDZ_E_INVAL;
   }
@@ -197,6 +209,9 @@ spdz_status spdz_linear(spdz_ctx *c, int n_terms, const spdz_shares *terms, cons
                         const uint64_t *c0, spdz_shares *out) {
   SPDZ_LIVE(c);
   if (!terms || !coeffs || !out || n_terms < 1 || n_terms > 8) return SPDZ_E_INVAL;
+  for (int k = 0; k < n_terms; k++)
+    if (!canonical(coeffs + k * c->L, c->fid)) return SPDZ_E_INVAL;
+  if (c0 && !canonical(c0, c->fid)) return SPDZ_E_INVAL;
   for (int k = 0; k < n_terms; k++) SPDZ_CHECK(check_sv(c, &terms[k], out->len));
   SPDZ_CHECK(check_sv(c, out, out->len));
   if (out->len == 0) return SPDZ_OK;
@@ -216,7 +231,7 @@ spdz_status spdz_matmul_triple(spdz_ctx *c, int64_t M, int64_t K, int64_t N, con
                                uint64_t *F_pub, int variant) {
   SPDZ_LIVE(c);
   if (!X || !Y || !T || !Z) return SPDZ_E_INVAL;
-  if (c->L != 1) return SPDZ_E_UNSUPPORTED;
+  if (c->fid != FID_61) return SPDZ_E_UNSUPPORTED;
   if (M <= 0 || K <= 0 || N <= 0) return SPDZ_E_SHAPE;
   if (variant == -1) variant = 1;
   if (variant != 0 && variant != 1) return SPDZ_E_INVAL;
@@ -231,6 +246,27 @@ spdz_status spdz_matmul_triple(spdz_ctx *c, int64_t M, int64_t K, int64_t N, con
       overlaps(c, Z, &T->c))
     return SPDZ_E_INVAL;
   return launch_matmul_triple(c, M, K, N, X, Y, T, Z, E_pub, F_pub, variant);
+}
+
+spdz_status spdz_linear_layer(spdz_ctx *c, int64_t dout, int64_t din, int64_t tile_rows, const spdz_shares *W,
+                              const spdz_shares *x, const spdz_shares *b, const spdz_triple *T, spdz_shares *y,
+                              uint64_t *D_pub, uint64_t *E_pub) {
+  SPDZ_LIVE(c);
+  if (!W || !x || !b || !T || !y) return SPDZ_E_INVAL;
+  if (c->L != 1) return SPDZ_E_UNSUPPORTED;
+  if (dout <= 0 || din <= 0 || tile_rows <= 0 || dout > (INT64_MAX / 4) / din) return SPDZ_E_SHAPE;
+  const int64_t n_tiles = (dout + tile_rows - 1) / tile_rows;
+  SPDZ_CHECK(check_sv(c, W, dout * din));
+  SPDZ_CHECK(check_sv(c, &T->a, dout * din));
+  SPDZ_CHECK(check_sv(c, x, din));
+  SPDZ_CHECK(check_sv(c, &T->b, n_tiles * din));
+  SPDZ_CHECK(check_sv(c, b, dout));
+  SPDZ_CHECK(check_sv(c, &T->c, dout));
+  SPDZ_CHECK(check_sv(c, y, dout));
+  if (overlaps(c, y, W) || overlaps(c, y, x) || overlaps(c, y, b) || overlaps(c, y, &T->a) ||
+      overlaps(c, y, &T->b) || overlaps(c, y, &T->c))
+    return SPDZ_E_INVAL;
+  return launch_linear_layer(c, dout, din, tile_rows, W, x, b, T, y, D_pub, E_pub);
 }
 
 spdz_status spdz_mac_check(spdz_ctx *c, int *accepted, uint64_t *sigma_out) {
@@ -257,10 +293,11 @@ spdz_status spdz_mac_check(spdz_ctx *c, int *accepted, uint64_t *sigma_out) {
     }
     zero = F::is_zero(tot);
   };
-  if (c->L == 1)
-    finish(F61{});
-  else
-    finish(F127{});
+  switch (c->fid) {
+    case FID_61: finish(F61{}); break;
+    case FID_127: finish(F127{}); break;
+    default: finish(F32{}); break;
+  }
   memset(c->host_acc, 0, sizeof(c->host_acc));
   c->epoch += 1;
   c->log_count = 0;
@@ -320,23 +357,16 @@ spdz_status spdz_copy_probe(uint64_t *dst, const uint64_t *src, int64_t words, v
 spdz_status spdz_deal_alpha(const uint64_t *p_limbs, int n_limbs, int n_parties, uint64_t seed,
                             uint64_t *alpha_out) {
   if (!p_limbs || !alpha_out || n_parties < 1 || n_parties > MAX_PARTIES) return SPDZ_E_INVAL;
-  if (!supported_modulus(p_limbs, n_limbs)) return SPDZ_E_MODULUS;
+  const int fid = field_of(p_limbs, n_limbs);
+  if (fid < 0) return SPDZ_E_MODULUS;
+  // element i of the uniform stream, with the device dealer's rejection rule
   const u64 state = sm_out(seed, stream_id(TAG_ALPHA, 0, 0));
   for (int i = 0; i < n_parties; i++) {
-    // element i of the uniform stream (same rejection rule as the device dealer)
-    const u64 base = (u64)i * 32u;
-    u64 lo = 0, hi = 0;
-    for (int k = 0; k < 16; k++) {
-      if (n_limbs == 1) {
-        u64 u = sm_out(state, base + k) & F61::P;
-        if (u < F61::P) { lo = u; break; }
-      } else {
-        u64 l = sm_out(state, base + 2 * k), h = sm_out(state, base + 2 * k + 1) & F127::PHI;
-        if (!(h == F127::PHI && l == ~0ull)) { lo = l; hi = h; break; }
-      }
+    switch (fid) {
+      case FID_61: F61::to_words(uniform_elem<F61>(state, i), alpha_out + i * n_limbs); break;
+      case FID_32: F32::to_words(uniform_elem<F32>(state, i), alpha_out + i * n_limbs); break;
+      default: F127::to_words(uniform_elem<F127>(state, i), alpha_out + i * n_limbs); break;
     }
-    alpha_out[i * n_limbs] = lo;
-    if (n_limbs == 2) alpha_out[i * n_limbs + 1] = hi;
   }
   return SPDZ_OK;
 }
@@ -350,11 +380,35 @@ spdz_status spdz_deal_secret(spdz_ctx *c, uint64_t seed, uint64_t array_id, cons
   return launch_deal_secret(c, seed, array_id, values, out, values_out);
 }
 
+spdz_status spdz_deal_matvec_triple(spdz_ctx *c, uint64_t seed, uint64_t array_id, int64_t dout, int64_t din,
+                                    int64_t tile_rows, spdz_triple *t) {
+  SPDZ_LIVE(c);
+  if (!t) return SPDZ_E_INVAL;
+  if (c->L != 1) return SPDZ_E_UNSUPPORTED;
+  if (dout <= 0 || din <= 0 || tile_rows <= 0 || dout > (INT64_MAX / 4) / din) return SPDZ_E_SHAPE;
+  const int64_t n_tiles = (dout + tile_rows - 1) / tile_rows;
+  SPDZ_CHECK(check_sv(c, &t->a, dout * din));
+  SPDZ_CHECK(check_sv(c, &t->b, n_tiles * din));
+  SPDZ_CHECK(check_sv(c, &t->c, dout));
+  // public A, B and C live in a temporary buffer
+  u64 *tmp = nullptr;
+  const size_t words = (size_t)(dout * din) + (size_t)(n_tiles * din) + (size_t)dout;
+  if (hipMalloc((void **)&tmp, words * 8) != hipSuccess) return SPDZ_E_NOMEM;
+  u64 *av = tmp, *bv = tmp + (size_t)(dout * din), *cv = bv + (size_t)(n_tiles * din);
+  spdz_status s = launch_deal_secret(c, seed, array_id, nullptr, &t->a, av);
+  if (s == SPDZ_OK) s = launch_deal_secret(c, seed, array_id + 1, nullptr, &t->b, bv);
+  if (s == SPDZ_OK) s = launch_public_matvec(c, dout, din, tile_rows, av, bv, cv);
+  if (s == SPDZ_OK) s = launch_deal_secret(c, seed, array_id + 2, cv, &t->c, nullptr);
+  if (hipStreamSynchronize(c->stream) != hipSuccess && s == SPDZ_OK) s = SPDZ_E_HIP;
+  hipFree(tmp);
+  return s;
+}
+
 spdz_status spdz_deal_matrix_triple(spdz_ctx *c, uint64_t seed, uint64_t array_id, int64_t M, int64_t K, int64_t N,
                                     spdz_triple *t) {
   SPDZ_LIVE(c);
   if (!t) return SPDZ_E_INVAL;
-  if (c->L != 1) return SPDZ_E_UNSUPPORTED;
+  if (c->fid != FID_61) return SPDZ_E_UNSUPPORTED;
   if (M <= 0 || K <= 0 || N <= 0 || K > MAX_MFMA_K) return SPDZ_E_SHAPE;
   SPDZ_CHECK(check_sv(c, &t->a, M * K));
   SPDZ_CHECK(check_sv(c, &t->b, K * N));

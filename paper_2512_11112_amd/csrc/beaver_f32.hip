@@ -1,0 +1,8 @@
+// Beaver product kernels over 2^32 - 5.
+#include "beaver.h"
+
+namespace spdz {
+template spdz_status launch_beaver_field<F32>(spdz_ctx *, const spdz_shares *, const spdz_shares *,
+                                              const spdz_triple *, spdz_shares *, u64 *, u64 *, const u64 *,
+                                              spdz_shares *, u64 *, spdz_shares *);
+}  // namespace spdz

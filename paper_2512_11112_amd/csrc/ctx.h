@@ -21,6 +21,9 @@ constexpr int WAVES = BLOCK / 64;   // wave64
 constexpr int MAX_SLOTS = 4096;     // per-block accumulator slots (upper bound on grid size)
 constexpr int64_t MAX_MFMA_K = 8191; // int32 class sums stay exact for inner dimension 2K <= 16382
 
+// fields of a context
+enum FieldId : int { FID_61 = 0, FID_127 = 1, FID_32 = 2 };
+
 // stream-id layout of the dealer and the MAC-check coefficients:
 // stream = tag << 56 | array_id << 8 | party
 constexpr u64 TAG_ALPHA = 1, TAG_VALUE = 2, TAG_SHARE = 3, TAG_MACSH = 4, TAG_COEF = 5;
@@ -37,6 +40,7 @@ inline SV sv_of(const spdz_shares *s) { return SV{s->val, s->mac, s->party_strid
 
 struct spdz_ctx {
   int n = 0, L = 0;
+  int fid = spdz::FID_61;
   spdz::u64 p[2] = {0, 0};
   spdz::u64 alpha[spdz::MAX_PARTIES][2] = {};
   spdz::u64 check_seed = 0, epoch = 0;
@@ -87,7 +91,12 @@ spdz_status visit_n(int n, Fn &&fn) {
 }
 template <class Fn>
 spdz_status visit(const spdz_ctx *c, Fn &&fn) {
-  return c->L == 1 ? visit_n<F61>(c->n, fn) : visit_n<F127>(c->n, fn);
+  switch (c->fid) {
+    case FID_61: return visit_n<F61>(c->n, fn);
+    case FID_127: return visit_n<F127>(c->n, fn);
+    case FID_32: return visit_n<F32>(c->n, fn);
+  }
+  return SPDZ_E_MODULUS;
 }
 
 inline spdz_status hip_status(hipError_t e) { return e == hipSuccess ? SPDZ_OK : SPDZ_E_HIP; }
@@ -148,5 +157,13 @@ spdz_status launch_matmul_triple(spdz_ctx *c, int64_t M, int64_t K, int64_t N, c
                                  const spdz_shares *Y, const spdz_triple *T, spdz_shares *Z, u64 *E_pub, u64 *F_pub,
                                  int variant);
 spdz_status launch_public_matmul(spdz_ctx *c, int64_t M, int64_t K, int64_t N, const u64 *A, const u64 *B, u64 *C);
+// grows the context workspace to at least `bytes` (waits for the stream before freeing the old one)
+spdz_status ensure_ws(spdz_ctx *c, size_t bytes);
+// linear_layer.hip
+spdz_status launch_linear_layer(spdz_ctx *c, int64_t dout, int64_t din, int64_t tile_rows, const spdz_shares *W,
+                                const spdz_shares *x, const spdz_shares *b, const spdz_triple *T, spdz_shares *y,
+                                u64 *D_pub, u64 *E_pub);
+spdz_status launch_public_matvec(spdz_ctx *c, int64_t dout, int64_t din, int64_t tile_rows, const u64 *A,
+                                 const u64 *B, u64 *C);
 
 }  // namespace spdz

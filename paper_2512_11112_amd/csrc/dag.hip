@@ -258,7 +258,7 @@ spdz_status spdz_dag_create(spdz_ctx *c, int n_inputs, const int64_t *input_widt
                             const spdz_dag_op *ops, spdz_dag **out) {
   if (!c || !out || !input_widths || (n_ops > 0 && !ops) || n_inputs < 1 || n_ops < 0) return SPDZ_E_INVAL;
   if (c->aborted) return SPDZ_E_ABORTED;
-  if (c->L != 1) return SPDZ_E_UNSUPPORTED;
+  if (c->fid != FID_61) return SPDZ_E_UNSUPPORTED;
   *out = nullptr;
   spdz_dag *g = new (std::nothrow) spdz_dag();
   if (!g) return SPDZ_E_NOMEM;

@@ -309,22 +309,9 @@ DealStreams<F, N> streams_for(u64 seed, u64 array_id) {
 
 template <class F, int N>
 typename F::E alpha_sum(const spdz_ctx *c) {
-  // host-side modular sum of the alpha shares (canonical inputs)
-  if constexpr (F::L == 1) {
-    u64 s = 0;
-    for (int i = 0; i < N; i++) {
-      s += c->alpha[i][0];
-      if (s >= F61::P) s -= F61::P;
-    }
-    return {s};
-  } else {
-    u128 p = ((u128)F127::PHI << 64) | ~0ull, s = 0;
-    for (int i = 0; i < N; i++) {
-      s += ((u128)c->alpha[i][1] << 64) | c->alpha[i][0];
-      if (s >= p) s -= p;
-    }
-    return {(u64)s, (u64)(s >> 64)};
-  }
+  typename F::E s = F::zero();
+  for (int i = 0; i < N; i++) s = F::add(s, F::from_words(c->alpha[i]));
+  return F::canon(s);
 }
 
 }  // namespace
@@ -378,8 +365,11 @@ spdz_status launch_beaver_field(spdz_ctx *c, const spdz_shares *x, const spdz_sh
 spdz_status launch_beaver(spdz_ctx *c, const spdz_shares *x, const spdz_shares *y, const spdz_triple *t,
                           spdz_shares *z, u64 *d_pub, u64 *e_pub, const u64 *lin, spdz_shares *w, u64 *w_pub,
                           spdz_shares *s) {
-  return c->L == 1 ? launch_beaver_field<F61>(c, x, y, t, z, d_pub, e_pub, lin, w, w_pub, s)
-                   : launch_beaver_field<F127>(c, x, y, t, z, d_pub, e_pub, lin, w, w_pub, s);
+  switch (c->fid) {
+    case FID_61: return launch_beaver_field<F61>(c, x, y, t, z, d_pub, e_pub, lin, w, w_pub, s);
+    case FID_127: return launch_beaver_field<F127>(c, x, y, t, z, d_pub, e_pub, lin, w, w_pub, s);
+    default: return launch_beaver_field<F32>(c, x, y, t, z, d_pub, e_pub, lin, w, w_pub, s);
+  }
 }
 
 spdz_status launch_linear(spdz_ctx *c, int nt, const spdz_shares *terms, const u64 *coeffs, const u64 *c0,

@@ -2,6 +2,8 @@
 //
 // F61:  p = 2^61 - 1,  one 64-bit limb.
 // F127: p = 2^127 - 1, two 64-bit limbs (lo, hi).
+// F32:  p = 2^32 - 5, one 64-bit limb holding a residue below 2^32 (the field
+//       of the paper's evaluation, Sec. IV-A).
 //
 // In registers a residue is kept "almost canonical": any value in [0, p],
 // where p itself stands for 0.  Because p = 2^k - 1 is all ones, this makes
@@ -56,6 +58,7 @@ struct F61 {
   struct Wide {
     u128 v;
   };
+  static constexpr int WIDE_TERMS = 32;
 
   SPDZ_HD static E zero() { return {0}; }
   SPDZ_HD static u64 fold(u64 s) { return (s & P) + (s >> 61); }
@@ -231,6 +234,74 @@ struct F127 {
   }
 };
 
+// ---------------------------------------------------------------------------
+// p = 2^32 - 5.  Residues are kept canonical in [0, p) in 32-bit registers and
+// zero-extended in memory.  2^32 = 5 (mod p), so a 64-bit value x = h 2^32 + l
+// reduces as 5 h + l; two such folds and one conditional subtraction give the
+// canonical residue of any x < 2^64.
+// ---------------------------------------------------------------------------
+struct F32 {
+  static constexpr int L = 1;
+  static constexpr int BITS = 32;
+  static constexpr u64 P = 4294967291ull;  // 2^32 - 5
+  struct E {
+    u32 v;
+  };
+  // sum of once-folded products (each < 6 * 2^32) and residues: exact below 2^64
+  struct Wide {
+    u64 v;
+  };
+  static constexpr int WIDE_TERMS = 1 << 28;
+
+  SPDZ_HD static E zero() { return {0}; }
+  SPDZ_HD static u64 fold(u64 x) { return 5 * (x >> 32) + (x & 0xffffffffull); }  // < 6 * 2^32
+  // any x < 2^64 -> [0, p)
+  SPDZ_HD static E reduce(u64 x) {
+    const u64 t = fold(fold(x));  // < 2^32 + 30 < 2p
+    return {(u32)(t >= P ? t - P : t)};
+  }
+  SPDZ_HD static E add(E a, E b) {
+    const u64 s = (u64)a.v + b.v;
+    return {(u32)(s >= P ? s - P : s)};
+  }
+  SPDZ_HD static E neg(E a) { return {a.v ? (u32)(P - a.v) : 0u}; }
+  SPDZ_HD static E sub(E a, E b) { return {a.v >= b.v ? a.v - b.v : (u32)(a.v + P - b.v)}; }
+  SPDZ_HD static E canon(E a) { return a; }
+  SPDZ_HD static bool is_zero(E a) { return a.v == 0; }
+  SPDZ_HD static E add_lazy(E a, E b) { return add(a, b); }
+  SPDZ_HD static E sub_lazy(E a, E b) { return sub(a, b); }
+  SPDZ_HD static E neg_lazy(E a) { return neg(a); }
+  SPDZ_HD static E mul(E a, E b) { return reduce((u64)a.v * b.v); }
+  SPDZ_HD static E mul_small(E a, u32 m) { return reduce((u64)a.v * m); }
+  SPDZ_HD static E mul_tiny(E a, u32 m) { return mul_small(a, m); }
+  SPDZ_HD static E neg_tiny(E a, u32 m) { return neg(mul_small(a, m)); }
+  SPDZ_HD static E mul_signed_tiny(E a, u32 m, u32 smask) {
+    const E t = mul_small(a, m);
+    return smask ? neg(t) : t;
+  }
+  SPDZ_HD static E norm(E a) { return a; }
+  SPDZ_HD static Wide wzero() { return {0}; }
+  SPDZ_HD static void wmac(Wide &w, E a, E b) { w.v += fold((u64)a.v * b.v); }
+  SPDZ_HD static void wadd(Wide &w, E a) { w.v += a.v; }
+  SPDZ_HD static E wreduce(Wide w) { return reduce(w.v); }
+
+  __device__ __forceinline__ static E load(const u64 *base, int64_t /*limb_stride*/, int64_t idx) {
+    return {(u32)__builtin_nontemporal_load(base + idx)};
+  }
+  __device__ __forceinline__ static E load_cached(const u64 *base, int64_t, int64_t idx) { return {(u32)base[idx]}; }
+  __device__ __forceinline__ static void store(u64 *base, int64_t /*limb_stride*/, int64_t idx, E x) {
+    __builtin_nontemporal_store((u64)x.v, base + idx);
+  }
+  __device__ __forceinline__ static E oload(const u64 *base, const u32 *off) { return {(u32)off_load(base, off[0])}; }
+  __device__ __forceinline__ static void ostore(u64 *base, const u32 *off, E x) { off_store(base, off[0], (u64)x.v); }
+  SPDZ_HD static E from_words(const u64 *w) { return {(u32)w[0]}; }
+  SPDZ_HD static void to_words(E x, u64 *w) { w[0] = x.v; }
+
+  static constexpr int WORDS32 = 1;
+  __device__ __forceinline__ static u32 word32(E a, int) { return a.v; }
+  __device__ __forceinline__ static E from32(const u32 *w) { return {w[0]}; }
+};
+
 // --------------------------------------------------------------------------
 // SplitMix64 (Steele, Lea, Flood, OOPSLA 2014) in counter mode, and uniform
 // residues by rejection sampling.  Output i of the generator with state s is
@@ -271,6 +342,16 @@ SPDZ_HD F127::E uniform_elem<F127>(u64 state, u64 e) {
     if (!(hi == F127::PHI && lo == ~0ull)) return {lo, hi};
   }
   return {0, 0};
+}
+
+template <>
+SPDZ_HD F32::E uniform_elem<F32>(u64 state, u64 e) {
+  const u64 base = e * 32u;
+  for (int k = 0; k < 16; k++) {
+    const u64 u = sm_out(state, base + k) & 0xffffffffull;
+    if (u < F32::P) return {(u32)u};
+  }
+  return {0};
 }
 
 }  // namespace spdz

@@ -271,10 +271,6 @@ __global__ __launch_bounds__(256, 1) void k_gemm_mfma(const GemmArgs A) {
 // ==========================================================================
 // host side
 // ==========================================================================
-namespace {
-
-int64_t up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
-
 spdz_status ensure_ws(spdz_ctx *c, size_t bytes) {
   if (c->ws_bytes >= bytes) return SPDZ_OK;
   if (c->ws) {
@@ -287,6 +283,10 @@ spdz_status ensure_ws(spdz_ctx *c, size_t bytes) {
   c->ws_bytes = bytes;
   return SPDZ_OK;
 }
+
+namespace {
+
+int64_t up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 spdz_status digits(spdz_ctx *c, const u64 *src, int64_t rows, int64_t cols, int8_t *planes, int64_t Rp, int64_t Kp,
                    bool right) {

@@ -70,6 +70,11 @@ def lib() -> ctypes.CDLL:
             "spdz_deal_triple": (i32, [vp, ctypes.c_uint64, ctypes.c_uint64, ctypes.POINTER(Triple)]),
             "spdz_matmul_triple": (i32, [vp, i64, i64, i64, ctypes.POINTER(Shares), ctypes.POINTER(Shares),
                                          ctypes.POINTER(Triple), ctypes.POINTER(Shares), vp, vp, i32]),
+            "spdz_linear_layer": (i32, [vp, i64, i64, i64, ctypes.POINTER(Shares), ctypes.POINTER(Shares),
+                                        ctypes.POINTER(Shares), ctypes.POINTER(Triple), ctypes.POINTER(Shares),
+                                        vp, vp]),
+            "spdz_deal_matvec_triple": (i32, [vp, ctypes.c_uint64, ctypes.c_uint64, i64, i64, i64,
+                                              ctypes.POINTER(Triple)]),
             "spdz_deal_matrix_triple": (i32, [vp, ctypes.c_uint64, ctypes.c_uint64, i64, i64, i64,
                                               ctypes.POINTER(Triple)]),
             "spdz_dag_create": (i32, [vp, i32, ctypes.POINTER(ctypes.c_int64), i64, vp, ctypes.POINTER(vp)]),
@@ -163,6 +168,13 @@ class TripleTensor:
     @staticmethod
     def empty(n, L, W, device="cuda") -> "TripleTensor":
         return TripleTensor(*(ShareTensor.empty(n, L, W, device) for _ in range(3)))
+
+    @staticmethod
+    def empty_layer(n, dout, din, tile_rows, device="cuda") -> "TripleTensor":
+        """Matrix-vector triples of a linear layer: A [dout*din], B [n_tiles*din], C [dout] (one limb)."""
+        n_tiles = -(-dout // tile_rows)
+        return TripleTensor(ShareTensor.empty(n, 1, dout * din, device), ShareTensor.empty(n, 1, n_tiles * din, device),
+                            ShareTensor.empty(n, 1, dout, device))
 
     @staticmethod
     def empty_matrix(n, M, K, N, device="cuda") -> "TripleTensor":
@@ -296,6 +308,18 @@ class Context:
                                         variant), "spdz_matmul_triple")
         return Z
 
+    def spdz_linear_layer(self, dout: int, din: int, tile_rows: int, W: ShareTensor, x: ShareTensor,
+                          b: ShareTensor, T: TripleTensor, y: Optional[ShareTensor] = None,
+                          D_pub: Optional[torch.Tensor] = None, E_pub: Optional[torch.Tensor] = None) -> ShareTensor:
+        """y = W x + b with one matrix-vector triple per tile of tile_rows rows (W row-major
+        [n][1][dout*din], x [n][1][din], b and y [n][1][dout], T.b [n][1][n_tiles*din])."""
+        y = self.new_shares(dout) if y is None else y
+        dW, dx, db, dt, dy = W.desc(), x.desc(), b.desc(), T.desc(), y.desc()
+        _check(lib().spdz_linear_layer(self._h, dout, din, tile_rows, ctypes.byref(dW), ctypes.byref(dx),
+                                       ctypes.byref(db), ctypes.byref(dt), ctypes.byref(dy), _ptr(D_pub),
+                                       _ptr(E_pub)), "spdz_linear_layer")
+        return y
+
     def spdz_mac_check(self):
         """(accepted, [sigma_i as ints])."""
         acc = ctypes.c_int(0)
@@ -331,6 +355,13 @@ class Context:
         d = out.desc()
         _check(lib().spdz_deal_matrix_triple(self._h, ctypes.c_uint64(seed), ctypes.c_uint64(array_id),
                                              M, K, N, ctypes.byref(d)), "spdz_deal_matrix_triple")
+        return out
+
+    def spdz_deal_matvec_triple(self, seed: int, array_id: int, dout: int, din: int, tile_rows: int,
+                                out: TripleTensor) -> TripleTensor:
+        d = out.desc()
+        _check(lib().spdz_deal_matvec_triple(self._h, ctypes.c_uint64(seed), ctypes.c_uint64(array_id),
+                                             dout, din, tile_rows, ctypes.byref(d)), "spdz_deal_matvec_triple")
         return out
 
     def spdz_deal_triple(self, seed: int, array_id: int, out: TripleTensor) -> TripleTensor:

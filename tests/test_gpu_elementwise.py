@@ -11,7 +11,7 @@ import torch
 import oracle.fast as F
 from oracle.pipelines import beaver_run, bump_share, deal_elementwise, pipeline_run
 from tests._util import dev, host, ints_of_sigma, share_to_dev, triple_to_dev
-from workloads import ARR_A, ARR_X, P61, P127, tamper_index
+from workloads import ARR_A, ARR_X, P61, P127, P_PAPER, tamper_index
 
 pytestmark = pytest.mark.gpu
 
@@ -35,7 +35,8 @@ def eq_shares(t, s: F.Shares, what=""):
 
 
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("p,n,W", [(P61, 2, 1000), (P61, 5, 4097), (P127, 3, 4099), (P127, 2, 1)])
+@pytest.mark.parametrize("p,n,W", [(P61, 2, 1000), (P61, 5, 4097), (P127, 3, 4099), (P127, 2, 1),
+                                   (P_PAPER, 2, 5001), (P_PAPER, 4, 333)])
 def test_device_dealer_matches_oracle(p, n, W):
     from paper_2512_11112_amd.spdz import ShareTensor, TripleTensor
     D = deal_elementwise(p, n, W, 7)
@@ -61,7 +62,8 @@ def test_device_dealer_matches_oracle(p, n, W):
 
 # --------------------------------------------------------------------------
 MUL_CASES = [(P61, 2, 1), (P61, 2, 1 << 16), (P61, 3, 100003), (P61, 8, 3001),
-             (P127, 3, 1), (P127, 3, 65539), (P127, 2, 5000), (P127, 6, 777)]
+             (P127, 3, 1), (P127, 3, 65539), (P127, 2, 5000), (P127, 6, 777),
+             (P_PAPER, 2, 1 << 16), (P_PAPER, 3, 100003), (P_PAPER, 8, 301)]
 
 
 @pytest.mark.parametrize("p,n,W", MUL_CASES)
@@ -83,12 +85,12 @@ def test_mul_batch_and_mac_check(p, n, W):
     assert ctx.opened_count() == 0
 
 
-@pytest.mark.parametrize("p,n,W", [(P61, 2, 70001), (P127, 3, 70001), (P127, 4, 333)])
+@pytest.mark.parametrize("p,n,W", [(P61, 2, 70001), (P127, 3, 70001), (P127, 4, 333), (P_PAPER, 2, 70001)])
 def test_open_linear_reduce(p, n, W):
     """open(x); w = c1 x + c2 y + c0; s = ReduceAdd(w); open(s); MAC check over [x, s]."""
     D = deal_elementwise(p, n, W, 2)
     f = D.f
-    c = [p - 2, (1 << 60) + 12345, 987654321]
+    c = [p - 2, ((1 << 60) + 12345) % p, 987654321 % p]
     log = F.MacLog(f, n, 2, 0)
     xo = f.open(D.x.val)
     log.add(xo, D.x.mac)
@@ -156,7 +158,7 @@ def check_fused(got, ref):
 
 
 @pytest.mark.parametrize("p,n,W", [(P127, 3, (1 << 16) + 5), (P61, 2, 100001), (P127, 2, 3),
-                                   (P61, 4, 12345)])
+                                   (P61, 4, 12345), (P_PAPER, 2, 100001), (P_PAPER, 3, 777)])
 def test_fused_pipeline(p, n, W):
     print(f"case p-bits={p.bit_length()} n={n} W={W}", flush=True)
     D = deal_elementwise(p, n, W, 4)
@@ -166,10 +168,10 @@ def test_fused_pipeline(p, n, W):
     assert got["ok"]
 
 
-def test_fused_general_coefficients():
-    p = P127
+@pytest.mark.parametrize("p", [P127, P61, P_PAPER])
+def test_fused_general_coefficients(p):
     D = deal_elementwise(p, 3, 9999, 5)
-    lin = (p - 7, (1 << 126) + 3, 1 << 64, p - 1)
+    lin = (p - 7, (p >> 1) + 3, (1 << (p.bit_length() // 2)) + 1, p - 1)
     ref = pipeline_run(D, check_seed=5, lin=lin)
     _, got = run_fused(D, 5, lin=lin, with_pub=False)
     check_fused(got, ref)
@@ -188,8 +190,9 @@ def wide_window(s: F.Shares, gap_words: int):
     return ShareTensor(place(s.val), place(s.mac))
 
 
-@pytest.mark.parametrize("p,n,fused", [(P127, 2, True), (P61, 3, False)])
-def test_wide_window_layout(p, n, fused):
+@pytest.mark.parametrize("p,n,fused,lin", [(P127, 2, True, None), (P61, 3, False, None),
+                                           (P_PAPER, 2, True, (5, 1 << 20, 9, 7)), (P127, 3, True, (11, 1, 0, 2))])
+def test_wide_window_layout(p, n, fused, lin):
     """x's party planes more than 4 GiB apart: addressing beyond 32-bit offsets."""
     from paper_2512_11112_amd.spdz import ShareTensor
     W = 4099
@@ -202,11 +205,12 @@ def test_wide_window_layout(p, n, fused):
     z = ShareTensor.empty(n, L, W)
     dp, ep = ctx.new_public(W), ctx.new_public(W)
     if fused:
-        ref = pipeline_run(D, check_seed=9)
+        lin = lin if lin is not None else (1, 3, p - 1, 0)
+        ref = pipeline_run(D, check_seed=9, lin=lin)
         w, s = ShareTensor.empty(n, L, W), ShareTensor.empty(n, L, 1)
         wp = ctx.new_public(W)
         ctx.spdz_mul_fused(xw, share_to_dev(D.y), triple_to_dev(D.t), z, dp, ep,
-                           lin=(1, 3, p - 1, 0), w=w, w_pub=wp, s=s)
+                           lin=lin, w=w, w_pub=wp, s=s)
         sp = ctx.spdz_open(s)
         ok, sigma = ctx.spdz_mac_check()
         got = dict(z=z, w=w, s=s, d=dp, e=ep, wpub=wp, spub=sp, ok=ok, sigma=sigma)
@@ -223,7 +227,7 @@ def test_wide_window_layout(p, n, fused):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("p,n,W", [(P127, 3, 50000), (P61, 2, 50000)])
+@pytest.mark.parametrize("p,n,W", [(P127, 3, 50000), (P61, 2, 50000), (P_PAPER, 2, 50000)])
 def test_tampered_share_is_rejected(p, n, W):
     """Party n-1's value share of one element of x bumped by one: the check must reject."""
     from paper_2512_11112_amd.spdz import SpdzError
@@ -238,6 +242,26 @@ def test_tampered_share_is_rejected(p, n, W):
     with pytest.raises(SpdzError) as ei:
         ctx.spdz_open(got["z"])
     assert ei.value.status == -6
+
+
+def test_non_canonical_coefficients_rejected():
+    """Public coefficients must be below p: the call does nothing and returns SPDZ_E_INVAL."""
+    from paper_2512_11112_amd.spdz import ShareTensor, SpdzError
+    p = P_PAPER
+    D = deal_elementwise(p, 2, 100, 8)
+    ctx = make_ctx(D, 8)
+    xd = share_to_dev(D.x)
+    with pytest.raises(SpdzError) as ei:
+        ctx.spdz_linear([xd], [p], 0)
+    assert ei.value.status == -1
+    with pytest.raises(SpdzError) as ei:
+        ctx.spdz_linear([xd], [1], p + 3)
+    assert ei.value.status == -1
+    z, w = ShareTensor.empty(2, 1, 100), ShareTensor.empty(2, 1, 100)
+    with pytest.raises(SpdzError) as ei:
+        ctx.spdz_mul_fused(xd, share_to_dev(D.y), triple_to_dev(D.t), z, None, None, lin=(1, 1 << 40, 0, 0), w=w)
+    assert ei.value.status == -1
+    assert ctx.opened_count() == 0
 
 
 def test_zero_width_and_shape_errors():
@@ -300,7 +324,7 @@ def edge_shares(f, n, W, rng):
     return Shares(arr(), arr())
 
 
-@pytest.mark.parametrize("p,n", [(P61, 2), (P61, 3), (P127, 3), (P127, 2)])
+@pytest.mark.parametrize("p,n", [(P61, 2), (P61, 3), (P127, 3), (P127, 2), (P_PAPER, 2), (P_PAPER, 3)])
 def test_edge_values_fused(p, n):
     from oracle.pipelines import Dealt
     rng = np.random.default_rng(p % 997 + n)

@@ -1,0 +1,171 @@
+"""Parity of the private linear layer y = W x + b (one matrix-vector triple per
+row tile) against the CPU oracle: dealer, opened D and E, output shares and MAC
+shares, sigma_i and the verdict, bit for bit."""
+import numpy as np
+import pytest
+import torch
+
+from oracle.pipelines import bump_share, deal_linear_layer, linear_layer_run, linear_layer_tile
+import oracle.fast as F
+from tests._util import host, ints_of_sigma, share_to_dev, triple_to_dev
+from workloads import ARR_LA, ARR_LB, ARR_LW, ARR_LX, P61, P_PAPER, layer_config
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2512_11112_amd import spdz
+    spdz.lib()
+
+
+def make_ctx(D, check_seed):
+    from paper_2512_11112_amd.spdz import Context
+    return Context(D.n, D.f.p, ints_of_sigma(D.alpha), check_seed)
+
+
+def eq_shares(t, s: F.Shares, what=""):
+    assert np.array_equal(host(t.val), s.val), f"{what} values differ"
+    assert np.array_equal(host(t.mac), s.mac), f"{what} MAC shares differ"
+
+
+@pytest.mark.parametrize("p,n,dout,din,tr", [(P_PAPER, 2, 37, 64, 8), (P61, 3, 20, 33, 20), (P_PAPER, 4, 9, 3000, 2)])
+def test_device_matvec_dealer_matches_oracle(p, n, dout, din, tr):
+    from paper_2512_11112_amd.spdz import TripleTensor
+    print(f"case p-bits={p.bit_length()} n={n} dout={dout} din={din} tile_rows={tr}", flush=True)
+    D = deal_linear_layer(p, n, dout, din, tr, 11)
+    ctx = make_ctx(D, 0)
+    T = TripleTensor.empty_layer(n, dout, din, tr)
+    ctx.spdz_deal_matvec_triple(11, ARR_LA, dout, din, tr, T)
+    eq_shares(T.a, D.T.a, "A")
+    eq_shares(T.b, D.T.b, "B")
+    eq_shares(T.c, D.T.c, "C")
+
+
+LAYER_CASES = [(P_PAPER, 2, 37, 64, 8),      # ragged last tile
+               (P_PAPER, 3, 130, 200, 63),
+               (P_PAPER, 2, 5, 10, 8),       # one partial tile
+               (P_PAPER, 2, 1, 1, 1),
+               (P61, 2, 50, 3000, 7),        # rows longer than one accumulation chunk
+               (P_PAPER, 8, 12, 777, 5)]
+
+
+@pytest.mark.parametrize("p,n,dout,din,tr", LAYER_CASES)
+def test_linear_layer_matches_oracle(p, n, dout, din, tr):
+    print(f"case p-bits={p.bit_length()} n={n} dout={dout} din={din} tile_rows={tr}", flush=True)
+    D = deal_linear_layer(p, n, dout, din, tr, 12)
+    ref = linear_layer_run(D, check_seed=12)
+    ctx = make_ctx(D, 12)
+    Dp = torch.empty((1, dout * din), dtype=torch.int64, device="cuda")
+    Ep = torch.empty((1, D.n_tiles * din), dtype=torch.int64, device="cuda")
+    y = ctx.spdz_linear_layer(dout, din, tr, share_to_dev(D.W), share_to_dev(D.x), share_to_dev(D.b),
+                              triple_to_dev(D.T), D_pub=Dp, E_pub=Ep)
+    assert ctx.opened_count() == dout * din + D.n_tiles * din
+    ok, sigma = ctx.spdz_mac_check()
+    assert np.array_equal(host(Dp), ref["D"]), "opened D differs"
+    assert np.array_equal(host(Ep), ref["E"]), "opened E differs"
+    eq_shares(y, ref["y"], "y")
+    assert ok and ref["ok"]
+    assert sigma == ints_of_sigma(ref["sigma"])
+
+
+def test_linear_layer_without_public_outputs():
+    """E in the library workspace, D never stored: the same y and sigma."""
+    p, n, dout, din, tr = P_PAPER, 2, 70, 129, 16
+    D = deal_linear_layer(p, n, dout, din, tr, 13)
+    ref = linear_layer_run(D, check_seed=13)
+    ctx = make_ctx(D, 13)
+    y = ctx.spdz_linear_layer(dout, din, tr, share_to_dev(D.W), share_to_dev(D.x), share_to_dev(D.b),
+                              triple_to_dev(D.T))
+    ok, sigma = ctx.spdz_mac_check()
+    eq_shares(y, ref["y"], "y")
+    assert ok and sigma == ints_of_sigma(ref["sigma"])
+
+
+def test_linear_layer_tamper_rejected():
+    from paper_2512_11112_amd.spdz import SpdzError
+    p, n, dout, din, tr = P_PAPER, 2, 40, 96, 8
+    D = deal_linear_layer(p, n, dout, din, tr, 14)
+    bump_share(D.f, D.W, n - 1, 17 * din + 5)
+    ref = linear_layer_run(D, check_seed=14)
+    assert not ref["ok"]
+    ctx = make_ctx(D, 14)
+    y = ctx.spdz_linear_layer(dout, din, tr, share_to_dev(D.W), share_to_dev(D.x), share_to_dev(D.b),
+                              triple_to_dev(D.T))
+    ok, sigma = ctx.spdz_mac_check()
+    assert not ok and sigma == ints_of_sigma(ref["sigma"])
+    eq_shares(y, ref["y"], "y")
+    with pytest.raises(SpdzError) as ei:
+        ctx.spdz_open(y)
+    assert ei.value.status == -6
+
+
+def test_linear_layer_shape_errors():
+    from paper_2512_11112_amd.spdz import Context, ShareTensor, SpdzError, TripleTensor, deal_alpha
+    ctx = Context(2, P_PAPER, deal_alpha(P_PAPER, 2, 1), 1)
+    W, x, b = ShareTensor.empty(2, 1, 12), ShareTensor.empty(2, 1, 4), ShareTensor.empty(2, 1, 3)
+    T = TripleTensor.empty_layer(2, 3, 4, 2)
+    with pytest.raises(SpdzError) as ei:   # B sized for 2 tiles, asked for 3
+        ctx.spdz_linear_layer(3, 4, 1, W, x, b, T)
+    assert ei.value.status == -3
+    with pytest.raises(SpdzError) as ei:
+        ctx.spdz_linear_layer(3, 4, 0, W, x, b, T)
+    assert ei.value.status == -3
+    with pytest.raises(SpdzError) as ei:   # y aliases b
+        ctx.spdz_linear_layer(3, 4, 2, W, x, b, T, y=b)
+    assert ei.value.status == -1
+    ctx127 = Context(2, (1 << 127) - 1, deal_alpha((1 << 127) - 1, 2, 1), 1)
+    with pytest.raises(SpdzError) as ei:
+        ctx127.spdz_linear_layer(3, 4, 2, ShareTensor.empty(2, 2, 12), ShareTensor.empty(2, 2, 4),
+                                 ShareTensor.empty(2, 2, 3), TripleTensor.empty_layer(2, 3, 4, 2))
+    assert ei.value.status == -7
+    assert ctx.opened_count() == 0
+
+
+# --------------------------------------------------------------------------
+# the paper's layer at full size: 8192 x 8192, 2 parties, p = 2^32 - 5, slice
+# 524280 (63-row tiles), launched as the benchmark launches it.  Inputs are
+# dealt on the device by the library and, independently, on the host by the
+# oracle's dealer; sampled tiles are compared in full, the MAC check over all
+# opened values bit for bit.
+# --------------------------------------------------------------------------
+@pytest.mark.timeout(900)
+def test_linear_layer_full_size_paper_config():
+    from paper_2512_11112_amd.spdz import Context, ShareTensor, TripleTensor
+    cfg = layer_config(8192)
+    n, dout, din, tr = cfg.n, cfg.dout, cfg.din, cfg.tile_rows
+    print(f"case full-size layer n={n} d={din} tile_rows={tr}", flush=True)
+    D = deal_linear_layer(cfg.p, n, dout, din, tr, 0)
+    ctx = Context(n, cfg.p, ints_of_sigma(D.alpha), 0)
+    W, x, b = ShareTensor.empty(n, 1, dout * din), ShareTensor.empty(n, 1, din), ShareTensor.empty(n, 1, dout)
+    ctx.spdz_deal_secret(0, ARR_LW, W)
+    ctx.spdz_deal_secret(0, ARR_LX, x)
+    ctx.spdz_deal_secret(0, ARR_LB, b)
+    T = ctx.spdz_deal_matvec_triple(0, ARR_LA, dout, din, tr, TripleTensor.empty_layer(n, dout, din, tr))
+    Ep = torch.empty((1, cfg.n_tiles * din), dtype=torch.int64, device="cuda")
+    y = ctx.spdz_linear_layer(dout, din, tr, W, x, b, T, E_pub=Ep)
+    ok, sigma = ctx.spdz_mac_check()
+    yv, ym, Eh = host(y.val), host(y.mac), host(Ep)
+    del W, x, b, T
+    torch.cuda.empty_cache()
+    # sampled tiles: first, middle, last (ragged)
+    for t in (0, cfg.n_tiles // 2, cfg.n_tiles - 1):
+        Dt, Et, yt = linear_layer_tile(D, t)
+        r0, r1 = D.tile(t)
+        assert np.array_equal(Eh[:, t * din:(t + 1) * din], Et), f"E of tile {t} differs"
+        assert np.array_equal(yv[:, :, r0:r1], yt.val), f"y of tile {t} differs"
+        assert np.array_equal(ym[:, :, r0:r1], yt.mac), f"y MACs of tile {t} differs"
+    # the MAC check over every opened value, in log order
+    log = F.MacLog(D.f, n, 0, 0)
+    from oracle.pipelines import _cols, open_difference
+    for t in range(cfg.n_tiles):
+        r0, r1 = D.tile(t)
+        Dt, Dm = open_difference(D.f, _cols(D.W, r0 * din, r1 * din), _cols(D.T.a, r0 * din, r1 * din))
+        log.add(Dt, Dm)
+        Et, Em = open_difference(D.f, D.x, _cols(D.T.b, t * din, (t + 1) * din))
+        log.add(Et, Em)
+    ref_ok, ref_sigma = log.check(D.alpha)
+    assert ok and ref_ok
+    assert sigma == ints_of_sigma(ref_sigma)
