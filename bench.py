@@ -39,22 +39,27 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "beaver_fused_n3_p127_w16777216_tr
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2512_11112_amd", "csrc", f) for f in ("beaver.h", "coef.h", "blockred.h", "field.h", "field127r.h")]
 
 
-def kernel_source_hash() -> str:
+LAYER_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "linear_layer_rows_n2_p32_d8192_s524280_traffic.md")
+LAYER_SOURCES = [os.path.join(ROOT, "paper_2512_11112_amd", "csrc", f) for f in ("linear_layer.hip", "coef.h", "blockred.h", "field.h")]
+
+
+def kernel_source_hash(sources=None) -> str:
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in (sources or KERNEL_SOURCES):
         h.update(open(f, "rb").read())
     return h.hexdigest()[:16]
 
 
-def read_traffic(W: int):
-    """HBM bytes per launch from the committed counter summary, if it was taken on the current kernel."""
-    if not os.path.exists(TRAFFIC_FILE):
+def read_traffic(W: int, path: str = TRAFFIC_FILE, sources=None):
+    """HBM bytes per launch from a committed counter summary, if it was taken on the current kernel
+    sources at the same width (else None)."""
+    if not os.path.exists(path):
         return None
-    txt = open(TRAFFIC_FILE).read()
+    txt = open(path).read()
     m_hash = re.search(r"kernel_source_hash:\s*([0-9a-f]+)", txt)
     m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
     m_w = re.search(r"width:\s*(\d+)", txt)
-    if not (m_hash and m_bytes and m_w) or m_hash.group(1) != kernel_source_hash() or int(m_w.group(1)) != W:
+    if not (m_hash and m_bytes and m_w) or m_hash.group(1) != kernel_source_hash(sources) or int(m_w.group(1)) != W:
         return None
     return float(m_bytes.group(1))
 
@@ -83,10 +88,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 22)
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--suite", choices=["pipeline", "matmul", "dag", "dispatch"], default="pipeline",
+    ap.add_argument("--suite", choices=["pipeline", "matmul", "dag", "dispatch", "layer"], default="pipeline",
                     help="pipeline: the headline step (default); matmul: matrix triples at N=1024, 4096; "
                          "dag: the 100k-op layered DAG per op / per level / hipGraph; dispatch: learned vs "
-                         "static CPU-GPU dispatch on 20 held-out DAG seeds")
+                         "static CPU-GPU dispatch on 20 held-out DAG seeds; layer: the paper's private "
+                         "linear layer at p = 2^32-5 (input sizes 2048-8192, slice sizes 131070-1048560)")
     ap.add_argument("--seeds", type=int, default=20, help="held-out DAG seeds of the dispatch suite")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -99,7 +105,7 @@ def main():
     from workloads import ARR_A, ARR_X, ARR_Y, P61, P127, SEEDS_TIMING
 
     if args.suite != "pipeline":
-        fn = {"matmul": suite_matmul, "dag": suite_dag, "dispatch": suite_dispatch}[args.suite]
+        fn = {"matmul": suite_matmul, "dag": suite_dag, "dispatch": suite_dispatch, "layer": suite_layer}[args.suite]
         print(json.dumps(fn(args)), flush=True)
         return
 
@@ -289,6 +295,102 @@ def suite_matmul(args):
             "mfma_over_valu_N4096": res["N4096_valu"]["gemm_ms"] / res["N4096_mfma"]["gemm_ms"],
             "mfma_over_valu_N1024": res["N1024_valu"]["gemm_ms"] / res["N1024_mfma"]["gemm_ms"],
             "results": res}
+
+
+def layer_bytes(n: int, dout: int, din: int, n_tiles: int):
+    """Algorithmic HBM bytes of one private linear layer (one limb, values and MACs of every
+    party): W and A read once (32 n dout din), B and x once per tile / once (16 n n_tiles din,
+    16 n din), E written and read (16 n_tiles din), b and C read and y written (48 n dout).
+    The row kernel's share: W, A, b, C, y."""
+    total = 32 * n * dout * din + 16 * n * n_tiles * din + 16 * n * din + 16 * n_tiles * din + 48 * n * dout
+    rows = 32 * n * dout * din + 48 * n * dout
+    return total, rows
+
+
+def suite_layer(args):
+    """The paper's private linear layer y = W x + b (Sec. III-D, IV): 2 parties, p = 2^32 - 5,
+    W d x d with d = 2048, 4096, 8192 at slice 524280 (Sec. IV-E), and slices 131070 .. 1048560
+    at d = 8192 (Sec. IV-D).  A step is the layer (open of every E_t, the row kernel) plus the
+    MAC check over everything it opened, verdict read back."""
+    import torch
+    from paper_2512_11112_amd import spdz as S
+    from workloads import ARR_LA, ARR_LB, ARR_LW, ARR_LX, LAYER_DIMS, LAYER_SLICES, SEEDS_TIMING, layer_config
+    seed = SEEDS_TIMING[0]
+    cfgs = [layer_config(d) for d in LAYER_DIMS] + [layer_config(8192, sl) for sl in LAYER_SLICES if sl != 524280]
+    res = {}
+    for cfg in cfgs:
+        n, p, dout, din, tr = cfg.n, cfg.p, cfg.dout, cfg.din, cfg.tile_rows
+        ctx = S.Context(n, p, S.deal_alpha(p, n, seed), seed)
+        W, x, b = S.ShareTensor.empty(n, 1, dout * din), S.ShareTensor.empty(n, 1, din), S.ShareTensor.empty(n, 1, dout)
+        ctx.spdz_deal_secret(seed, ARR_LW, W)
+        ctx.spdz_deal_secret(seed, ARR_LX, x)
+        ctx.spdz_deal_secret(seed, ARR_LB, b)
+        T = ctx.spdz_deal_matvec_triple(seed, ARR_LA, dout, din, tr, S.TripleTensor.empty_layer(n, dout, din, tr))
+        y = ctx.new_shares(dout)
+        for _ in range(args.warmup):
+            ctx.spdz_linear_layer(dout, din, tr, W, x, b, T, y)
+            ok, _ = ctx.spdz_mac_check()
+            assert ok
+        torch.cuda.synchronize()
+        ctx.spdz_timing_enable(True)
+        ts = []
+        for _ in range(args.steps):
+            t0 = time.perf_counter()
+            ctx.spdz_linear_layer(dout, din, tr, W, x, b, T, y)
+            ok, _ = ctx.spdz_mac_check()
+            ts.append((time.perf_counter() - t0) * 1e3)
+            assert ok
+        rows_ms, rc = ctx.spdz_timing_get("layer_rows")
+        e_ms, ec = ctx.spdz_timing_get("layer_open_e")
+        ctx.spdz_timing_enable(False)
+        total_b, rows_b = layer_bytes(n, dout, din, cfg.n_tiles)
+        ms = _median(ts)
+        res[cfg.name] = {"d": din, "slice": cfg.slice, "tile_rows": tr, "tiles": cfg.n_tiles, "step_ms": ms,
+                         "rows_kernel_ms": rows_ms / rc, "open_e_kernel_ms": e_ms / ec,
+                         "alg_bytes": total_b, "rows_kernel_GBps": rows_b / (rows_ms / rc) / 1e6,
+                         "step_GBps": total_b / ms / 1e6}
+        log(f"layer d={din} slice={cfg.slice} ({tr}-row tiles): {ms:.3f} ms/step, row kernel {rows_ms / rc:.3f} ms "
+            f"({rows_b / (rows_ms / rc) / 1e6:.0f} GB/s), E kernel {e_ms / ec:.3f} ms")
+        ctx.close()
+        del W, x, b, T, y
+        torch.cuda.empty_cache()
+    main = res[layer_config(8192).name]
+    out = {"metric": "private linear layer y = W x + b latency (2 parties, p = 2^32-5, d = 8192, slice 524280, "
+                     "incl. MAC check)",
+           "value": main["step_ms"], "unit": "ms", "higher_is_better": False, "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": main["step_ms"], "vs_baseline": None,
+           "dtype": "u64 words (residues < 2^32)", "data": "synthetic",
+           "config": {"workload": layer_config(8192).name, "parties": 2, "modulus": "2^32-5", "din": 8192,
+                      "dout": 8192, "slice": 524280, "tile_rows": main["tile_rows"]},
+           "roofline": {"bound": "hbm", "kernel": "k_ll_rows<F32,2>", "achieved": main["rows_kernel_GBps"],
+                        "peak": 8000.0, "unit": "GB/s", "frac": main["rows_kernel_GBps"] / 8000.0,
+                        "traffic": read_traffic(8192 * 8192, LAYER_TRAFFIC_FILE, LAYER_SOURCES),
+                        "kernel_ms": main["rows_kernel_ms"], "alg_bytes_per_launch": layer_bytes(2, 8192, 8192, 131)[1]},
+           # the paper's own GPU back end on this layer (Sec. IV-D text, 8 threads, another machine): context only
+           "paper_context": {"gpu_backend_s_slice131070_T8": 13.37, "gpu_backend_s_slice1048560_T8": 11.07},
+           "results": res}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_layer(layer_config(8192).n_tiles)
+    return out
+
+
+def cpu_baseline_layer(tiles: int):
+    """The oracle on `tiles` tiles of the d = 8192 layer (same din, fewer rows), scaled to the layer."""
+    import os
+    from oracle.pipelines import deal_linear_layer, linear_layer_run
+    from workloads import layer_config
+    cfg = layer_config(8192)
+    rows = min(cfg.dout, tiles * cfg.tile_rows)
+    D = deal_linear_layer(cfg.p, cfg.n, rows, cfg.din, cfg.tile_rows, 1)
+    t0 = time.perf_counter()
+    r = linear_layer_run(D, check_seed=1)
+    dt = time.perf_counter() - t0
+    assert r["ok"]
+    ms = dt * 1e3 * cfg.dout / rows
+    return {"value": ms, "unit": "ms", "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+            "kind": "oracle", "sample": f"{rows} of the 8192 rows ({-(-rows // cfg.tile_rows)} tiles) of the d=8192 "
+                                        f"layer, whole protocol (opens, products, MAC check) on the oracle, "
+                                        f"{dt:.2f} s wall, scaled by 8192/{rows}; dealing excluded"}
 
 
 def dag_alg_bytes(dag):
