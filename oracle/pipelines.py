@@ -287,17 +287,24 @@ def deal_linear_layer(p: int, n: int, dout: int, din: int, tile_rows: int, seed:
     Wv, W = f.deal_uniform_secret(n, seed, ARR_LW, dout * din, al)
     xv, x = f.deal_uniform_secret(n, seed, ARR_LX, din, al)
     bv, b = f.deal_uniform_secret(n, seed, ARR_LB, dout, al)
+    assert ARR_LB_T == ARR_LA + 1 and ARR_LC == ARR_LA + 2
+    T = deal_matvec_triple(f, n, seed, ARR_LA, dout, din, tile_rows, al)
+    return DealtLayer(f, n, seed, dout, din, tile_rows, al, Wv, W, xv, x, bv, b, T)
+
+
+def deal_matvec_triple(f: F.Field, n: int, seed: int, aid: int, dout: int, din: int, tile_rows: int, al):
+    """Per-tile matrix-vector triples: A (dout*din) from array aid, B (n_tiles*din) from aid + 1,
+    C_t = A_t B_t shared with aid + 2."""
     n_tiles = -(-dout // tile_rows)
-    Av = f.deal_values(seed, ARR_LA, dout * din)
-    Bv = f.deal_values(seed, ARR_LB_T, n_tiles * din)
+    Av = f.deal_values(seed, aid, dout * din)
+    Bv = f.deal_values(seed, aid + 1, n_tiles * din)
     Cv = np.empty((1, dout), dtype=np.uint64)
     for t in range(n_tiles):
         r0, r1 = t * tile_rows, min((t + 1) * tile_rows, dout)
         Cv[:, r0:r1] = f.matmul(Av[:, r0 * din:r1 * din].reshape(r1 - r0, din),
                                 Bv[:, t * din:(t + 1) * din].reshape(din, 1)).reshape(1, r1 - r0)
-    T = F.TripleArr(f.deal_secret(n, seed, ARR_LA, Av, al), f.deal_secret(n, seed, ARR_LB_T, Bv, al),
-                    f.deal_secret(n, seed, ARR_LC, Cv, al))
-    return DealtLayer(f, n, seed, dout, din, tile_rows, al, Wv, W, xv, x, bv, b, T)
+    return F.TripleArr(f.deal_secret(n, seed, aid, Av, al), f.deal_secret(n, seed, aid + 1, Bv, al),
+                       f.deal_secret(n, seed, aid + 2, Cv, al))
 
 
 def linear_layer_tile(D: DealtLayer, t: int, log: Optional["F.MacLog"] = None):

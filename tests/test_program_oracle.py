@@ -1,0 +1,151 @@
+"""Pins of the control-flow interpreter (oracle/program.py) on the CPU.
+
+A plaintext evaluation of each program (cleartext field elements, the program's
+definition read directly: select as f + c (t - f), shl as a product with 2^k, a
+layer as W x + b) must equal the reconstruction of the oracle's shares; MAC
+shares must reconstruct to alpha times the value; every opened value must equal
+the plaintext value of what was opened; block-entry counts follow the control
+flow; secret control flow and malformed programs are rejected.
+"""
+import numpy as np
+import pytest
+
+import oracle.fast as F
+from oracle.program import ProgramError, parse, run_program
+from workloads import P61, P_PAPER, P_TINY, programs as P
+
+
+def plain_run(text: str, p: int, seed: int):
+    """Cleartext execution: every value a list of integers."""
+    prog = parse(text, p)
+    f = F.Field(p)
+    val, opened, entries = {}, [], 0
+    for nid, nd in prog.nodes.items():
+        if nd.op == "input":
+            val[nid] = [int(v) for v in F.from_limbs(f.deal_values(seed, nd.imm[0], nd.width))]
+        elif nd.op == "const":
+            val[nid] = [nd.imm[0]] * nd.width
+
+    def get(nid, w):
+        v = val[nid]
+        return v * w if len(v) == 1 and w > 1 else v
+
+    blk, pred = prog.entry, None
+    while True:
+        entries += 1
+        b = prog.blocks[blk]
+        for nid in b.lines:
+            nd = prog.nodes[nid]
+            w = nd.width
+            if nd.op == "phi":
+                val[nid] = val[[v for v, bb in nd.phi if bb == pred][0]]
+            elif nd.op in ("add", "sub", "mul"):
+                x, y = get(nd.args[0], w), get(nd.args[1], w)
+                op = {"add": lambda a, c: (a + c) % p, "sub": lambda a, c: (a - c) % p,
+                      "mul": lambda a, c: (a * c) % p}[nd.op]
+                val[nid] = [op(a, c) for a, c in zip(x, y)]
+                if nd.op == "mul" and prog.nodes[nd.args[0]].secret and prog.nodes[nd.args[1]].secret:
+                    opened.append(None)   # d, e: masked, not comparable in cleartext
+            elif nd.op == "lt":
+                val[nid] = [int(a < c) for a, c in zip(get(nd.args[0], w), get(nd.args[1], w))]
+            elif nd.op == "eq":
+                val[nid] = [int(a == c) for a, c in zip(get(nd.args[0], w), get(nd.args[1], w))]
+            elif nd.op == "reduce":
+                val[nid] = [sum(val[nd.args[0]]) % p]
+            elif nd.op == "open":
+                val[nid] = val[nd.args[0]]
+                opened.append(val[nid])
+            elif nd.op == "load":
+                s = val[nd.args[1]][0]
+                val[nid] = val[nd.args[0]][s:s + nd.imm[0]]
+            elif nd.op == "layer":
+                din, dout, _ = nd.imm
+                x, W, bb = (val[i] for i in nd.args)
+                val[nid] = [(sum(W[r * din + k] * x[k] for k in range(din)) + bb[r]) % p for r in range(dout)]
+                opened.append(None)
+        if b.term[0] == "ret":
+            break
+        if b.term[0] == "br":
+            nxt = b.term[1]
+        else:
+            nxt = b.term[2] if val[b.term[1]][0] != 0 else b.term[3]
+        pred, blk = blk, nxt
+    return val, [o for o in opened if o is not None], entries
+
+
+PROGRAMS = [("pipeline", P.pipeline(37)), ("branch", P.branch(21)), ("loop", P.loop(13, 4)),
+            ("nested", P.nested(9, 3)), ("select_shl_load", P.select_shl_load(40, 10, 7)),
+            ("revealed_branch", P.revealed_branch(11)), ("layer", P.layer(9, 7, 3)),
+            ("loop_program", P.loop_program(16, 3))]
+
+
+@pytest.mark.parametrize("p,n", [(P_PAPER, 2), (P61, 3), (P_TINY, 2)])
+@pytest.mark.parametrize("name,text", PROGRAMS)
+def test_program_reconstructs_plaintext(name, text, p, n):
+    if name == "revealed_branch" and p == P_TINY:
+        pytest.skip("its constant exceeds p = 101")
+    res = run_program(text, p, n, 5, 5)
+    plain, plain_open, entries = plain_run(text, p, 5)
+    al = sum(int(a) for a in F.from_limbs(res["alpha"].T.copy())) % p
+    for o, v in res["outputs"].items():
+        want = plain[o]
+        if isinstance(v, F.Shares):
+            got = [sum(int(v.val[i, 0, e]) for i in range(n)) % p for e in range(v.width)]
+            gotm = [sum(int(v.mac[i, 0, e]) for i in range(n)) % p for e in range(v.width)]
+            assert got == want, f"output {o}"
+            assert gotm == [al * x % p for x in want], f"output {o} MAC"
+        else:
+            assert [int(x) for x in F.from_limbs(v)] == want, f"public output {o}"
+    opened_pub = [[int(x) for x in F.from_limbs(o)] for o in res["opened"]]
+    # the plaintext of every open (the masked d, e and D, E are not comparable) appears in order
+    it = iter(opened_pub)
+    for want in plain_open:
+        assert any(got == want for got in it)
+    assert res["entries"] == entries
+    assert res["ok"] and sum(int(s) for s in F.from_limbs(res["sigma"].T.copy())) % p == 0
+
+
+def test_loop_closed_form():
+    """acc_T = x y^T + sum_{i<T} i y^(T-1-i) for the loop program, in Python integers."""
+    p, T, W = P_PAPER, 5, 7
+    res = run_program(P.loop(W, T), p, 2, 3, 3)
+    f = F.Field(p)
+    x = [int(v) for v in F.from_limbs(f.deal_values(3, 0, W))]
+    y = [int(v) for v in F.from_limbs(f.deal_values(3, 1, W))]
+    want = [(x[e] * pow(y[e], T, p) + sum(i * pow(y[e], T - 1 - i, p) for i in range(T))) % p for e in range(W)]
+    assert [int(v) for v in F.from_limbs(res["outputs"][12])] == want
+    assert res["entries"] == 1 + (T + 1) + T + 1
+
+
+def test_nested_entries_follow_the_inner_trip_counts():
+    outer = 4
+    res = run_program(P.nested(3, outer), P61, 2, 1, 1)
+    inner = sum(i + 1 for i in range(outer))
+    # entry + outer headers + outer bodies + inner headers + inner bodies + latches + exit
+    assert res["entries"] == 1 + (outer + 1) + outer + (inner + outer) + inner + outer + 1
+
+
+def test_secret_control_flow_rejected():
+    with pytest.raises(ProgramError):
+        parse(P.secret_branch(4), P_PAPER)
+
+
+@pytest.mark.parametrize("bad", [
+    "input 1 private 4 0\ninput 2 private 5 1\nblock 0\n3 = add 1 2\nret\n",        # widths
+    "input 1 private 4 0\nblock 0\n2 = lt 1 1\nret\n",                                # secret comparison
+    "input 1 public 4 0\nblock 0\n2 = open 1\nret\n",                                 # open of a public value
+    "const 1 1 200\nblock 0\nret\n",                                                  # constant not below p
+])
+def test_malformed_programs_rejected(bad):
+    with pytest.raises(ProgramError):
+        parse(bad, P_TINY)
+
+
+def test_mac_log_order_is_program_order():
+    """The first opened values of the pipeline program are the product's d and e, then w, then s."""
+    p, W = P_PAPER, 12
+    res = run_program(P.pipeline(W), p, 2, 7, 7)
+    assert [o.shape[1] for o in res["opened"]] == [W, W, W, 1]
+    plain, plain_open, _ = plain_run(P.pipeline(W), p, 7)
+    assert [int(v) for v in F.from_limbs(res["opened"][2])] == plain[7]
+    assert [int(v) for v in F.from_limbs(res["opened"][3])] == plain[8]

@@ -1,0 +1,289 @@
+"""Programs for the control-flow runtime: a data-flow graph per basic block plus
+the control-flow graph between blocks, as a compiler front end would emit them
+(Sec. III-B, "Compile-time Control-Flow Analysis").  This module holds the text
+format's definition and seeded example programs; it contains no arithmetic.
+
+Text format (one statement per line, '#' starts a comment, ids are integers):
+
+    input <id> private|public <width> <array_id>
+        secret input dealt from array <array_id>, or public input whose values are
+        element 0..width-1 of that array's value stream
+    const <id> <width> <value>          public vector, every entry <value> (0 <= value < p)
+    output <id>                         a result: the value of <id> when the program returns
+    block <bid>                         the following lines belong to block <bid>; the first
+                                        block of the file is the entry
+    <id> = add|sub|mul <a> <b>          widths equal, or one operand a public scalar
+    <id> = shl <a> <k>                  a * 2^k, k a literal (lowered, see below)
+    <id> = select <c> <t> <f>           f + c (t - f) (lowered, see below)
+    <id> = lt|eq <a> <b>                public operands only: 1 if a < b (a = b) as integers
+    <id> = reduce <a>                   sum of the elements (width 1)
+    <id> = open <a>                     reveal a secret value (public result)
+    <id> = load <base> <start> <count>  elements start .. start+count-1 of base; <start> is a
+                                        public scalar node
+    <id> = phi <v1> <b1> [<v2> <b2> ...]  value vk when the block was entered from block bk
+    <id> = layer <x> <W> <b> <din> <dout> <tile_rows>   private linear layer W x + b
+    br <bid>                            terminators: one per block, last line of the block
+    cbr <cond> <bid_true> <bid_false>   cond a public scalar; nonzero selects bid_true
+    ret
+
+A value is secret if it depends on a private input (secret inputs, and any op with a
+secret operand); lt/eq take public operands and open takes a secret one; a conditional
+branch on a secret condition is rejected (control flow must be public).  Source ids are
+below 2^14.  Lowering, part of the format's meaning (both executors apply it):
+  select(c, t, f) at id v:  v + 2^14 = sub t f;  v + 2 * 2^14 = mul c (v + 2^14);
+                            v = add f (v + 2 * 2^14)
+  shl(a, k) at id v:        v + 2^14 = const 1 (2^k mod p);  v = mul a (v + 2^14)
+in that order, in place of the original line.
+
+Semantics: blocks execute one at a time in control-flow order, the lines of a block in
+order; every line of an entered block executes once per entry.  The opened-value log
+records, in this order, each secret-by-secret product's d then e, each open's values,
+and each layer's D_t then E_t per tile.  The k-th execution of product node v (k = 0, 1,
+...) consumes the Beaver triple dealt as arrays PROG_TRIPLE0 + 3 (v + 2^16 k) (+0 a, +1 b,
++2 c); the k-th execution of layer node v the matrix-vector triples dealt from array
+PROG_TRIPLE0 + 3 (v + 2^16 k).
+"""
+from __future__ import annotations
+
+PROG_TRIPLE0 = 1 << 20
+AUX = 1 << 14
+NODE_STRIDE = 1 << 16
+MAX_BLOCK_ENTRIES = 1_000_000
+
+
+def triple_array(node: int, instance: int) -> int:
+    return PROG_TRIPLE0 + 3 * (node + NODE_STRIDE * instance)
+
+
+def pipeline(W: int) -> str:
+    """z = x y, w = z + 3x - y, s = sum z, open w and s (straight-line)."""
+    return f"""
+input 1 private {W} 0
+input 2 private {W} 1
+const 3 1 3
+output 4
+output 9
+output 10
+block 0
+4 = mul 1 2
+5 = mul 1 3
+6 = sub 4 2
+7 = add 6 5
+8 = reduce 4
+9 = open 7
+10 = open 8
+ret
+"""
+
+
+def branch(W: int, t_array: int = 2) -> str:
+    """if t < 5 (public t): r = x y else r = x + y; r merged by a phi and opened."""
+    return f"""
+input 1 private {W} 0
+input 2 private {W} 1
+input 3 public 1 {t_array}
+const 4 1 5
+output 8
+output 9
+block 0
+5 = lt 3 4
+cbr 5 1 2
+block 1
+6 = mul 1 2
+br 3
+block 2
+7 = add 1 2
+br 3
+block 3
+8 = phi 6 1 7 2
+9 = open 8
+ret
+"""
+
+
+def loop(W: int, trips: int) -> str:
+    """acc = x; for i in 0 .. trips-1: acc = acc y + i; open acc."""
+    return f"""
+input 1 private {W} 0
+input 2 private {W} 1
+const 3 1 {trips}
+const 4 1 0
+const 5 1 1
+output 6
+output 12
+block 0
+br 1
+block 1
+6 = phi 1 0 9 2
+7 = phi 4 0 10 2
+8 = lt 7 3
+cbr 8 2 3
+block 2
+11 = mul 6 2
+9 = add 11 7
+10 = add 7 5
+br 1
+block 3
+12 = open 6
+ret
+"""
+
+
+def nested(W: int, outer: int) -> str:
+    """for i < outer: for j < i + 1: acc = acc * y + x; acc opened after every outer
+    iteration (its reduction); the inner trip count depends on the outer counter."""
+    return f"""
+input 1 private {W} 0
+input 2 private {W} 1
+const 3 1 {outer}
+const 4 1 0
+const 5 1 1
+output 20
+output 31
+block 0
+br 1
+block 1
+20 = phi 1 0 24 4
+21 = phi 4 0 27 4
+22 = lt 21 3
+cbr 22 2 5
+block 2
+27 = add 21 5
+br 3
+block 3
+23 = phi 20 2 25 6
+26 = phi 4 2 28 6
+29 = lt 26 27
+cbr 29 6 4
+block 6
+30 = mul 23 2
+25 = add 30 1
+28 = add 26 5
+br 3
+block 4
+24 = add 23 4
+32 = reduce 24
+33 = open 32
+br 1
+block 5
+31 = open 20
+ret
+"""
+
+
+def select_shl_load(W: int, count: int, start: int) -> str:
+    """r = select(c, x, y) with a secret c; s = shl(r, 5); v = load(s, start, count)
+    with a public start computed from constants; u = v * open(reduce(v)) (public scalar)."""
+    return f"""
+input 1 private {W} 0
+input 2 private {W} 1
+input 3 private {W} 2
+const 4 1 {start - 1}
+const 5 1 1
+output 7
+output 10
+output 12
+block 0
+6 = select 3 1 2
+7 = shl 6 5
+8 = add 4 5
+10 = load 7 8 {count}
+11 = reduce 10
+13 = open 11
+12 = mul 10 13
+ret
+"""
+
+
+def revealed_branch(W: int) -> str:
+    """b = open(reduce(x y)); if b < p/2: out = x y - x else out = x y + y (a branch on a
+    revealed value), then one more product of the result with x."""
+    return f"""
+input 1 private {W} 0
+input 2 private {W} 1
+const 3 1 2147483646
+output 9
+output 10
+block 0
+4 = mul 1 2
+5 = reduce 4
+6 = open 5
+7 = lt 6 3
+cbr 7 1 2
+block 1
+8 = sub 4 1
+br 3
+block 2
+11 = add 4 2
+br 3
+block 3
+12 = phi 8 1 11 2
+9 = mul 12 1
+10 = open 9
+ret
+"""
+
+
+def layer(din: int, dout: int, tile_rows: int) -> str:
+    """y = W x + b (private linear layer), then z = y y opened."""
+    return f"""
+input 1 private {din} 0
+input 2 private {din * dout} 1
+input 3 private {dout} 2
+output 4
+output 6
+block 0
+4 = layer 1 2 3 {din} {dout} {tile_rows}
+5 = mul 4 4
+6 = open 5
+ret
+"""
+
+
+def secret_branch(W: int) -> str:
+    """A conditional branch on a secret value: must be rejected."""
+    return f"""
+input 1 private 1 0
+input 2 private {W} 1
+block 0
+cbr 1 1 2
+block 1
+3 = mul 2 2
+br 2
+block 2
+ret
+"""
+
+
+def loop_program(W: int, trips: int) -> str:
+    """The runtime's measured program: a loop whose body holds a batch of independent
+    products and additions of width W (an inner product pipeline over `trips` rounds):
+    acc <- acc * y + x; t <- acc * x; u <- t + y, then one open at the end."""
+    return f"""
+input 1 private {W} 0
+input 2 private {W} 1
+const 3 1 {trips}
+const 4 1 0
+const 5 1 1
+output 6
+output 15
+block 0
+br 1
+block 1
+6 = phi 1 0 9 2
+7 = phi 4 0 10 2
+8 = lt 7 3
+cbr 8 2 3
+block 2
+11 = mul 6 2
+9 = add 11 1
+12 = mul 9 1
+13 = add 12 2
+14 = mul 13 6
+10 = add 7 5
+br 1
+block 3
+16 = reduce 6
+15 = open 16
+ret
+"""
