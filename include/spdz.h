@@ -132,6 +132,18 @@ spdz_status spdz_mul_batch(spdz_ctx *ctx, const spdz_shares *x, const spdz_share
 spdz_status spdz_linear(spdz_ctx *ctx, int n_terms, const spdz_shares *terms,
                         const uint64_t *coeffs, const uint64_t *c0, spdz_shares *out);
 
+/* Local operations with a public operand (Sec. II-A: public constants join
+ * the shares of party 0, every party's MAC share takes alpha_i times them):
+ *   SPDZ_PUB_ADD   out = x + v   (party 0: x_0 + v; MAC_i + alpha_i v)
+ *   SPDZ_PUB_MUL   out = x * v   element by element (values and MAC shares times v)
+ *   SPDZ_PUB_SHARE out = v as a shared value (party 0 holds v, MAC_i = alpha_i v);
+ *                  x must be NULL.
+ * v: DEVICE [L][vwidth] canonical residues, vwidth = out->len or 1 (a scalar
+ * applied to every element).  out may alias x.  Opens nothing. */
+enum { SPDZ_PUB_ADD = 0, SPDZ_PUB_MUL = 1, SPDZ_PUB_SHARE = 2 };
+spdz_status spdz_public_op(spdz_ctx *ctx, int mode, const spdz_shares *x, const uint64_t *v, int64_t vwidth,
+                           spdz_shares *out);
+
 /* ReduceAdd (Sec. III-B, "Vectorization is first-class"): per-party sum over
  * the elements of x, values and MAC shares.  out has len 1.  Opens nothing. */
 spdz_status spdz_reduce_add(spdz_ctx *ctx, const spdz_shares *x, spdz_shares *out);
@@ -346,6 +358,56 @@ spdz_status spdz_timing_get(spdz_ctx *ctx, const char *kernel, double *total_ms,
  * the element-wise kernels are compared.  dst and src are device pointers and
  * must not overlap. */
 spdz_status spdz_copy_probe(uint64_t *dst, const uint64_t *src, int64_t words, void *hip_stream);
+
+/* ---------------------------------------------------------------------- */
+/* Programs with control flow (Sec. III-B/C): a data-flow graph per basic   */
+/* block plus the control-flow graph, run by the non-blocking scheduler of  */
+/* Algorithm 1 with the loop gating of Algorithm 2.                         */
+/* ---------------------------------------------------------------------- */
+typedef struct spdz_prog spdz_prog; /* opaque, library-owned */
+
+/* Reads a program in the text format documented with the example programs
+ * (inputs, constants, outputs, blocks of SSA statements add/sub/mul/shl/
+ * select/lt/eq/reduce/open/load/phi/layer, terminators br/cbr/ret).  select
+ * and shl are lowered to arithmetic (f + c (t - f); a product with 2^k).
+ * Rejected with SPDZ_E_INVAL and a message in err (HOST, err_len bytes,
+ * nullable): malformed text, undefined names, width mismatches, comparisons or
+ * opens that break the public/secret rules, and any conditional branch on a
+ * secret value (control flow must be public).  Allocates every node's
+ * buffers on the device (values, MAC shares, triples). */
+spdz_status spdz_prog_create(spdz_ctx *ctx, const char *text, spdz_prog **out, char *err, int64_t err_len);
+spdz_status spdz_prog_destroy(spdz_prog *prog);
+
+/* Deals the program's inputs from `seed` (secret inputs as shared arrays,
+ * public inputs as value streams), then runs it: blocks are entered along the
+ * control-flow path, ready nodes issued heavy first; the k-th execution of
+ * product node v consumes the Beaver triple of arrays 2^20 + 3 (v + 2^16 k)
+ * (dealt on the fly), of layer node v the matrix-vector triples from the same
+ * array id.  The opened values enter the log in program order (each product's
+ * d then e, each open, each layer's D_t then E_t per tile), whatever the issue
+ * order, and one MAC check over the whole run follows (*accepted, sigma_out
+ * HOST [n][L] nullable, as spdz_mac_check; a rejection aborts the context).
+ * *wall_ms (nullable): host wall time from the first block entry to the
+ * verdict.  Synchronous.  A run-time fault of the program (a load beyond its
+ * base, more than 10^6 block entries, a phi without a value for the taken
+ * edge) returns SPDZ_E_INVAL with spdz_prog_error set. */
+spdz_status spdz_prog_run(spdz_prog *prog, uint64_t seed, int *accepted, uint64_t *sigma_out, double *wall_ms);
+
+/* After a run: an output node's final value, into out_shares (secret; len =
+ * the node's width, any strides) or out_pub (public; DEVICE [L][width]).
+ * SPDZ_E_INVAL for a node that is not an output.  Synchronous. */
+spdz_status spdz_prog_output(spdz_prog *prog, int node, spdz_shares *out_shares, uint64_t *out_pub);
+
+/* Privacy and width of a node (for allocating outputs). */
+spdz_status spdz_prog_node_info(spdz_prog *prog, int node, int *secret, int64_t *width);
+
+/* Counters of the last run: block entries, kernel launches (approximate:
+ * product = dealer + product, layer = 6), host synchronisations, opened values. */
+spdz_status spdz_prog_stats(spdz_prog *prog, int64_t *block_entries, int64_t *launches, int64_t *host_syncs,
+                            int64_t *opened);
+
+/* Message of the last failure of spdz_prog_run ("" if none). */
+const char *spdz_prog_error(spdz_prog *prog);
 
 /* ---------------------------------------------------------------------- */
 /* Fake preprocessing (trusted dealer; Sec. IV-A uses fake preprocessing).  */

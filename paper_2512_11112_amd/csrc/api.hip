@@ -218,6 +218,18 @@ spdz_status spdz_linear(spdz_ctx *c, int n_terms, const spdz_shares *terms, cons
   return launch_linear(c, n_terms, terms, coeffs, c0, out);
 }
 
+spdz_status spdz_public_op(spdz_ctx *c, int mode, const spdz_shares *x, const uint64_t *v, int64_t vwidth,
+                           spdz_shares *out) {
+  SPDZ_LIVE(c);
+  if (!out || !v || mode < SPDZ_PUB_ADD || mode > SPDZ_PUB_SHARE) return SPDZ_E_INVAL;
+  if ((mode == SPDZ_PUB_SHARE) != (x == nullptr)) return SPDZ_E_INVAL;
+  SPDZ_CHECK(check_sv(c, out, out->len));
+  if (x) SPDZ_CHECK(check_sv(c, x, out->len));
+  if (vwidth != 1 && vwidth != out->len) return SPDZ_E_SHAPE;
+  if (out->len == 0) return SPDZ_OK;
+  return launch_pubop(c, mode, x, v, vwidth, out);
+}
+
 spdz_status spdz_reduce_add(spdz_ctx *c, const spdz_shares *x, spdz_shares *out) {
   SPDZ_LIVE(c);
   if (!x || !out) return SPDZ_E_INVAL;

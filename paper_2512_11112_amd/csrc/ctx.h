@@ -146,6 +146,9 @@ spdz_status launch_beaver(spdz_ctx *c, const spdz_shares *x, const spdz_shares *
 spdz_status launch_linear(spdz_ctx *c, int nt, const spdz_shares *terms, const u64 *coeffs, const u64 *c0,
                           spdz_shares *out);
 spdz_status launch_reduce(spdz_ctx *c, const spdz_shares *x, spdz_shares *out);
+// out = x + v, x * v or share(v) for a public v of width out->len or 1 (mode SPDZ_PUB_*)
+spdz_status launch_pubop(spdz_ctx *c, int mode, const spdz_shares *x, const u64 *v, int64_t vwidth,
+                         spdz_shares *out);
 spdz_status launch_reduce_finalize(spdz_ctx *c, int grid, spdz_shares *out);
 spdz_status launch_maccheck_finalize(spdz_ctx *c);
 spdz_status launch_deal_secret(spdz_ctx *c, u64 seed, u64 array_id, const u64 *values, spdz_shares *out,

@@ -109,6 +109,50 @@ __global__ __launch_bounds__(BLOCK) void k_linear(const LinArgs<F, N> A) {
 }
 
 // --------------------------------------------------------------------------
+// secret and public values together (Sec. II-A, local operations with a public
+// operand): out = x + v (party 0 adds v, every party alpha_i v to its MAC
+// share), out = x * v element by element (values and MACs scaled), or
+// out = share(v) (party 0 holds v, MAC shares alpha_i v).  v is [L][W], or a
+// public scalar broadcast when vstride = 0.
+// --------------------------------------------------------------------------
+template <class F, int N>
+struct PubArgs {
+  SV x, out;
+  const u64 *v;
+  int64_t vstride, W;
+  int mode;  // SPDZ_PUB_ADD, SPDZ_PUB_MUL, SPDZ_PUB_SHARE
+  typename F::E alpha[N];
+};
+
+template <class F, int N>
+__global__ __launch_bounds__(BLOCK) void k_pubop(const PubArgs<F, N> A) {
+  using E = typename F::E;
+  for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < A.W; e += (int64_t)gridDim.x * BLOCK) {
+    const E v = F::load_cached(A.v, A.vstride ? A.W : 1, e * A.vstride);  // limb stride W, or 1 for a scalar
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+      E ov, om;
+      if (A.mode == SPDZ_PUB_SHARE) {
+        ov = i == 0 ? v : F::zero();
+        om = F::mul(A.alpha[i], v);
+      } else {
+        const E xv = F::load_cached(A.x.val + i * A.x.ps, A.x.ls, e);
+        const E xm = F::load_cached(A.x.mac + i * A.x.ps, A.x.ls, e);
+        if (A.mode == SPDZ_PUB_MUL) {
+          ov = F::mul(xv, v);
+          om = F::mul(xm, v);
+        } else {
+          ov = i == 0 ? F::add(xv, v) : xv;
+          om = F::add(xm, F::mul(A.alpha[i], v));
+        }
+      }
+      F::store(A.out.val + i * A.out.ps, A.out.ls, e, ov);
+      F::store(A.out.mac + i * A.out.ps, A.out.ls, e, om);
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
 // ReduceAdd: per-block partials, then one-block finalisation
 // --------------------------------------------------------------------------
 template <class F, int N>
@@ -393,6 +437,26 @@ spdz_status launch_linear(spdz_ctx *c, int nt, const spdz_shares *terms, const u
     int g = grid_for(c, (const void *)k_linear<F, N>, A.W);
     KTimer tm(c, "linear");
     hipLaunchKernelGGL((k_linear<F, N>), dim3(g), dim3(BLOCK), 0, c->stream, A);
+    return hip_status(hipGetLastError());
+  });
+}
+
+spdz_status launch_pubop(spdz_ctx *c, int mode, const spdz_shares *x, const u64 *v, int64_t vwidth,
+                         spdz_shares *out) {
+  return visit(c, [&](auto f, auto nn) -> spdz_status {
+    using F = decltype(f);
+    constexpr int N = decltype(nn)::value;
+    PubArgs<F, N> A;
+    A.x = x ? sv_of(x) : SV{nullptr, nullptr, 0, 0};
+    A.out = sv_of(out);
+    A.v = v;
+    A.W = out->len;
+    A.vstride = vwidth == 1 ? 0 : 1;
+    A.mode = mode;
+    alpha_of<F, N>(c, A.alpha);
+    const int g = grid_for(c, (const void *)k_pubop<F, N>, A.W);
+    KTimer tm(c, "public_op");
+    hipLaunchKernelGGL((k_pubop<F, N>), dim3(g), dim3(BLOCK), 0, c->stream, A);
     return hip_status(hipGetLastError());
   });
 }

@@ -1,0 +1,969 @@
+// Runtime for control-flow programs (Sec. III-C, "Runtime Scheduling"): a
+// data-flow graph per basic block plus the control-flow graph between blocks,
+// in the text format of workloads/programs.py.
+//
+// Execution follows the paper's non-blocking scheduler (Algorithm 1): a node
+// becomes ready when control has entered its block and its operands' current
+// values exist; ready nodes are issued heavy first (products, opens, layers,
+// which open values), then light ones; the pending branch of the current block
+// is tried whenever it may have become takeable.  Secret operations are the
+// library's kernels, enqueued on the context stream, so a device result is
+// usable by later device work as soon as it is issued (stream order);
+// public arithmetic, comparisons and branch conditions run on the host, and a
+// public value produced on the device (an open) reaches the host at the next
+// stream synchronisation, taken only when nothing else can proceed.
+//
+// Loops (Algorithm 2): a branch in a loop is taken only when every node
+// instance entered in the loop's current iteration has been issued, so an
+// iteration's buffers are never overwritten before its readers are enqueued;
+// nested loops count towards every enclosing loop.  Control flow is public:
+// branch conditions must be public scalars (checked when the program is read).
+//
+// MAC-check order: control is one path of block entries, and each block opens
+// a statically known number of values, so at block entry every opening of the
+// block receives its position in the program-order log; out-of-order issue
+// then produces exactly the sequential program's MAC-check sums.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <new>
+#include <deque>
+#include <sstream>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "ctx.h"
+
+using namespace spdz;
+
+namespace {
+
+constexpr int AUX = 1 << 14;
+constexpr u64 NODE_STRIDE = 1 << 16;
+constexpr u64 PROG_TRIPLE0 = 1ull << 20;
+constexpr int64_t MAX_ENTRIES = 1000000;
+
+enum Op { OP_INPUT, OP_CONST, OP_ADD, OP_SUB, OP_MUL, OP_LT, OP_EQ, OP_REDUCE, OP_OPEN, OP_LOAD, OP_PHI, OP_LAYER };
+
+u64 triple_array(int node, int64_t instance) { return PROG_TRIPLE0 + 3 * ((u64)node + NODE_STRIDE * (u64)instance); }
+
+struct PNode {
+  int id = 0, op = 0;
+  std::vector<int> args;                 // operand node ids
+  std::vector<std::pair<int, int>> phi;  // (value, predecessor block)
+  std::vector<int64_t> imm;              // input array id / constant / load count / layer din, dout, tile rows
+  int64_t width = 1;
+  bool secret = false, is_private = false;
+  int block = -1;
+  int64_t log_static = 0, opens = 0;  // position of its openings inside a block entry, values opened
+  bool heavy = false, device = false;  // issued before light nodes; runs on the device
+  // buffers
+  spdz_shares sh{};      // secret value: device [n][L][width] (values, MACs)
+  u64 *dpub = nullptr;   // public value (or a secret node's public scratch): device [L][width]
+  u64 *hpub = nullptr;   // public value: pinned host [L][width]
+  spdz_triple tri{};     // product / layer triples
+  u64 *ltmp = nullptr;   // layer dealer: public A, B, C
+  // run state
+  int64_t inst = 0;
+  bool pending = false, queued = false, dev_ready = false, host_ready = false, await_host = false;
+  int64_t log_off = 0;
+  int phi_src = -1;
+  std::vector<int> users;
+};
+
+struct PBlock {
+  int id = 0;
+  std::vector<int> lines;
+  int term = 0;  // 0 ret, 1 br, 2 cbr
+  int cond = -1, t = -1, f = -1;
+  int64_t opens = 0;
+  std::vector<int> loops;  // loops containing the block
+  int inner = -1;          // innermost of them
+};
+
+struct Loop {
+  int header = -1;
+  std::vector<int> members;
+  int64_t outstanding = 0;
+};
+
+bool parse_int(const std::string &s, int64_t &v) {
+  char *end = nullptr;
+  v = strtoll(s.c_str(), &end, 10);
+  return end && *end == 0 && !s.empty();
+}
+
+}  // namespace
+
+struct spdz_prog {
+  spdz_ctx *c = nullptr;
+  std::unordered_map<int, PNode> nodes;
+  std::vector<int> decl;  // inputs and constants
+  std::unordered_map<int, PBlock> blocks;
+  std::vector<int> block_order;
+  int entry = -1;
+  std::vector<int> outputs;
+  std::vector<Loop> loops;
+  std::string err;
+  // run state and statistics
+  std::deque<int> heavy, light;
+  int cur = -1;
+  int64_t log_cur = 0, pending_total = 0, entries = 0, launches = 0, syncs = 0;
+  u64 seed = 0;
+  double wall_ms = 0;
+  bool ran = false;
+  // pinned staging for host-to-device copies of public values: every upload gets its
+  // own slice, reused only after a stream synchronisation (a node's host words may be
+  // rewritten by its next execution before an earlier copy has run)
+  u64 *arena = nullptr;
+  size_t arena_words = 0, arena_used = 0;
+};
+
+namespace {
+
+// --------------------------------------------------------------------------
+// reading the program
+// --------------------------------------------------------------------------
+spdz_status fail(spdz_prog *g, const std::string &msg) {
+  g->err = msg;
+  return SPDZ_E_INVAL;
+}
+
+// p - 1 as limbs (the coefficient of a subtraction)
+void p_minus_1(const spdz_ctx *c, u64 *out) {
+  out[0] = c->p[0] - 1;
+  if (c->L == 2) out[1] = c->p[1];
+}
+
+bool below_p(const spdz_ctx *c, u64 v) { return c->L == 2 || v < c->p[0]; }
+
+spdz_status parse(spdz_prog *g, const char *text) {
+  std::istringstream in(text);
+  std::string raw;
+  PBlock *cur = nullptr;
+  auto add_line = [&](PNode n) {
+    n.block = cur->id;
+    cur->lines.push_back(n.id);
+    g->nodes[n.id] = std::move(n);
+  };
+  int lineno = 0;
+  while (std::getline(in, raw)) {
+    lineno++;
+    const auto hash = raw.find('#');
+    if (hash != std::string::npos) raw = raw.substr(0, hash);
+    std::istringstream ls(raw);
+    std::vector<std::string> t;
+    for (std::string w; ls >> w;) t.push_back(w);
+    if (t.empty()) continue;
+    std::vector<int64_t> v;
+    auto ints = [&](size_t from) -> bool {
+      v.clear();
+      for (size_t i = from; i < t.size(); i++) {
+        int64_t x;
+        if (!parse_int(t[i], x)) return false;
+        v.push_back(x);
+      }
+      return true;
+    };
+    const std::string where = "line " + std::to_string(lineno) + ": ";
+    if (t[0] == "input") {
+      if (t.size() != 5 || (t[2] != "private" && t[2] != "public")) return fail(g, where + "input <id> private|public <width> <array>");
+      int64_t id, w, aid;
+      if (!parse_int(t[1], id) || !parse_int(t[3], w) || !parse_int(t[4], aid) || w < 1 || aid < 0 || aid >= (1 << 20))
+        return fail(g, where + "bad input");
+      PNode n;
+      n.id = (int)id, n.op = OP_INPUT, n.width = w, n.secret = n.is_private = t[2] == "private", n.imm = {aid};
+      g->nodes[n.id] = n;
+      g->decl.push_back(n.id);
+    } else if (t[0] == "const") {
+      if (t.size() != 4 || !ints(1) || v[1] < 1 || v[2] < 0 || !below_p(g->c, (u64)v[2])) return fail(g, where + "bad constant");
+      PNode n;
+      n.id = (int)v[0], n.op = OP_CONST, n.width = v[1], n.imm = {v[2]};
+      g->nodes[n.id] = n;
+      g->decl.push_back(n.id);
+    } else if (t[0] == "output") {
+      if (t.size() != 2 || !ints(1)) return fail(g, where + "bad output");
+      g->outputs.push_back((int)v[0]);
+    } else if (t[0] == "block") {
+      if (t.size() != 2 || !ints(1) || g->blocks.count((int)v[0])) return fail(g, where + "bad block");
+      PBlock b;
+      b.id = (int)v[0];
+      g->blocks[b.id] = b;
+      g->block_order.push_back(b.id);
+      cur = &g->blocks[b.id];
+    } else if (!cur) {
+      return fail(g, where + "statement outside a block");
+    } else if (t[0] == "br") {
+      if (t.size() != 2 || !ints(1)) return fail(g, where + "bad br");
+      cur->term = 1, cur->t = (int)v[0];
+    } else if (t[0] == "cbr") {
+      if (t.size() != 4 || !ints(1)) return fail(g, where + "bad cbr");
+      cur->term = 2, cur->cond = (int)v[0], cur->t = (int)v[1], cur->f = (int)v[2];
+    } else if (t[0] == "ret") {
+      cur->term = 0;
+    } else {
+      if (t.size() < 4 || t[1] != "=" || !ints(3)) return fail(g, where + "bad statement");
+      int64_t id;
+      if (!parse_int(t[0], id) || id < 0 || id >= AUX) return fail(g, where + "source ids are below 2^14");
+      const std::string &op = t[2];
+      const int nid = (int)id;
+      auto need = [&](size_t k) { return v.size() == k; };
+      PNode n;
+      n.id = nid;
+      if (op == "select") {
+        if (!need(3)) return fail(g, where + "select c t f");
+        PNode d, m;
+        d.id = nid + AUX, d.op = OP_SUB, d.args = {(int)v[1], (int)v[2]};
+        m.id = nid + 2 * AUX, m.op = OP_MUL, m.args = {(int)v[0], nid + AUX};
+        add_line(d);
+        add_line(m);
+        n.op = OP_ADD, n.args = {(int)v[2], nid + 2 * AUX};
+        add_line(n);
+      } else if (op == "shl") {
+        if (!need(2) || v[1] < 0) return fail(g, where + "shl a k");
+        PNode k;
+        k.id = nid + AUX, k.op = OP_CONST, k.width = 1;
+        // 2^k mod p, computed with the field's own arithmetic on the host
+        u64 w[2] = {0, 0};
+        visit(g->c, [&](auto f, auto) -> spdz_status {
+          using F = decltype(f);
+          typename F::E x = F::zero(), two;
+          u64 one[2] = {1, 0}, tw[2] = {2, 0};
+          x = F::from_words(one);
+          two = F::from_words(tw);
+          for (int64_t i = 0; i < v[1]; i++) x = F::mul(x, two);
+          F::to_words(x, w);
+          return SPDZ_OK;
+        });
+        k.imm = {(int64_t)w[0], (int64_t)w[1]};
+        g->nodes[k.id] = k;
+        g->decl.push_back(k.id);
+        n.op = OP_MUL, n.args = {(int)v[0], nid + AUX};
+        add_line(n);
+      } else if (op == "add" || op == "sub" || op == "mul" || op == "lt" || op == "eq") {
+        if (!need(2)) return fail(g, where + op + " a b");
+        n.op = op == "add" ? OP_ADD : op == "sub" ? OP_SUB : op == "mul" ? OP_MUL : op == "lt" ? OP_LT : OP_EQ;
+        n.args = {(int)v[0], (int)v[1]};
+        add_line(n);
+      } else if (op == "reduce" || op == "open") {
+        if (!need(1)) return fail(g, where + op + " a");
+        n.op = op == "reduce" ? OP_REDUCE : OP_OPEN, n.args = {(int)v[0]};
+        add_line(n);
+      } else if (op == "load") {
+        if (!need(3) || v[2] < 1) return fail(g, where + "load base start count");
+        n.op = OP_LOAD, n.args = {(int)v[0], (int)v[1]}, n.imm = {v[2]};
+        add_line(n);
+      } else if (op == "phi") {
+        if (v.empty() || v.size() % 2) return fail(g, where + "phi v1 b1 ...");
+        n.op = OP_PHI;
+        for (size_t i = 0; i < v.size(); i += 2) n.phi.push_back({(int)v[i], (int)v[i + 1]});
+        add_line(n);
+      } else if (op == "layer") {
+        if (!need(6) || v[3] < 1 || v[4] < 1 || v[5] < 1) return fail(g, where + "layer x W b din dout tile_rows");
+        n.op = OP_LAYER, n.args = {(int)v[0], (int)v[1], (int)v[2]}, n.imm = {v[3], v[4], v[5]};
+        add_line(n);
+      } else {
+        return fail(g, where + "unknown op " + op);
+      }
+    }
+  }
+  if (g->block_order.empty()) return fail(g, "no blocks");
+  g->entry = g->block_order[0];
+  return SPDZ_OK;
+}
+
+// widths, privacy and the program's rules (the same as the sequential interpreter's)
+spdz_status infer(spdz_prog *g) {
+  auto &N = g->nodes;
+  std::vector<int> lines;
+  for (int b : g->block_order)
+    for (int id : g->blocks[b].lines) lines.push_back(id);
+  for (int id : lines) {
+    PNode &n = N[id];
+    for (int a : n.args)
+      if (!N.count(a)) return fail(g, "node " + std::to_string(id) + " reads undefined node " + std::to_string(a));
+    for (auto &pv : n.phi)
+      if (!N.count(pv.first) || !g->blocks.count(pv.second)) return fail(g, "phi " + std::to_string(id) + ": undefined value or block");
+  }
+  for (int pass = 0; pass < 4; pass++) {
+    for (int id : lines) {
+      PNode &n = N[id];
+      switch (n.op) {
+        case OP_PHI: {
+          n.width = 0, n.secret = false;
+          for (auto &pv : n.phi) {
+            n.width = std::max(n.width, N[pv.first].width);
+            n.secret = n.secret || N[pv.first].secret;
+          }
+          break;
+        }
+        case OP_ADD:
+        case OP_SUB:
+        case OP_MUL:
+          n.width = std::max(N[n.args[0]].width, N[n.args[1]].width);
+          n.secret = N[n.args[0]].secret || N[n.args[1]].secret;
+          break;
+        case OP_LT:
+        case OP_EQ:
+          n.width = std::max(N[n.args[0]].width, N[n.args[1]].width);
+          n.secret = false;
+          break;
+        case OP_REDUCE: n.width = 1, n.secret = N[n.args[0]].secret; break;
+        case OP_OPEN: n.width = N[n.args[0]].width, n.secret = false; break;
+        case OP_LOAD: n.width = n.imm[0], n.secret = N[n.args[0]].secret; break;
+        case OP_LAYER: n.width = n.imm[1], n.secret = true; break;
+      }
+    }
+  }
+  for (int id : lines) {
+    PNode &n = N[id];
+    const std::string nm = "node " + std::to_string(id) + ": ";
+    if (n.op == OP_ADD || n.op == OP_SUB || n.op == OP_MUL) {
+      const PNode &x = N[n.args[0]], &y = N[n.args[1]];
+      if (x.width != y.width && !((!x.secret && x.width == 1) || (!y.secret && y.width == 1)))
+        return fail(g, nm + "operand widths differ");
+    }
+    if ((n.op == OP_LT || n.op == OP_EQ) && (N[n.args[0]].secret || N[n.args[1]].secret))
+      return fail(g, nm + "comparison of a secret value");
+    if (n.op == OP_OPEN && !N[n.args[0]].secret) return fail(g, nm + "open of a public value");
+    if (n.op == OP_LOAD && (N[n.args[1]].secret || N[n.args[1]].width != 1)) return fail(g, nm + "load start must be a public scalar");
+    if (n.op == OP_PHI)
+      for (auto &pv : n.phi)
+        if (N[pv.first].width != n.width) return fail(g, nm + "phi widths differ");
+    if (n.op == OP_LAYER) {
+      const PNode &x = N[n.args[0]], &W = N[n.args[1]], &b = N[n.args[2]];
+      if (x.width != n.imm[0] || W.width != n.imm[0] * n.imm[1] || b.width != n.imm[1]) return fail(g, nm + "layer shapes");
+      if (!x.secret || !W.secret || !b.secret) return fail(g, nm + "layer operands must be secret");
+      if (g->c->L != 1) return fail(g, nm + "layers need a single-limb field");
+    }
+  }
+  for (int b : g->block_order) {
+    const PBlock &B = g->blocks[b];
+    if (B.term == 2) {
+      if (!N.count(B.cond)) return fail(g, "block " + std::to_string(b) + ": undefined condition");
+      if (N[B.cond].secret || N[B.cond].width != 1)
+        return fail(g, "block " + std::to_string(b) + ": branch on a secret or non-scalar condition");
+    }
+    if (B.term >= 1 && (!g->blocks.count(B.t) || (B.term == 2 && !g->blocks.count(B.f))))
+      return fail(g, "block " + std::to_string(b) + ": branch to an undefined block");
+  }
+  for (int o : g->outputs)
+    if (!N.count(o)) return fail(g, "output " + std::to_string(o) + " undefined");
+  // per node: users, what it opens, where it runs; per block: the log layout
+  for (int b : g->block_order) {
+    PBlock &B = g->blocks[b];
+    for (int id : B.lines) {
+      PNode &n = N[id];
+      for (int a : n.args) N[a].users.push_back(id);
+      for (auto &pv : n.phi) N[pv.first].users.push_back(id);
+      const bool ss = n.op == OP_MUL && N[n.args[0]].secret && N[n.args[1]].secret;
+      if (ss) n.opens = 2 * n.width;
+      if (n.op == OP_OPEN) n.opens = n.width;
+      if (n.op == OP_LAYER) {
+        const int64_t din = n.imm[0], dout = n.imm[1], tiles = (dout + n.imm[2] - 1) / n.imm[2];
+        n.opens = dout * din + tiles * din;
+      }
+      n.log_static = B.opens;
+      B.opens += n.opens;
+      n.heavy = ss || n.op == OP_OPEN || n.op == OP_LAYER;
+      n.device = n.secret || n.op == OP_OPEN;
+    }
+  }
+  return SPDZ_OK;
+}
+
+// natural loops of the back edges found by a depth-first walk from the entry block
+void find_loops(spdz_prog *g) {
+  std::unordered_map<int, std::vector<int>> succ, pred;
+  for (int b : g->block_order) {
+    const PBlock &B = g->blocks[b];
+    if (B.term >= 1) succ[b].push_back(B.t);
+    if (B.term == 2 && B.f != B.t) succ[b].push_back(B.f);
+    for (int s : succ[b]) pred[s].push_back(b);
+  }
+  std::unordered_map<int, int> state;  // 0 new, 1 on stack, 2 done
+  std::vector<std::pair<int, int>> back;
+  std::vector<std::pair<int, size_t>> stack{{g->entry, 0}};
+  state[g->entry] = 1;
+  while (!stack.empty()) {
+    auto &top = stack.back();
+    const auto &ss = succ[top.first];
+    if (top.second < ss.size()) {
+      const int s = ss[top.second++];
+      if (state[s] == 1) back.push_back({top.first, s});
+      else if (state[s] == 0) {
+        state[s] = 1;
+        stack.push_back({s, 0});
+      }
+    } else {
+      state[top.first] = 2;
+      stack.pop_back();
+    }
+  }
+  std::unordered_map<int, int> by_header;
+  for (auto &e : back) {
+    const int latch = e.first, h = e.second;
+    if (!by_header.count(h)) {
+      by_header[h] = (int)g->loops.size();
+      Loop L;
+      L.header = h;
+      L.members = {h};
+      g->loops.push_back(L);
+    }
+    Loop &L = g->loops[by_header[h]];
+    std::vector<int> work{latch};
+    while (!work.empty()) {
+      const int b = work.back();
+      work.pop_back();
+      if (std::find(L.members.begin(), L.members.end(), b) != L.members.end()) continue;
+      L.members.push_back(b);
+      for (int q : pred[b]) work.push_back(q);
+    }
+  }
+  for (size_t i = 0; i < g->loops.size(); i++)
+    for (int b : g->loops[i].members) g->blocks[b].loops.push_back((int)i);
+  for (auto &kv : g->blocks) {
+    PBlock &B = kv.second;
+    size_t best = SIZE_MAX;
+    for (int l : B.loops)
+      if (g->loops[l].members.size() < best) best = g->loops[l].members.size(), B.inner = l;
+  }
+}
+
+// --------------------------------------------------------------------------
+// buffers
+// --------------------------------------------------------------------------
+spdz_status alloc_shares(spdz_prog *g, spdz_shares &s, int64_t w) {
+  const spdz_ctx *c = g->c;
+  const size_t words = (size_t)c->n * c->L * w;
+  u64 *v = nullptr, *m = nullptr;
+  if (hipMalloc((void **)&v, words * 8) != hipSuccess) return SPDZ_E_NOMEM;
+  if (hipMalloc((void **)&m, words * 8) != hipSuccess) {
+    hipFree(v);
+    return SPDZ_E_NOMEM;
+  }
+  s = spdz_shares{v, m, w, c->L * w, w};
+  return SPDZ_OK;
+}
+
+void free_shares(spdz_shares &s) {
+  if (s.val) hipFree(s.val);
+  if (s.mac) hipFree(s.mac);
+  s = spdz_shares{};
+}
+
+spdz_status alloc_buffers(spdz_prog *g) {
+  const spdz_ctx *c = g->c;
+  for (auto &kv : g->nodes) {
+    PNode &n = kv.second;
+    if (n.secret) SPDZ_RET(alloc_shares(g, n.sh, n.width));
+    // public values, and a public scratch for secret nodes with a public operand
+    if (hipMalloc((void **)&n.dpub, (size_t)c->L * n.width * 8) != hipSuccess) return SPDZ_E_NOMEM;
+    if (!n.secret && hipHostMalloc((void **)&n.hpub, (size_t)c->L * n.width * 8, hipHostMallocDefault) != hipSuccess)
+      return SPDZ_E_NOMEM;
+    const bool ss = n.op == OP_MUL && g->nodes[n.args[0]].secret && g->nodes[n.args[1]].secret;
+    if (ss) {
+      SPDZ_RET(alloc_shares(g, n.tri.a, n.width));
+      SPDZ_RET(alloc_shares(g, n.tri.b, n.width));
+      SPDZ_RET(alloc_shares(g, n.tri.c, n.width));
+    }
+    if (n.op == OP_LAYER) {
+      const int64_t din = n.imm[0], dout = n.imm[1], tiles = (dout + n.imm[2] - 1) / n.imm[2];
+      SPDZ_RET(alloc_shares(g, n.tri.a, dout * din));
+      SPDZ_RET(alloc_shares(g, n.tri.b, tiles * din));
+      SPDZ_RET(alloc_shares(g, n.tri.c, dout));
+      if (hipMalloc((void **)&n.ltmp, (size_t)(dout * din + tiles * din + dout) * 8) != hipSuccess) return SPDZ_E_NOMEM;
+    }
+  }
+  return SPDZ_OK;
+}
+
+// --------------------------------------------------------------------------
+// host arithmetic on public values ([L][w] words, a width-1 operand broadcast)
+// --------------------------------------------------------------------------
+template <class F>
+void host_binop(int op, const u64 *a, int64_t wa, const u64 *b, int64_t wb, u64 *out, int64_t w) {
+  for (int64_t e = 0; e < w; e++) {
+    u64 xa[2], xb[2], r[2] = {0, 0};
+    for (int l = 0; l < F::L; l++) {
+      xa[l] = a[l * wa + (wa == 1 ? 0 : e)];
+      xb[l] = b[l * wb + (wb == 1 ? 0 : e)];
+    }
+    const typename F::E x = F::from_words(xa), y = F::from_words(xb);
+    switch (op) {
+      case OP_ADD: F::to_words(F::add(x, y), r); break;
+      case OP_SUB: F::to_words(F::sub(x, y), r); break;
+      case OP_MUL: F::to_words(F::mul(x, y), r); break;
+      case OP_LT:
+      case OP_EQ: {
+        const bool hi_lt = F::L == 2 && xa[1] != xb[1];
+        const bool lt = hi_lt ? xa[1] < xb[1] : xa[0] < xb[0];
+        const bool eq = xa[0] == xb[0] && (F::L == 1 || xa[1] == xb[1]);
+        r[0] = op == OP_LT ? lt : eq;
+        break;
+      }
+    }
+    for (int l = 0; l < F::L; l++) out[l * w + e] = r[l];
+  }
+}
+
+template <class F>
+void host_reduce(const u64 *a, int64_t w, u64 *out) {
+  typename F::E s = F::zero();
+  for (int64_t e = 0; e < w; e++) {
+    u64 x[2];
+    for (int l = 0; l < F::L; l++) x[l] = a[l * w + e];
+    s = F::add(s, F::from_words(x));
+  }
+  F::to_words(s, out);  // [L][1]
+}
+
+// --------------------------------------------------------------------------
+// the scheduler
+// --------------------------------------------------------------------------
+bool uses_host(const PNode &n) { return !n.device; }
+
+bool ready(spdz_prog *g, const PNode &n) {
+  auto &N = g->nodes;
+  if (n.op == OP_PHI) {
+    const PNode &s = N[n.phi_src];
+    return n.secret ? s.dev_ready : s.host_ready;
+  }
+  if (n.op == OP_LOAD) {
+    const PNode &base = N[n.args[0]], &start = N[n.args[1]];
+    return start.host_ready && (n.secret ? base.dev_ready : base.host_ready);
+  }
+  for (int a : n.args) {
+    const PNode &x = N[a];
+    if (uses_host(n) ? !x.host_ready : !x.dev_ready) return false;
+  }
+  return true;
+}
+
+void enqueue(spdz_prog *g, PNode &n) {
+  if (!n.pending || n.queued || !ready(g, n)) return;
+  n.queued = true;
+  (n.heavy ? g->heavy : g->light).push_back(n.id);
+}
+
+spdz_status enter_block(spdz_prog *g, int dst, int pred) {
+  if (++g->entries > MAX_ENTRIES) return fail(g, "too many block entries");
+  PBlock &B = g->blocks[dst];
+  auto &N = g->nodes;
+  for (int id : B.lines) {
+    PNode &n = N[id];
+    if (n.pending) return fail(g, "block " + std::to_string(dst) + " re-entered before node " + std::to_string(id) + " ran");
+    n.inst++;
+    n.pending = true;
+    n.queued = n.dev_ready = n.host_ready = n.await_host = false;
+    n.log_off = g->log_cur + n.log_static;
+    if (n.op == OP_PHI) {
+      n.phi_src = -1;
+      for (auto &pv : n.phi)
+        if (pv.second == pred) {
+          n.phi_src = pv.first;
+          break;
+        }
+      if (n.phi_src < 0) return fail(g, "phi " + std::to_string(id) + ": no value for predecessor block " + std::to_string(pred));
+    }
+    g->pending_total++;
+    for (int l : B.loops) g->loops[l].outstanding++;
+  }
+  g->log_cur += B.opens;
+  g->cur = dst;
+  for (int id : B.lines) enqueue(g, N[id]);
+  return SPDZ_OK;
+}
+
+spdz_status stream_sync(spdz_prog *g) {
+  SPDZ_RET(hip_status(hipStreamSynchronize(g->c->stream)));
+  g->syncs++;
+  g->arena_used = 0;
+  return SPDZ_OK;
+}
+
+// copy `words` host words to device `dst` through a fresh slice of the staging arena
+spdz_status upload_words(spdz_prog *g, u64 *dst, const u64 *src, size_t words) {
+  if (g->arena_used + words > g->arena_words) {
+    SPDZ_RET(stream_sync(g));
+    if (words > g->arena_words) {
+      if (g->arena) hipHostFree(g->arena);
+      g->arena = nullptr;
+      g->arena_words = std::max(words, (size_t)1 << 20);
+      if (hipHostMalloc((void **)&g->arena, g->arena_words * 8, hipHostMallocDefault) != hipSuccess) {
+        g->arena_words = 0;
+        return SPDZ_E_NOMEM;
+      }
+    }
+  }
+  u64 *slice = g->arena + g->arena_used;
+  std::memcpy(slice, src, words * 8);
+  g->arena_used += words;
+  return hip_status(hipMemcpyAsync(dst, slice, words * 8, hipMemcpyHostToDevice, g->c->stream));
+}
+
+// the device copy of a public node's host words (stream-ordered)
+spdz_status upload(spdz_prog *g, PNode &n) { return upload_words(g, n.dpub, n.hpub, (size_t)g->c->L * n.width); }
+
+spdz_status copy_shares(spdz_prog *g, const spdz_shares &src, int64_t first, spdz_shares &dst) {
+  const spdz_ctx *c = g->c;
+  // planes [party][limb] are spaced by the node width in both buffers
+  for (u64 *const *pp : {&src.val, &src.mac}) {
+    const u64 *s = *pp + first;
+    u64 *d = pp == &src.val ? dst.val : dst.mac;
+    if (hipMemcpy2DAsync(d, dst.len * 8, s, src.len * 8, dst.len * 8, (size_t)c->n * c->L, hipMemcpyDeviceToDevice,
+                         c->stream) != hipSuccess)
+      return SPDZ_E_HIP;
+  }
+  return SPDZ_OK;
+}
+
+spdz_status issue(spdz_prog *g, PNode &n) {
+  spdz_ctx *c = g->c;
+  auto &N = g->nodes;
+  const int L = c->L;
+  n.pending = false;
+  g->pending_total--;
+  for (int l : g->blocks[n.block].loops) g->loops[l].outstanding--;
+  spdz_status st = SPDZ_OK;
+  auto host_visit = [&](auto fn) {
+    switch (c->fid) {
+      case FID_61: fn(F61{}); break;
+      case FID_127: fn(F127{}); break;
+      default: fn(F32{}); break;
+    }
+  };
+  switch (n.op) {
+    case OP_ADD:
+    case OP_SUB:
+    case OP_MUL: {
+      PNode &a = N[n.args[0]], &b = N[n.args[1]];
+      if (!n.secret) {
+        host_visit([&](auto f) { host_binop<decltype(f)>(n.op, a.hpub, a.width, b.hpub, b.width, n.hpub, n.width); });
+        st = upload(g, n);
+      } else if (a.secret && b.secret) {
+        if (n.op == OP_MUL) {
+          st = launch_deal_triple(c, g->seed, triple_array(n.id, n.inst - 1), &n.tri);
+          c->log_count = n.log_off;
+          if (st == SPDZ_OK)
+            st = launch_beaver(c, &a.sh, &b.sh, &n.tri, &n.sh, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+          g->launches += 2;
+        } else {
+          const spdz_shares terms[2] = {a.sh, b.sh};
+          u64 cf[4] = {0, 0, 0, 0};  // [term][L]: 1, then 1 or p - 1
+          cf[0] = 1;
+          if (n.op == OP_SUB) p_minus_1(c, cf + L);
+          else cf[L] = 1;
+          st = launch_linear(c, 2, terms, cf, nullptr, &n.sh);
+          g->launches++;
+        }
+      } else {
+        PNode &s = a.secret ? a : b, &pb = a.secret ? b : a;
+        if (n.op == OP_MUL) {
+          st = launch_pubop(c, SPDZ_PUB_MUL, &s.sh, pb.dpub, pb.width, &n.sh);
+        } else if (n.op == OP_ADD) {
+          st = launch_pubop(c, SPDZ_PUB_ADD, &s.sh, pb.dpub, pb.width, &n.sh);
+        } else if (a.secret) {  // secret - public: add the negated public value (host, then upload)
+          std::vector<u64> neg((size_t)L * pb.width, 0);
+          host_visit([&](auto f) {
+            host_binop<decltype(f)>(OP_SUB, neg.data(), pb.width, pb.hpub, pb.width, neg.data(), pb.width);
+          });
+          st = upload_words(g, n.dpub, neg.data(), neg.size());
+          if (st == SPDZ_OK) st = launch_pubop(c, SPDZ_PUB_ADD, &s.sh, n.dpub, pb.width, &n.sh);
+        } else {  // public - secret = -secret + public
+          u64 cf[2];
+          p_minus_1(c, cf);
+          st = launch_linear(c, 1, &s.sh, cf, nullptr, &n.sh);
+          if (st == SPDZ_OK) st = launch_pubop(c, SPDZ_PUB_ADD, &n.sh, pb.dpub, pb.width, &n.sh);
+        }
+        g->launches++;
+      }
+      break;
+    }
+    case OP_LT:
+    case OP_EQ: {
+      PNode &a = N[n.args[0]], &b = N[n.args[1]];
+      host_visit([&](auto f) { host_binop<decltype(f)>(n.op, a.hpub, a.width, b.hpub, b.width, n.hpub, n.width); });
+      st = upload(g, n);
+      break;
+    }
+    case OP_REDUCE: {
+      PNode &a = N[n.args[0]];
+      if (n.secret) {
+        st = launch_reduce(c, &a.sh, &n.sh);
+        g->launches += 2;
+      } else {
+        host_visit([&](auto f) { host_reduce<decltype(f)>(a.hpub, a.width, n.hpub); });
+        st = upload(g, n);
+      }
+      break;
+    }
+    case OP_OPEN: {
+      PNode &a = N[n.args[0]];
+      c->log_count = n.log_off;
+      st = launch_open(c, &a.sh, n.dpub);
+      if (st == SPDZ_OK)
+        st = hip_status(hipMemcpyAsync(n.hpub, n.dpub, (size_t)L * n.width * 8, hipMemcpyDeviceToHost, c->stream));
+      n.await_host = true;
+      g->launches++;
+      break;
+    }
+    case OP_LOAD: {
+      PNode &base = N[n.args[0]], &start = N[n.args[1]];
+      const u64 s0 = start.hpub[0];
+      if ((L == 2 && start.hpub[1] != 0) || s0 > (u64)base.width || (int64_t)s0 + n.width > base.width)
+        return fail(g, "load " + std::to_string(n.id) + ": elements beyond the width of node " + std::to_string(base.id));
+      if (n.secret) {
+        st = copy_shares(g, base.sh, (int64_t)s0, n.sh);
+      } else {
+        for (int l = 0; l < L; l++)
+          for (int64_t e = 0; e < n.width; e++) n.hpub[l * n.width + e] = base.hpub[l * base.width + s0 + e];
+        st = upload(g, n);
+      }
+      break;
+    }
+    case OP_PHI: {
+      PNode &s = N[n.phi_src];
+      if (!n.secret) {
+        std::memcpy(n.hpub, s.hpub, (size_t)L * n.width * 8);
+        st = upload(g, n);
+      } else if (s.secret) {
+        st = copy_shares(g, s.sh, 0, n.sh);
+      } else {
+        st = launch_pubop(c, SPDZ_PUB_SHARE, nullptr, s.dpub, s.width, &n.sh);
+        g->launches++;
+      }
+      break;
+    }
+    case OP_LAYER: {
+      PNode &x = N[n.args[0]], &W = N[n.args[1]], &b = N[n.args[2]];
+      const int64_t din = n.imm[0], dout = n.imm[1], tr = n.imm[2], tiles = (dout + tr - 1) / tr;
+      const u64 aid = triple_array(n.id, n.inst - 1);
+      u64 *av = n.ltmp, *bv = av + dout * din, *cv = bv + tiles * din;
+      st = launch_deal_secret(c, g->seed, aid, nullptr, &n.tri.a, av);
+      if (st == SPDZ_OK) st = launch_deal_secret(c, g->seed, aid + 1, nullptr, &n.tri.b, bv);
+      if (st == SPDZ_OK) st = launch_public_matvec(c, dout, din, tr, av, bv, cv);
+      if (st == SPDZ_OK) st = launch_deal_secret(c, g->seed, aid + 2, cv, &n.tri.c, nullptr);
+      c->log_count = n.log_off;
+      if (st == SPDZ_OK) st = launch_linear_layer(c, dout, din, tr, &W.sh, &x.sh, &b.sh, &n.tri, &n.sh, nullptr, nullptr);
+      g->launches += 6;
+      break;
+    }
+    default: return fail(g, "cannot issue node " + std::to_string(n.id));
+  }
+  if (st != SPDZ_OK) return st;
+  n.dev_ready = true;
+  if (!n.device) n.host_ready = true;
+  for (int u : n.users) enqueue(g, N[u]);
+  return SPDZ_OK;
+}
+
+// Algorithm 2's TryBranchOnce for the current block's terminator; *done on return
+spdz_status try_branch(spdz_prog *g, bool &taken, bool &done) {
+  taken = done = false;
+  PBlock &B = g->blocks[g->cur];
+  if (B.term == 0) {
+    done = g->pending_total == 0;
+    return SPDZ_OK;
+  }
+  if (B.inner >= 0 && g->loops[B.inner].outstanding > 0) return SPDZ_OK;  // iteration not fully issued
+  int dst = B.t;
+  if (B.term == 2) {
+    const PNode &cnd = g->nodes[B.cond];
+    if (!cnd.host_ready) return SPDZ_OK;
+    const bool nz = cnd.hpub[0] != 0 || (g->c->L == 2 && cnd.hpub[1] != 0);
+    dst = nz ? B.t : B.f;
+  }
+  taken = true;
+  return enter_block(g, dst, B.id);
+}
+
+spdz_status run(spdz_prog *g) {
+  auto &N = g->nodes;
+  spdz_ctx *c = g->c;
+  g->heavy.clear();
+  g->light.clear();
+  g->log_cur = g->pending_total = g->entries = g->launches = g->syncs = 0;
+  g->arena_used = 0;  // deal_inputs ended with a synchronisation
+  for (auto &l : g->loops) l.outstanding = 0;
+  for (auto &kv : N) {
+    PNode &n = kv.second;
+    n.inst = 0;
+    n.pending = n.queued = n.await_host = false;
+    const bool leaf = n.op == OP_INPUT || n.op == OP_CONST;
+    n.dev_ready = n.host_ready = leaf && !n.secret;
+    if (leaf && n.secret) n.dev_ready = true;
+  }
+  SPDZ_RET(enter_block(g, g->entry, -1));
+  for (;;) {
+    bool progress = false;
+    while (!g->heavy.empty() || !g->light.empty()) {
+      std::deque<int> &q = !g->heavy.empty() ? g->heavy : g->light;
+      const int id = q.front();
+      q.pop_front();
+      N[id].queued = false;
+      SPDZ_RET(issue(g, N[id]));
+      progress = true;
+    }
+    bool taken, done;
+    SPDZ_RET(try_branch(g, taken, done));
+    if (done) break;
+    if (taken) continue;
+    if (!progress) {
+      // only host values of opens can unblock: wait for the stream
+      bool waiting = false;
+      for (auto &kv : N) waiting = waiting || kv.second.await_host;
+      if (!waiting) return fail(g, "no node can proceed");
+      SPDZ_RET(stream_sync(g));
+      for (auto &kv : N)
+        if (kv.second.await_host) {
+          kv.second.await_host = false;
+          kv.second.host_ready = true;
+          for (int u : kv.second.users) enqueue(g, N[u]);
+        }
+    }
+  }
+  c->log_count = g->log_cur;
+  return SPDZ_OK;
+}
+
+spdz_status deal_inputs(spdz_prog *g) {
+  spdz_ctx *c = g->c;
+  for (int id : g->decl) {
+    PNode &n = g->nodes[id];
+    if (n.op == OP_INPUT && n.secret) {
+      SPDZ_RET(launch_deal_secret(c, g->seed, (u64)n.imm[0], nullptr, &n.sh, nullptr));
+    } else {
+      // public input: elements of the array's value stream; constant: every entry the value
+      visit(c, [&](auto f, auto) -> spdz_status {
+        using F = decltype(f);
+        const u64 st = sm_out(g->seed, stream_id(TAG_VALUE, n.op == OP_INPUT ? (u64)n.imm[0] : 0, 0));
+        for (int64_t e = 0; e < n.width; e++) {
+          u64 w[2] = {0, 0};
+          if (n.op == OP_INPUT) {
+            F::to_words(uniform_elem<F>(st, (u64)e), w);
+          } else {
+            w[0] = (u64)n.imm[0];
+            w[1] = n.imm.size() > 1 ? (u64)n.imm[1] : 0;
+          }
+          for (int l = 0; l < F::L; l++) n.hpub[l * n.width + e] = w[l];
+        }
+        return SPDZ_OK;
+      });
+      SPDZ_RET(upload(g, n));
+    }
+  }
+  return stream_sync(g);
+}
+
+void destroy(spdz_prog *g) {
+  if (g->arena) hipHostFree(g->arena);
+  for (auto &kv : g->nodes) {
+    PNode &n = kv.second;
+    free_shares(n.sh);
+    free_shares(n.tri.a);
+    free_shares(n.tri.b);
+    free_shares(n.tri.c);
+    if (n.dpub) hipFree(n.dpub);
+    if (n.hpub) hipHostFree(n.hpub);
+    if (n.ltmp) hipFree(n.ltmp);
+  }
+  delete g;
+}
+
+}  // namespace
+
+// ==========================================================================
+// C-ABI
+// ==========================================================================
+spdz_status spdz_prog_create(spdz_ctx *c, const char *text, spdz_prog **out, char *err, int64_t err_len) {
+  if (!c || !text || !out) return SPDZ_E_INVAL;
+  *out = nullptr;
+  if (c->aborted) return SPDZ_E_ABORTED;
+  spdz_prog *g = new (std::nothrow) spdz_prog();
+  if (!g) return SPDZ_E_NOMEM;
+  g->c = c;
+  spdz_status st = parse(g, text);
+  if (st == SPDZ_OK) st = infer(g);
+  if (st == SPDZ_OK) {
+    find_loops(g);
+    st = alloc_buffers(g);
+  }
+  if (st != SPDZ_OK) {
+    if (err && err_len > 0) {
+      std::strncpy(err, g->err.c_str(), (size_t)err_len - 1);
+      err[err_len - 1] = 0;
+    }
+    destroy(g);
+    return st;
+  }
+  *out = g;
+  return SPDZ_OK;
+}
+
+spdz_status spdz_prog_destroy(spdz_prog *g) {
+  if (!g) return SPDZ_E_INVAL;
+  (void)hipStreamSynchronize(g->c->stream);
+  destroy(g);
+  return SPDZ_OK;
+}
+
+spdz_status spdz_prog_run(spdz_prog *g, uint64_t seed, int *accepted, uint64_t *sigma_out, double *wall_ms) {
+  if (!g || !accepted) return SPDZ_E_INVAL;
+  *accepted = 0;
+  if (g->c->aborted) return SPDZ_E_ABORTED;
+  g->seed = seed;
+  g->err.clear();
+  SPDZ_RET(deal_inputs(g));
+  const auto t0 = std::chrono::steady_clock::now();
+  SPDZ_RET(run(g));
+  const spdz_status st = spdz_mac_check(g->c, accepted, sigma_out);
+  const auto t1 = std::chrono::steady_clock::now();
+  g->wall_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  if (wall_ms) *wall_ms = g->wall_ms;
+  g->ran = true;
+  return st;
+}
+
+spdz_status spdz_prog_output(spdz_prog *g, int node, spdz_shares *out_shares, uint64_t *out_pub) {
+  if (!g || !g->ran) return SPDZ_E_INVAL;
+  if (std::find(g->outputs.begin(), g->outputs.end(), node) == g->outputs.end()) return SPDZ_E_INVAL;
+  PNode &n = g->nodes[node];
+  spdz_ctx *c = g->c;
+  if (n.secret) {
+    if (!out_shares || out_shares->len != n.width) return SPDZ_E_SHAPE;
+    for (int i = 0; i < c->n; i++)
+      for (int l = 0; l < c->L; l++) {
+        const size_t so = ((size_t)i * c->L + l) * n.width;
+        const size_t dof = (size_t)i * out_shares->party_stride + (size_t)l * out_shares->limb_stride;
+        if (hipMemcpyAsync(out_shares->val + dof, n.sh.val + so, n.width * 8, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+            hipMemcpyAsync(out_shares->mac + dof, n.sh.mac + so, n.width * 8, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+          return SPDZ_E_HIP;
+      }
+  } else {
+    if (!out_pub) return SPDZ_E_INVAL;
+    if (hipMemcpyAsync(out_pub, n.dpub, (size_t)c->L * n.width * 8, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+      return SPDZ_E_HIP;
+  }
+  return hip_status(hipStreamSynchronize(c->stream));
+}
+
+spdz_status spdz_prog_node_info(spdz_prog *g, int node, int *secret, int64_t *width) {
+  if (!g || !secret || !width || !g->nodes.count(node)) return SPDZ_E_INVAL;
+  *secret = g->nodes[node].secret;
+  *width = g->nodes[node].width;
+  return SPDZ_OK;
+}
+
+spdz_status spdz_prog_stats(spdz_prog *g, int64_t *block_entries, int64_t *launches, int64_t *host_syncs,
+                            int64_t *opened) {
+  if (!g) return SPDZ_E_INVAL;
+  if (block_entries) *block_entries = g->entries;
+  if (launches) *launches = g->launches;
+  if (host_syncs) *host_syncs = g->syncs;
+  if (opened) *opened = g->log_cur;
+  return SPDZ_OK;
+}
+
+const char *spdz_prog_error(spdz_prog *g) { return g ? g->err.c_str() : ""; }

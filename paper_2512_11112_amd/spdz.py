@@ -77,6 +77,15 @@ def lib() -> ctypes.CDLL:
                                               ctypes.POINTER(Triple)]),
             "spdz_deal_matrix_triple": (i32, [vp, ctypes.c_uint64, ctypes.c_uint64, i64, i64, i64,
                                               ctypes.POINTER(Triple)]),
+            "spdz_public_op": (i32, [vp, i32, ctypes.POINTER(Shares), vp, i64, ctypes.POINTER(Shares)]),
+            "spdz_prog_create": (i32, [vp, ctypes.c_char_p, ctypes.POINTER(vp), ctypes.c_char_p, i64]),
+            "spdz_prog_destroy": (i32, [vp]),
+            "spdz_prog_run": (i32, [vp, ctypes.c_uint64, ctypes.POINTER(i32), u64p, ctypes.POINTER(ctypes.c_double)]),
+            "spdz_prog_output": (i32, [vp, i32, ctypes.POINTER(Shares), vp]),
+            "spdz_prog_node_info": (i32, [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_int64)]),
+            "spdz_prog_stats": (i32, [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+            "spdz_prog_error": (ctypes.c_char_p, [vp]),
             "spdz_dag_create": (i32, [vp, i32, ctypes.POINTER(ctypes.c_int64), i64, vp, ctypes.POINTER(vp)]),
             "spdz_dag_destroy": (i32, [vp]),
             "spdz_dag_node": (i32, [vp, i64, ctypes.POINTER(Shares)]),
@@ -388,6 +397,81 @@ def dag_op_dtype():
                                  ("src1", np.int64), ("off1", np.int64), ("src2", np.int64),
                                  ("off2", np.int64), ("konst", np.uint64)])
     return DAG_OP_DTYPE
+
+
+SPDZ_PUB_ADD, SPDZ_PUB_MUL, SPDZ_PUB_SHARE = 0, 1, 2
+
+
+def public_op(ctx: "Context", mode: int, x: Optional[ShareTensor], v: torch.Tensor, out: ShareTensor) -> ShareTensor:
+    """out = x + v, x * v (element-wise) or share(v); v is a [L][W] or [L][1] device tensor."""
+    dx = x.desc() if x is not None else None
+    do = out.desc()
+    _check(lib().spdz_public_op(ctx._h, mode, ctypes.byref(dx) if dx is not None else None, _ptr(v), v.shape[-1],
+                                ctypes.byref(do)), "spdz_public_op")
+    return out
+
+
+class ProgramError(Exception):
+    pass
+
+
+class Program:
+    """A control-flow program (text format of workloads.programs) on a context."""
+
+    def __init__(self, ctx: "Context", text: str):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        err = ctypes.create_string_buffer(512)
+        st = lib().spdz_prog_create(ctx._h, text.encode(), ctypes.byref(h), err, 512)
+        if st != SPDZ_OK:
+            raise ProgramError(f"spdz_prog_create: {status_str(st)}: {err.value.decode()}")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().spdz_prog_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, seed: int):
+        """(accepted, [sigma_i as ints], wall_ms)."""
+        acc = ctypes.c_int(0)
+        n, L = self.ctx.n, self.ctx.L
+        sig = (ctypes.c_uint64 * (n * L))()
+        ms = ctypes.c_double(0)
+        st = lib().spdz_prog_run(self._h, ctypes.c_uint64(seed), ctypes.byref(acc), sig, ctypes.byref(ms))
+        if st not in (SPDZ_OK, SPDZ_MAC_REJECT):
+            msg = lib().spdz_prog_error(self._h)
+            raise SpdzError(st, f"spdz_prog_run: {msg.decode() if msg else ''}")
+        sigma = [sum(int(sig[i * L + l]) << (64 * l) for l in range(L)) for i in range(n)]
+        return bool(acc.value) and st == SPDZ_OK, sigma, ms.value
+
+    def info(self, node: int):
+        sec, w = ctypes.c_int(0), ctypes.c_int64(0)
+        _check(lib().spdz_prog_node_info(self._h, node, ctypes.byref(sec), ctypes.byref(w)), "spdz_prog_node_info")
+        return bool(sec.value), int(w.value)
+
+    def output(self, node: int):
+        """ShareTensor for a secret output, a [L][width] device tensor for a public one."""
+        secret, w = self.info(node)
+        if secret:
+            out = self.ctx.new_shares(w)
+            d = out.desc()
+            _check(lib().spdz_prog_output(self._h, node, ctypes.byref(d), None), "spdz_prog_output")
+        else:
+            out = self.ctx.new_public(w)
+            _check(lib().spdz_prog_output(self._h, node, None, _ptr(out)), "spdz_prog_output")
+        return out
+
+    def stats(self):
+        v = [ctypes.c_int64(0) for _ in range(4)]
+        _check(lib().spdz_prog_stats(self._h, *[ctypes.byref(x) for x in v]), "spdz_prog_stats")
+        return dict(zip(("block_entries", "launches", "host_syncs", "opened"), (int(x.value) for x in v)))
 
 
 class Dag:

@@ -1,0 +1,114 @@
+"""Parity of the control-flow runtime (non-blocking scheduler over the GPU
+kernels) with the sequential interpreter of the oracle: every output's shares
+or public values, every sigma_i and the verdict, bit for bit, and the number of
+block entries; plus the public-operand kernel and the runtime's errors."""
+import numpy as np
+import pytest
+import torch
+
+import oracle.fast as F
+from oracle.program import Exec, parse, run_program
+from tests._util import dev, host, ints_of_sigma, share_to_dev
+from workloads import P61, P127, P_PAPER, programs as P
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2512_11112_amd import spdz
+    spdz.lib()
+
+
+def ctx_for(p, n, seed, check_seed):
+    from paper_2512_11112_amd.spdz import Context, deal_alpha
+    return Context(n, p, deal_alpha(p, n, seed), check_seed)
+
+
+PROGRAMS = [("pipeline", P.pipeline(3001)), ("branch", P.branch(777)), ("loop", P.loop(1000, 5)),
+            ("nested", P.nested(257, 3)), ("select_shl_load", P.select_shl_load(4099, 1000, 77)),
+            ("revealed_branch", P.revealed_branch(513)), ("layer", P.layer(300, 70, 16)),
+            ("loop_program", P.loop_program(2048, 4))]
+
+
+@pytest.mark.parametrize("p,n", [(P_PAPER, 2), (P61, 3), (P127, 2)])
+@pytest.mark.parametrize("name,text", PROGRAMS)
+def test_program_matches_oracle(name, text, p, n):
+    from paper_2512_11112_amd.spdz import Program
+    if name == "layer" and p == P127:
+        pytest.skip("layers need a single-limb field")
+    print(f"case {name} p-bits={p.bit_length()} n={n}", flush=True)
+    seed, check = 21, 22
+    ref = run_program(text, p, n, seed, check)
+    ctx = ctx_for(p, n, seed, check)
+    prog = Program(ctx, text)
+    ok, sigma, ms = prog.run(seed)
+    for o, v in ref["outputs"].items():
+        got = prog.output(o)
+        if isinstance(v, F.Shares):
+            assert np.array_equal(host(got.val), v.val), f"{name}: output {o} values"
+            assert np.array_equal(host(got.mac), v.mac), f"{name}: output {o} MAC shares"
+        else:
+            assert np.array_equal(host(got), v), f"{name}: public output {o}"
+    assert ok == ref["ok"] and ok
+    assert sigma == ints_of_sigma(ref["sigma"])
+    st = prog.stats()
+    assert st["block_entries"] == ref["entries"]
+    assert st["opened"] == sum(o.shape[1] for o in ref["opened"])
+    assert ms > 0
+    prog.close()
+
+
+def test_program_reruns_are_identical():
+    """A second run of the same program object (new MAC-check epoch) matches the oracle at epoch 1."""
+    from paper_2512_11112_amd.spdz import Program
+    p, n, text = P_PAPER, 2, P.loop(64, 3)
+    ctx = ctx_for(p, n, 5, 6)
+    prog = Program(ctx, text)
+    r1 = prog.run(5)
+    r2 = prog.run(5)
+    ref1 = run_program(text, p, n, 5, 6, epoch=0)
+    ref2 = run_program(text, p, n, 5, 6, epoch=1)
+    assert r1[1] == ints_of_sigma(ref1["sigma"]) and r2[1] == ints_of_sigma(ref2["sigma"])
+    assert r1[0] and r2[0]
+
+
+@pytest.mark.parametrize("p,n", [(P_PAPER, 3), (P127, 2)])
+def test_public_op_modes(p, n):
+    """x + v, x * v (vector and scalar v) and share(v) against the oracle's definitions."""
+    from paper_2512_11112_amd.spdz import SPDZ_PUB_ADD, SPDZ_PUB_MUL, SPDZ_PUB_SHARE, ShareTensor, public_op
+    W = 5000
+    text = f"input 1 private {W} 0\ninput 2 public {W} 1\ninput 3 public 1 2\nblock 0\nret\n"
+    ex = Exec(parse(text, p), p, n, 9, 9)
+    ex.run()
+    x, v, s = ex.val[1], ex.val[2], ex.val[3]
+    ctx = ctx_for(p, n, 9, 9)
+    xd, vd, sd = share_to_dev(x), dev(v), dev(s)
+    L = ex.f.L
+    for mode, pub, want in [(SPDZ_PUB_ADD, vd, ex.add_pub(x, v)), (SPDZ_PUB_MUL, vd, ex.mul_pub(x, v)),
+                            (SPDZ_PUB_ADD, sd, ex.add_pub(x, ex.pub(3, W))),
+                            (SPDZ_PUB_MUL, sd, ex.mul_pub(x, ex.pub(3, W)))]:
+        out = public_op(ctx, mode, xd, pub, ShareTensor.empty(n, L, W))
+        torch.cuda.synchronize()
+        assert np.array_equal(host(out.val), want.val) and np.array_equal(host(out.mac), want.mac)
+    out = public_op(ctx, SPDZ_PUB_SHARE, None, vd, ShareTensor.empty(n, L, W))
+    torch.cuda.synchronize()
+    want = ex.share_pub(v)
+    assert np.array_equal(host(out.val), want.val) and np.array_equal(host(out.mac), want.mac)
+
+
+def test_program_errors():
+    from paper_2512_11112_amd.spdz import Program, ProgramError, SpdzError
+    ctx = ctx_for(P_PAPER, 2, 1, 1)
+    with pytest.raises(ProgramError, match="secret"):
+        Program(ctx, P.secret_branch(8))
+    with pytest.raises(ProgramError, match="widths"):
+        Program(ctx, "input 1 private 4 0\ninput 2 private 5 1\nblock 0\n3 = add 1 2\nret\n")
+    # a load whose public start runs past its base: a run-time error, nothing left enqueued
+    bad = "input 1 private 10 0\nconst 2 1 8\nblock 0\n3 = load 1 2 5\nret\n"
+    prog = Program(ctx, bad)
+    with pytest.raises(SpdzError, match="beyond"):
+        prog.run(1)
+    prog.close()
