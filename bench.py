@@ -88,11 +88,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 22)
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--suite", choices=["pipeline", "matmul", "dag", "dispatch", "layer"], default="pipeline",
+    ap.add_argument("--suite", choices=["pipeline", "matmul", "dag", "dispatch", "layer", "program"], default="pipeline",
                     help="pipeline: the headline step (default); matmul: matrix triples at N=1024, 4096; "
                          "dag: the 100k-op layered DAG per op / per level / hipGraph; dispatch: learned vs "
                          "static CPU-GPU dispatch on 20 held-out DAG seeds; layer: the paper's private "
-                         "linear layer at p = 2^32-5 (input sizes 2048-8192, slice sizes 131070-1048560)")
+                         "linear layer at p = 2^32-5 (input sizes 2048-8192, slice sizes 131070-1048560); "
+                         "program: the control-flow runtime on loop programs (throughput and per-entry latency)")
     ap.add_argument("--seeds", type=int, default=20, help="held-out DAG seeds of the dispatch suite")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -105,7 +106,8 @@ def main():
     from workloads import ARR_A, ARR_X, ARR_Y, P61, P127, SEEDS_TIMING
 
     if args.suite != "pipeline":
-        fn = {"matmul": suite_matmul, "dag": suite_dag, "dispatch": suite_dispatch, "layer": suite_layer}[args.suite]
+        fn = {"matmul": suite_matmul, "dag": suite_dag, "dispatch": suite_dispatch, "layer": suite_layer,
+              "program": suite_program}[args.suite]
         print(json.dumps(fn(args)), flush=True)
         return
 
@@ -391,6 +393,95 @@ def cpu_baseline_layer(tiles: int):
             "kind": "oracle", "sample": f"{rows} of the 8192 rows ({-(-rows // cfg.tile_rows)} tiles) of the d=8192 "
                                         f"layer, whole protocol (opens, products, MAC check) on the oracle, "
                                         f"{dt:.2f} s wall, scaled by 8192/{rows}; dealing excluded"}
+
+
+def loop_program_bytes(n: int, L: int, W: int, trips: int):
+    """Algorithmic bytes of the loop program's online device work: per iteration three
+    Beaver products (12 n L words per element each, triples read from HBM), two secret
+    additions (6 n L) and the phi copy of the accumulator (4 n L); dealing a product's
+    triple on the fly would write 6 n L more (reported apart)."""
+    per_iter = (3 * 12 + 2 * 6 + 4) * n * L * 8 * W
+    deal = 3 * 6 * n * L * 8 * W
+    return per_iter * trips, deal * trips
+
+
+def suite_program(args):
+    """The control-flow runtime (Sec. III-C): a loop program whose body holds three Beaver
+    products and two additions of width W (2 parties, p = 2^32 - 5), run end to end with
+    public loop control, phi copies and the final MAC check; and the same loop at width 64
+    (per block-entry latency of the scheduler).  Triples are dealt ahead (fake preprocessing,
+    as the paper's evaluation); the first, untimed run deals them on the fly and its wall
+    time is reported beside."""
+    import torch
+    from paper_2512_11112_amd import spdz as S
+    from workloads import P_PAPER, SEEDS_TIMING, programs as PR
+    seed, n, p = SEEDS_TIMING[0], 2, P_PAPER
+    res = {}
+    for W, trips, reps in ((1 << 22, 16, 5), (64, 2000, 3)):
+        ctx = S.Context(n, p, S.deal_alpha(p, n, seed), seed)
+        prog = S.Program(ctx, PR.loop_program(W, trips))
+        ok, _, ms_deal = prog.run(seed)   # warm-up, triples dealt on the fly
+        assert ok
+        prog.predeal(seed, trips)         # fake preprocessing ahead of the timed online runs
+        torch.cuda.synchronize()
+        ctx.spdz_timing_enable(True)
+        walls = []
+        for _ in range(reps):
+            ok, _, ms = prog.run(seed)
+            assert ok
+            walls.append(ms)
+        kern = 0.0
+        for k in ("beaver", "linear", "public_op", "open", "reduce"):
+            t, c = ctx.spdz_timing_get(k)
+            kern += t
+        ctx.spdz_timing_enable(False)
+        st = prog.stats()
+        ms = _median(walls)
+        alg, deal = loop_program_bytes(n, 1, W, trips)
+        mults = 3 * W * trips
+        res[f"W{W}_trips{trips}"] = {
+            "wall_ms": ms, "kernel_ms_sum": kern / reps, "host_overhead_ms": ms - kern / reps,
+            "block_entries": st["block_entries"], "launches": st["launches"], "host_syncs": st["host_syncs"],
+            "us_per_block_entry": ms * 1e3 / st["block_entries"], "mults_per_s": mults / (ms * 1e-3),
+            "alg_GBps": alg / (ms * 1e-3) / 1e9, "alg_bytes": alg,
+            "wall_ms_dealing_on_the_fly": ms_deal, "dealing_bytes": deal}
+        log(f"program W={W} trips={trips}: {ms:.3f} ms wall, kernels {kern / reps:.3f} ms, "
+            f"{st['block_entries']} block entries ({ms * 1e3 / st['block_entries']:.1f} us each), "
+            f"{st['launches']} launches, {st['host_syncs']} syncs, {mults / (ms * 1e-3) / 1e9:.2f} G mult/s")
+        prog.close()
+        ctx.close()
+        torch.cuda.empty_cache()
+    big = res["W4194304_trips16"]
+    out = {"metric": "control-flow runtime: MAC'd Beaver mults/s of a 16-iteration loop program "
+                     "(2 parties, p = 2^32-5, width 2^22, public loop control, MAC check included)",
+           "value": big["mults_per_s"], "unit": "mults/s", "higher_is_better": True, "n_gpus": 1,
+           "steps": 5, "warmup": 1, "ms_per_step": big["wall_ms"], "vs_baseline": None,
+           "dtype": "u64 words (residues < 2^32)", "data": "synthetic",
+           "config": {"workload": "loop_program_n2_p32_w4194304_trips16", "parties": 2, "modulus": "2^32-5"},
+           "roofline": {"bound": "hbm", "kernel": "whole program (Beaver, linear, copies)",
+                        "achieved": big["alg_GBps"], "peak": 8000.0, "unit": "GB/s", "frac": big["alg_GBps"] / 8000.0,
+                        "traffic": None},
+           "results": res}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_program()
+    return out
+
+
+def cpu_baseline_program():
+    """The oracle's sequential interpreter on the loop program at a smaller width, scaled."""
+    import os
+    from oracle.program import run_program
+    from workloads import P_PAPER, programs as PR
+    W, trips = 1 << 18, 16
+    t0 = time.perf_counter()
+    r = run_program(PR.loop_program(W, trips), P_PAPER, 2, 1, 1)
+    dt = time.perf_counter() - t0
+    assert r["ok"]
+    mults = 3 * W * trips
+    return {"value": mults / dt, "unit": "mults/s", "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+            "kind": "oracle", "sample": f"loop program at width 2^18 (16 iterations), sequential interpreter with the "
+                                        f"tier-1 oracle arithmetic, dealing included (its dealer runs inside the "
+                                        f"interpreter), {dt:.2f} s wall"}
 
 
 def dag_alg_bytes(dag):

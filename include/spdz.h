@@ -393,6 +393,13 @@ spdz_status spdz_prog_destroy(spdz_prog *prog);
  * edge) returns SPDZ_E_INVAL with spdz_prog_error set. */
 spdz_status spdz_prog_run(spdz_prog *prog, uint64_t seed, int *accepted, uint64_t *sigma_out, double *wall_ms);
 
+/* Fake preprocessing ahead of the online phase: deals, for seed `seed`, the
+ * triples of executions 0 .. executions-1 of every product and layer node
+ * (the same triples spdz_prog_run would deal on the fly) into device pools;
+ * a later run with the same seed takes them from the pools and deals only
+ * executions beyond them.  Replaces earlier pools.  Synchronous. */
+spdz_status spdz_prog_predeal(spdz_prog *prog, uint64_t seed, int64_t executions);
+
 /* After a run: an output node's final value, into out_shares (secret; len =
  * the node's width, any strides) or out_pub (public; DEVICE [L][width]).
  * SPDZ_E_INVAL for a node that is not an output.  Synchronous. */

@@ -62,7 +62,8 @@ struct PNode {
   spdz_shares sh{};      // secret value: device [n][L][width] (values, MACs)
   u64 *dpub = nullptr;   // public value (or a secret node's public scratch): device [L][width]
   u64 *hpub = nullptr;   // public value: pinned host [L][width]
-  spdz_triple tri{};     // product / layer triples
+  spdz_triple tri{};     // product / layer triples dealt during the run
+  std::vector<spdz_triple> pool;  // triples dealt ahead (spdz_prog_predeal), by execution number
   u64 *ltmp = nullptr;   // layer dealer: public A, B, C
   // run state
   int64_t inst = 0;
@@ -118,6 +119,7 @@ struct spdz_prog {
   // rewritten by its next execution before an earlier copy has run)
   u64 *arena = nullptr;
   size_t arena_words = 0, arena_used = 0;
+  u64 pool_seed = 0;
 };
 
 namespace {
@@ -619,6 +621,35 @@ spdz_status copy_shares(spdz_prog *g, const spdz_shares &src, int64_t first, spd
   return SPDZ_OK;
 }
 
+bool is_product(spdz_prog *g, const PNode &n) {
+  return n.op == OP_MUL && g->nodes[n.args[0]].secret && g->nodes[n.args[1]].secret;
+}
+
+// deals execution k's triple of a product or layer node into t (layer: public A, B, C through n.ltmp)
+spdz_status deal_node_triple(spdz_prog *g, PNode &n, int64_t k, u64 seed, spdz_triple &t) {
+  spdz_ctx *c = g->c;
+  const u64 aid = triple_array(n.id, k);
+  if (n.op == OP_MUL) return launch_deal_triple(c, seed, aid, &t);
+  const int64_t din = n.imm[0], dout = n.imm[1], tr = n.imm[2], tiles = (dout + tr - 1) / tr;
+  u64 *av = n.ltmp, *bv = av + dout * din, *cv = bv + tiles * din;
+  SPDZ_RET(launch_deal_secret(c, seed, aid, nullptr, &t.a, av));
+  SPDZ_RET(launch_deal_secret(c, seed, aid + 1, nullptr, &t.b, bv));
+  SPDZ_RET(launch_public_matvec(c, dout, din, tr, av, bv, cv));
+  return launch_deal_secret(c, seed, aid + 2, cv, &t.c, nullptr);
+}
+
+// the triple of the node's current execution: from the pool dealt ahead, else dealt now
+spdz_status node_triple(spdz_prog *g, PNode &n, spdz_triple *&t) {
+  const int64_t k = n.inst - 1;
+  if (g->pool_seed == g->seed && k < (int64_t)n.pool.size()) {
+    t = &n.pool[k];
+    return SPDZ_OK;
+  }
+  t = &n.tri;
+  g->launches += n.op == OP_MUL ? 1 : 4;
+  return deal_node_triple(g, n, k, g->seed, n.tri);
+}
+
 spdz_status issue(spdz_prog *g, PNode &n) {
   spdz_ctx *c = g->c;
   auto &N = g->nodes;
@@ -644,11 +675,12 @@ spdz_status issue(spdz_prog *g, PNode &n) {
         st = upload(g, n);
       } else if (a.secret && b.secret) {
         if (n.op == OP_MUL) {
-          st = launch_deal_triple(c, g->seed, triple_array(n.id, n.inst - 1), &n.tri);
+          spdz_triple *t = nullptr;
+          st = node_triple(g, n, t);
           c->log_count = n.log_off;
           if (st == SPDZ_OK)
-            st = launch_beaver(c, &a.sh, &b.sh, &n.tri, &n.sh, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
-          g->launches += 2;
+            st = launch_beaver(c, &a.sh, &b.sh, t, &n.sh, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+          g->launches += 1;
         } else {
           const spdz_shares terms[2] = {a.sh, b.sh};
           u64 cf[4] = {0, 0, 0, 0};  // [term][L]: 1, then 1 or p - 1
@@ -738,16 +770,12 @@ spdz_status issue(spdz_prog *g, PNode &n) {
     }
     case OP_LAYER: {
       PNode &x = N[n.args[0]], &W = N[n.args[1]], &b = N[n.args[2]];
-      const int64_t din = n.imm[0], dout = n.imm[1], tr = n.imm[2], tiles = (dout + tr - 1) / tr;
-      const u64 aid = triple_array(n.id, n.inst - 1);
-      u64 *av = n.ltmp, *bv = av + dout * din, *cv = bv + tiles * din;
-      st = launch_deal_secret(c, g->seed, aid, nullptr, &n.tri.a, av);
-      if (st == SPDZ_OK) st = launch_deal_secret(c, g->seed, aid + 1, nullptr, &n.tri.b, bv);
-      if (st == SPDZ_OK) st = launch_public_matvec(c, dout, din, tr, av, bv, cv);
-      if (st == SPDZ_OK) st = launch_deal_secret(c, g->seed, aid + 2, cv, &n.tri.c, nullptr);
+      const int64_t din = n.imm[0], dout = n.imm[1], tr = n.imm[2];
+      spdz_triple *t = nullptr;
+      st = node_triple(g, n, t);
       c->log_count = n.log_off;
-      if (st == SPDZ_OK) st = launch_linear_layer(c, dout, din, tr, &W.sh, &x.sh, &b.sh, &n.tri, &n.sh, nullptr, nullptr);
-      g->launches += 6;
+      if (st == SPDZ_OK) st = launch_linear_layer(c, dout, din, tr, &W.sh, &x.sh, &b.sh, t, &n.sh, nullptr, nullptr);
+      g->launches += 2;
       break;
     }
     default: return fail(g, "cannot issue node " + std::to_string(n.id));
@@ -865,6 +893,11 @@ void destroy(spdz_prog *g) {
     free_shares(n.tri.a);
     free_shares(n.tri.b);
     free_shares(n.tri.c);
+    for (auto &t : n.pool) {
+      free_shares(t.a);
+      free_shares(t.b);
+      free_shares(t.c);
+    }
     if (n.dpub) hipFree(n.dpub);
     if (n.hpub) hipHostFree(n.hpub);
     if (n.ltmp) hipFree(n.ltmp);
@@ -924,6 +957,39 @@ spdz_status spdz_prog_run(spdz_prog *g, uint64_t seed, int *accepted, uint64_t *
   if (wall_ms) *wall_ms = g->wall_ms;
   g->ran = true;
   return st;
+}
+
+spdz_status spdz_prog_predeal(spdz_prog *g, uint64_t seed, int64_t executions) {
+  if (!g || executions < 0) return SPDZ_E_INVAL;
+  if (g->c->aborted) return SPDZ_E_ABORTED;
+  (void)hipStreamSynchronize(g->c->stream);
+  for (auto &kv : g->nodes) {
+    PNode &n = kv.second;
+    for (auto &t : n.pool) {
+      free_shares(t.a);
+      free_shares(t.b);
+      free_shares(t.c);
+    }
+    n.pool.clear();
+  }
+  g->pool_seed = seed;
+  for (auto &kv : g->nodes) {
+    PNode &n = kv.second;
+    if (!is_product(g, n) && n.op != OP_LAYER) continue;
+    const int64_t wa = n.op == OP_MUL ? n.width : n.imm[0] * n.imm[1];
+    const int64_t wb = n.op == OP_MUL ? n.width : (n.imm[1] + n.imm[2] - 1) / n.imm[2] * n.imm[0];
+    const int64_t wc = n.width;
+    for (int64_t k = 0; k < executions; k++) {
+      spdz_triple t{};
+      spdz_status st = alloc_shares(g, t.a, wa);
+      if (st == SPDZ_OK) st = alloc_shares(g, t.b, wb);
+      if (st == SPDZ_OK) st = alloc_shares(g, t.c, wc);
+      if (st == SPDZ_OK) st = deal_node_triple(g, n, k, seed, t);
+      n.pool.push_back(t);
+      if (st != SPDZ_OK) return st;
+    }
+  }
+  return hip_status(hipStreamSynchronize(g->c->stream));
 }
 
 spdz_status spdz_prog_output(spdz_prog *g, int node, spdz_shares *out_shares, uint64_t *out_pub) {

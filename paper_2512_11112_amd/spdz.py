@@ -81,6 +81,7 @@ def lib() -> ctypes.CDLL:
             "spdz_prog_create": (i32, [vp, ctypes.c_char_p, ctypes.POINTER(vp), ctypes.c_char_p, i64]),
             "spdz_prog_destroy": (i32, [vp]),
             "spdz_prog_run": (i32, [vp, ctypes.c_uint64, ctypes.POINTER(i32), u64p, ctypes.POINTER(ctypes.c_double)]),
+            "spdz_prog_predeal": (i32, [vp, ctypes.c_uint64, i64]),
             "spdz_prog_output": (i32, [vp, i32, ctypes.POINTER(Shares), vp]),
             "spdz_prog_node_info": (i32, [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_int64)]),
             "spdz_prog_stats": (i32, [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
@@ -450,6 +451,10 @@ class Program:
             raise SpdzError(st, f"spdz_prog_run: {msg.decode() if msg else ''}")
         sigma = [sum(int(sig[i * L + l]) << (64 * l) for l in range(L)) for i in range(n)]
         return bool(acc.value) and st == SPDZ_OK, sigma, ms.value
+
+    def predeal(self, seed: int, executions: int):
+        """Deal the triples of the first `executions` executions of every product / layer node ahead."""
+        _check(lib().spdz_prog_predeal(self._h, ctypes.c_uint64(seed), executions), "spdz_prog_predeal")
 
     def info(self, node: int):
         sec, w = ctypes.c_int(0), ctypes.c_int64(0)

@@ -112,3 +112,20 @@ def test_program_errors():
     with pytest.raises(SpdzError, match="beyond"):
         prog.run(1)
     prog.close()
+
+
+@pytest.mark.parametrize("pool_seed", [31, 99])
+def test_predealt_triples_give_the_same_run(pool_seed):
+    """Triples dealt ahead for the first two executions (or for another seed, then unused):
+    the run still matches the oracle bit for bit."""
+    from paper_2512_11112_amd.spdz import Program
+    p, n, text = P_PAPER, 2, P.loop_program(1000, 5)
+    ref = run_program(text, p, n, 31, 32)
+    ctx = ctx_for(p, n, 31, 32)
+    prog = Program(ctx, text)
+    prog.predeal(pool_seed, 2)
+    ok, sigma, _ = prog.run(31)
+    got = prog.output(6)
+    assert np.array_equal(host(got.val), ref["outputs"][6].val)
+    assert np.array_equal(host(got.mac), ref["outputs"][6].mac)
+    assert ok and sigma == ints_of_sigma(ref["sigma"])
