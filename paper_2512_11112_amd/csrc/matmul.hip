@@ -26,13 +26,13 @@ namespace spdz {
 
 constexpr int MAXOUT = 2 * MAX_PARTIES;
 constexpr int TILE = 64;
-constexpr int MFMA_K = 32;
 constexpr int NDIG = 8;
+constexpr int SK = 64;  // inner-dimension depth of one MFMA LDS stage (planes are padded to it)
 
 struct GemmJob {
   int npairs;
-  const void *L[2];  // VALU: u64 [rows][K] (ld K); MFMA: int8 digit planes [8][Mp][Kp]
-  const void *R[2];  // VALU: u64 [K][cols] (ld cols); MFMA: int8 digit planes [8][Np][Kp]
+  const void *L[2];  // VALU: u64 [rows][K] (ld K); MFMA: tile-major int8 digit planes (Mp Kp bytes x 8)
+  const void *R[2];  // VALU: u64 [K][cols] (ld cols); MFMA: tile-major int8 digit planes (Np Kp bytes x 8)
   const u64 *init;   // [M][N] canonical or null
   const u64 *pmat;   // [M][N] canonical or null, added times pscale
   u64 pscale;
@@ -131,24 +131,20 @@ __device__ __forceinline__ void balanced_digits(u64 v, int8_t (&dg)[NDIG]) {
   }
 }
 
-// LEFT: src [rows][cols] (ld = cols), planes [8][Rp][Kp], plane[d][r][k] = digit d of src[r][k]
-// RIGHT: src [K][cols] (ld = cols), planes [8][Rp][Kp] with Rp over cols, plane[d][c][k] = digit d of src[k][c]
-// one thread per (r, 16 consecutive k); zero padding outside the matrix
+// Tile-major planes: for plane-row block b (64 rows) and stage s (64 inner indices),
+// the STAGE = 32 KB at (b (Kp / 64) + s) STAGE hold [digit 8][chunk 4][row 64][16 bytes];
+// byte j of (d, c, row) is digit d of the element at plane row 64 b + row and inner
+// index k = 64 s + 16 c + j.  One operand stage of one tile is thus one contiguous block.
+// LEFT: src [rows][cols] (ld = cols); plane row = source row, k = source column.
+// RIGHT: src [K][cols] (ld = cols); plane row = source column, k = source row.
+// One thread per (plane row, 16-deep chunk), consecutive threads on consecutive plane
+// rows (coalesced 16-byte writes; coalesced reads for RIGHT); zero padding outside the matrix.
 template <bool RIGHT>
 __global__ __launch_bounds__(256) void k_digits(const u64 *__restrict__ src, int64_t rows, int64_t cols,
                                                int8_t *__restrict__ planes, int64_t Rp, int64_t Kp) {
-  // RIGHT: the plane rows are the source columns, the plane k are the source rows
-  const int64_t prow_n = Rp, kchunks = Kp / 16;
-  const int64_t total = prow_n * kchunks;
+  const int64_t kchunks = Kp / 16, total = Rp * kchunks;
   for (int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x; w < total; w += (int64_t)gridDim.x * 256) {
-    int64_t pr, kc;
-    if (RIGHT) {  // consecutive threads take consecutive source columns (coalesced reads)
-      pr = w % prow_n;
-      kc = w / prow_n;
-    } else {
-      pr = w / kchunks;
-      kc = w % kchunks;
-    }
+    const int64_t pr = w % Rp, kc = w / Rp;
     int8_t out[NDIG][16];
 #pragma unroll
     for (int j = 0; j < 16; j++) {
@@ -168,17 +164,27 @@ __global__ __launch_bounds__(256) void k_digits(const u64 *__restrict__ src, int
     for (int d = 0; d < NDIG; d++) {
       int4 pk;
       __builtin_memcpy(&pk, out[d], 16);
-      *reinterpret_cast<int4 *>(planes + ((int64_t)d * Rp + pr) * Kp + kc * 16) = pk;
+      const int64_t tile = (pr / TILE) * (Kp / SK) + kc / (SK / 16);
+      *reinterpret_cast<int4 *>(planes + tile * (NDIG * SK * TILE) + ((d * (SK / 16) + kc % (SK / 16)) * TILE + pr % TILE) * 16) = pk;
     }
   }
 }
 
 // --------------------------------------------------------------------------
 // MFMA engine: 4 waves per block, 64 x 64 output tile, 32 x 32 per wave
+//
+// One operand stage of a tile (SK = 64 inner indices, 8 digits, 64 rows) is one
+// contiguous 32 KB block of the tile-major digit planes, ordered [digit][16-deep
+// chunk][row][16 bytes]; the 256 threads move it 16 bytes each per round (fully
+// coalesced, sequential addresses) and store it to LDS in the same order, which makes
+// the 16-byte LDS writes and the MFMA operand reads (32 consecutive rows per half
+// wave) conflict-free without padding.
 // --------------------------------------------------------------------------
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
-constexpr int LDS_ROW = 48;  // bytes per staged row (32 used; padded against bank conflicts)
+constexpr int SCH = SK / 16;            // 16-byte chunks per row in a stage
+constexpr int RUN = TILE * 16;          // one (digit, chunk) run of a tile: 1 KB
+constexpr int STAGE = NDIG * SCH * RUN; // bytes per operand and stage: 32 KB
 
 __device__ __forceinline__ u64 rot61(u64 x, int t) {
   return t == 0 ? x : (((x << t) | (x >> (61 - t))) & F61::P);
@@ -187,84 +193,97 @@ __device__ __forceinline__ u64 rot61(u64 x, int t) {
 __global__ __launch_bounds__(256, 1) void k_gemm_mfma(const GemmArgs A) {
   const GemmJob &J = A.job[blockIdx.z];
   const int64_t r0 = (int64_t)blockIdx.y * TILE, c0 = (int64_t)blockIdx.x * TILE;
-  // two LDS stages: step s is staged in buffer s & 1 while step s + 1 is in flight from HBM
-  __shared__ __attribute__((aligned(16))) int8_t As[2][NDIG][TILE][LDS_ROW];
-  __shared__ __attribute__((aligned(16))) int8_t Bs[2][NDIG][TILE][LDS_ROW];
+  // two stage buffers: stage s is read from buffer s & 1 while stage s + 1 is in flight
+  __shared__ __attribute__((aligned(16))) int8_t S[2][2][STAGE];  // [buffer][left | right]
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   v16i acc[2 * NDIG - 1];
 #pragma unroll
   for (int s = 0; s < 2 * NDIG - 1; s++) acc[s] = (v16i){0};
-  const int64_t Mp = A.Mp, Np = A.Np, Kp = A.Kp;
-  const int64_t ksteps = Kp / MFMA_K, nsteps = J.npairs * ksteps;
-  // this thread's four 16-byte chunks of each operand tile (plane d, row, half): offsets
-  // into the digit planes at k = 0 and into one LDS stage
-  int64_t goa[4], gob[4];
-  int lo[4];
+  const int ks = (int)(A.Kp / SK), nst = J.npairs * ks;
+  // the stage s of tile row (column) block b is STAGE contiguous bytes at (b ks + s) STAGE;
+  // round q of a fetch moves run 4 q + wave of it, 16 bytes per lane
+  const int64_t toff = (int64_t)t * 16;
+  const int8_t *gl = (const int8_t *)J.L[0] + (int64_t)blockIdx.y * ks * STAGE + toff;
+  const int8_t *gr = (const int8_t *)J.R[0] + (int64_t)blockIdx.x * ks * STAGE + toff;
+  const int8_t *l1 = (const int8_t *)J.L[1] + (int64_t)blockIdx.y * ks * STAGE + toff;
+  const int8_t *r1 = (const int8_t *)J.R[1] + (int64_t)blockIdx.x * ks * STAGE + toff;
+  v4i ra[NDIG], rb[NDIG];  // the next stage, on its way from global memory to LDS
 #pragma unroll
-  for (int q = 0; q < 4; q++) {
-    const int idx = t + q * 256;
-    const int d = idx >> 7, row = (idx & 127) >> 1, half = idx & 1;
-    goa[q] = ((int64_t)d * Mp + r0 + row) * Kp + half * 16;
-    gob[q] = ((int64_t)d * Np + c0 + row) * Kp + half * 16;
-    lo[q] = (d * TILE + row) * LDS_ROW + half * 16;
+  for (int q = 0; q < NDIG; q++) {
+    ra[q] = *reinterpret_cast<const v4i *>(gl + q * SCH * RUN);
+    rb[q] = *reinterpret_cast<const v4i *>(gr + q * SCH * RUN);
+    *reinterpret_cast<v4i *>(&S[0][0][q * SCH * RUN + t * 16]) = ra[q];
+    *reinterpret_cast<v4i *>(&S[0][1][q * SCH * RUN + t * 16]) = rb[q];
   }
-  auto fetch = [&](int64_t step, v4i (&ra)[4], v4i (&rb)[4]) {
-    const int pr = (int)(step / ksteps);
-    const int64_t k0 = (step % ksteps) * MFMA_K;
-    const int8_t *Lp = (const int8_t *)J.L[pr] + k0;
-    const int8_t *Rp = (const int8_t *)J.R[pr] + k0;
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-      ra[q] = *reinterpret_cast<const v4i *>(Lp + goa[q]);
-      rb[q] = *reinterpret_cast<const v4i *>(Rp + gob[q]);
+  __syncthreads();
+  // MFMA operands: lane supplies row (lane & 31) of its wave's 32 rows (columns) at chunk
+  // 2 kk + (lane >> 5); left and right use the same chunk, so the k pairing is consistent
+  const int aoff = ((lane >> 5) * TILE + wr * 32 + (lane & 31)) * 16;
+  const int boff = ((lane >> 5) * TILE + wc * 32 + (lane & 31)) * 16;
+  for (int st = 0; st < nst; st++) {
+    const int buf = st & 1;
+    // the next stage's operand blocks (the last stage re-reads its own: in bounds, unused)
+    const int nx = st + 1 < nst ? st + 1 : st;
+    if (nx != st) {
+      gl = nx == ks ? l1 : gl + STAGE;
+      gr = nx == ks ? r1 : gr + STAGE;
     }
-  };
-  v4i ra[4], rb[4];
-  fetch(0, ra, rb);
-  const int kg = (lane >> 5) * 16;
-  const int arow = ((wr * 32 + (lane & 31)) * LDS_ROW) + kg, brow = ((wc * 32 + (lane & 31)) * LDS_ROW) + kg;
-  for (int64_t step = 0; step < nsteps; step++) {
-    const int buf = (int)(step & 1);
-    int8_t *as = &As[buf][0][0][0], *bs = &Bs[buf][0][0][0];
+    const int8_t *sl = &S[buf][0][0], *sr = &S[buf][1][0];
+    int8_t *wl = &S[buf ^ 1][0][0], *wrr = &S[buf ^ 1][1][0];
+    // operand reads: at most 13 LDS operations are outstanding at any MFMA group, so each
+    // group waits for exactly the reads it needs (the LDS counter field holds 15)
+    v4i a0[NDIG], b0[NDIG], a1[NDIG], b1[NDIG];
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-      *reinterpret_cast<v4i *>(as + lo[q]) = ra[q];
-      *reinterpret_cast<v4i *>(bs + lo[q]) = rb[q];
-    }
-    __syncthreads();
-    if (step + 1 < nsteps) fetch(step + 1, ra, rb);  // in flight during this step's MFMAs
-    v4i b[NDIG];
-#pragma unroll
-    for (int d = 0; d < NDIG; d++) b[d] = *reinterpret_cast<const v4i *>(bs + d * TILE * LDS_ROW + brow);
+    for (int d = 0; d < NDIG; d++) b0[d] = *reinterpret_cast<const v4i *>(sr + (d * SCH) * RUN + boff);
+    a0[0] = *reinterpret_cast<const v4i *>(sl + aoff);
+    a0[1] = *reinterpret_cast<const v4i *>(sl + SCH * RUN + aoff);
+    // first half: each group of 8 MFMAs also issues two global loads of the next stage,
+    // reads a first-half operand two groups ahead and two second-half operands, so no
+    // burst of memory instructions holds up the matrix pipe
 #pragma unroll
     for (int dk = 0; dk < NDIG; dk++) {
-      const v4i a = *reinterpret_cast<const v4i *>(as + dk * TILE * LDS_ROW + arow);
+      __builtin_amdgcn_sched_barrier(0);
+      ra[dk] = *reinterpret_cast<const v4i *>(gl + dk * SCH * RUN);
+      rb[dk] = *reinterpret_cast<const v4i *>(gr + dk * SCH * RUN);
+      if (dk + 2 < NDIG) a0[dk + 2] = *reinterpret_cast<const v4i *>(sl + ((dk + 2) * SCH) * RUN + aoff);
+      b1[dk] = *reinterpret_cast<const v4i *>(sr + (dk * SCH + 2) * RUN + boff);
+      a1[dk] = *reinterpret_cast<const v4i *>(sl + (dk * SCH + 2) * RUN + aoff);
 #pragma unroll
       for (int dl = 0; dl < NDIG; dl++)
-        acc[dk + dl] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b[dl], acc[dk + dl], 0, 0, 0);
+        acc[dk + dl] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0[dk], b0[dl], acc[dk + dl], 0, 0, 0);
     }
+    // second half: the next stage goes to the other buffer (last read in stage st - 1,
+    // before every wave passed the previous barrier), two 16-byte stores per group
+#pragma unroll
+    for (int dk = 0; dk < NDIG; dk++) {
+      __builtin_amdgcn_sched_barrier(0);
+      *reinterpret_cast<v4i *>(wl + dk * SCH * RUN + t * 16) = ra[dk];
+      *reinterpret_cast<v4i *>(wrr + dk * SCH * RUN + t * 16) = rb[dk];
+#pragma unroll
+      for (int dl = 0; dl < NDIG; dl++)
+        acc[dk + dl] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1[dk], b1[dl], acc[dk + dl], 0, 0, 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    __syncthreads();
   }
-  // recombine the shift classes mod p (one class at a time, 16 running sums) and apply the epilogue
+  // recombine the shift classes mod p, one output element at a time, and apply the epilogue
   const int64_t M = A.M, N = A.N;
-  u64 x[16];
-#pragma unroll
-  for (int r = 0; r < 16; r++) x[r] = 0;
-#pragma unroll
-  for (int s = 0; s < 2 * NDIG - 1; s++) {
-#pragma unroll
-    for (int r = 0; r < 16; r++) {
-      const int cs = acc[s][r];
-      const u64 m = cs < 0 ? (u64)((int64_t)cs + (int64_t)F61::P) : (u64)cs;  // |cs| < 2^31
-      x[r] = F61::add(F61::E{x[r]}, F61::E{rot61(m, (8 * s) % 61)}).v;
-    }
-  }
 #pragma unroll
   for (int r = 0; r < 16; r++) {
+    u64 x = 0;
+#pragma unroll
+    for (int s = 0; s < 2 * NDIG - 1; s++) {
+      int cs = acc[s][r];
+      asm volatile("" : "+v"(cs));  // read the accumulator here, not hoisted across rows
+      const u64 m = cs < 0 ? (u64)((int64_t)cs + (int64_t)F61::P) : (u64)cs;  // |cs| < 2^31
+      x = F61::add(F61::E{x}, F61::E{rot61(m, (8 * s) % 61)}).v;
+    }
     const int row = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
     const int col = lane & 31;
     const int64_t gr = r0 + wr * 32 + row, gc = c0 + wc * 32 + col;
-    if (gr < M && gc < N) J.out[gr * N + gc] = epilogue_add(x[r], J, gr * N + gc);
+    if (gr < M && gc < N) J.out[gr * N + gc] = epilogue_add(x, J, gr * N + gc);
+    __builtin_amdgcn_sched_barrier(0);  // keep each element's 15 conversions together
   }
 }
 
@@ -306,7 +325,7 @@ spdz_status launch_matmul_triple(spdz_ctx *c, int64_t M, int64_t K, int64_t N, c
                                  const spdz_shares *Y, const spdz_triple *T, spdz_shares *Z, u64 *E_pub, u64 *F_pub,
                                  int variant) {
   const int n = c->n;
-  const int64_t Mp = up(M, TILE), Np = up(N, TILE), Kp = up(K, MFMA_K), Kpm = up(K, TILE);
+  const int64_t Mp = up(M, TILE), Np = up(N, TILE), Kp = up(K, SK), Kpm = up(K, TILE);
   // workspace: [E][F][P] (u64) if not supplied, then digit planes when the MFMA engine runs
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
   const size_t e_bytes = al((size_t)M * K * 8), f_bytes = al((size_t)K * N * 8), p_bytes = al((size_t)M * N * 8);
@@ -384,7 +403,7 @@ spdz_status launch_matmul_triple(spdz_ctx *c, int64_t M, int64_t K, int64_t N, c
 
 // C = A B mod p for public matrices (used by the dealer of matrix triples)
 spdz_status launch_public_matmul(spdz_ctx *c, int64_t M, int64_t K, int64_t N, const u64 *Am, const u64 *Bm, u64 *Cm) {
-  const int64_t Mp = up(M, TILE), Np = up(N, TILE), Kp = up(K, MFMA_K);
+  const int64_t Mp = up(M, TILE), Np = up(N, TILE), Kp = up(K, SK);
   const size_t lplane = (size_t)NDIG * Mp * Kp, rplane = (size_t)NDIG * Np * Kp;
   SPDZ_RET(ensure_ws(c, lplane + rplane + 256));
   int8_t *lp = (int8_t *)c->ws, *rp = lp + lplane;
