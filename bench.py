@@ -17,6 +17,7 @@ import hashlib
 import json
 import os
 import re
+import subprocess
 import sys
 import time
 
@@ -288,12 +289,26 @@ def suite_matmul(args):
         del X, Y, Z, T
         torch.cuda.empty_cache()
     best = res["N4096_mfma"]
+    # the int8 MFMA rate this GPU holds with operands in registers (random vs structured
+    # bytes): the power-limited ceiling of the GEMM, measured by a child process
+    calib = os.path.join(ROOT, "paper_2512_11112_amd", "calib", "mfma_rate")
+    rate = None
+    if os.path.exists(calib):
+        r = subprocess.run([calib, "4096", "400"], capture_output=True, text=True, timeout=300)
+        if r.returncode == 0:
+            rate = json.loads(r.stdout.strip().splitlines()[-1])
+            rate["gemm_frac_of_random_operand_rate"] = best["int8_tops_equiv"] / rate["int8_mfma_register_tops_random"]
+            log(f"int8 MFMA register rate: random {rate['int8_mfma_register_tops_random']:.0f} TOPS, "
+                f"structured {rate['int8_mfma_register_tops_structured']:.0f} TOPS")
+        else:
+            log(f"mfma_rate failed: {r.stderr.strip()}")
     return {"metric": "matrix-triple mod-p multiply-adds per second (2 parties, p=2^61-1, N=4096)",
             "value": best["modp_mac_per_s"], "unit": "modp_mac/s", "higher_is_better": True, "n_gpus": 1,
             "dtype": "u64 (int8 digits on MFMA)", "data": "synthetic",
             "config": {"workload": "matrix_triple_n2_p61_N1024_N4096", "parties": 2, "modulus": "2^61-1"},
             "roofline": {"bound": "mfma", "achieved": best["int8_tops_equiv"], "peak": 5000.0, "unit": "TOPS (int8)",
                          "frac": best["int8_tops_equiv"] / 5000.0, "traffic": None},
+            "mfma_rate_calibration": rate,
             "mfma_over_valu_N4096": res["N4096_valu"]["gemm_ms"] / res["N4096_mfma"]["gemm_ms"],
             "mfma_over_valu_N1024": res["N1024_valu"]["gemm_ms"] / res["N1024_mfma"]["gemm_ms"],
             "results": res}

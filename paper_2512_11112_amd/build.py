@@ -3,7 +3,9 @@
     python -m paper_2512_11112_amd.build
 
 Every .hip file under csrc/ is compiled to an object in _build/ (in
-parallel), then linked into paper_2512_11112_amd/libspdz.so.
+parallel), then linked into paper_2512_11112_amd/libspdz.so.  The calibration
+program calib/mfma_rate.hip (the int8 MFMA rate this GPU sustains, reported
+beside the GEMM's measurements) is built next to its source.
 """
 from __future__ import annotations
 
@@ -51,6 +53,11 @@ def build(verbose: bool = True) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(tmp, OUT)
+    calib = os.path.join(PKG, "calib", "mfma_rate")
+    r = subprocess.run([HIPCC, *CFLAGS, os.path.join(PKG, "calib", "mfma_rate.hip"), "-o", calib],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for calib/mfma_rate.hip:\n{r.stderr}")
     if verbose:
         print(f"built {OUT} from {len(srcs)} sources", file=sys.stderr)
     return OUT
