@@ -81,7 +81,29 @@ def cpu_baseline(p: int, n: int, W_sample: int, seed: int, min_s: float = 10.0, 
     return {"value": done * W_sample / dt, "unit": "mults/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} pass(es) over {W_sample} of {1 << 24} elements, whole pipeline (Beaver, linear, "
                       f"ReduceAdd, opens, MAC check) on the oracle (plain C, generic long-division mod p), "
-                      f"{dt:.2f} s wall, dealing excluded"}
+                      f"{dt:.2f} s wall, dealing excluded",
+            "cpu_model": cpu_model()}
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_one_thread(W_sample: int = 1 << 20):
+    """The same oracle pipeline at one OpenMP thread, in a child process (the thread count of
+    an OpenMP runtime is fixed once it has started)."""
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-only", str(W_sample)],
+                       env=env, capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        return {"error": r.stderr.strip()[-300:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
 
 
 def main():
@@ -100,7 +122,13 @@ def main():
                          "linear layer at p = 2^32-5 (input sizes 2048-8192, slice sizes 131070-1048560); "
                          "program: the control-flow runtime on loop programs (throughput and per-entry latency)")
     ap.add_argument("--seeds", type=int, default=20, help="held-out DAG seeds of the dispatch suite")
+    ap.add_argument("--cpu-only", type=int, default=0, metavar="W",
+                    help="time only the oracle on a W-element sample of the headline pipeline (no GPU)")
     args = ap.parse_args()
+    if args.cpu_only:
+        from workloads import P127, SEEDS_TIMING
+        print(json.dumps(cpu_baseline(P127, 3, args.cpu_only, SEEDS_TIMING[0], min_s=3.0, max_passes=4)), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the build simulates all parties on one device "
               f"(--gpus {args.gpus} is not supported)", file=sys.stderr)
@@ -186,6 +214,7 @@ def main():
         out["roofline"]["frac_of_copy"] = achieved / out["extra"]["copy_GBps"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, n, args.cpu_sample, seed)
+        out["cpu_baseline"]["one_thread"] = cpu_baseline_one_thread()
     print(json.dumps(out), flush=True)
 
 
@@ -596,6 +625,10 @@ def suite_dispatch(args):
         # both policies may use the captured graph: the library replays it when every op of the
         # run is on the GPU and launches level by level otherwise
         for name, policy in (("static", S.POLICY_STATIC), ("learned", S.POLICY_LEARNED)):
+            if name == "learned":   # the first run predicts every op (later runs reuse the decisions)
+                timed_run(ctx, g, S.MODE_GRAPH, policy)
+                rec["predict_first_run_ms"] = g.last_stats()["predict_ms"]
+                rec["predict_ns_per_decision"] = rec["predict_first_run_ms"] * 1e6 / dag.n_ops
             rec[name + "_ms"] = policy_time(ctx, g, policy)
             st = g.last_stats()
             rec[name + "_cpu_ops"] = st["cpu_ops"]
@@ -631,6 +664,7 @@ def suite_dispatch(args):
             "static_mean_ms": float(np.mean(static)), "speedup_learned_vs_static": float(np.mean(static) / np.mean(learned)),
             "learned_wins_on_seeds": int(sum(l < s for l, s in zip(learned, static))),
             "best_static_threshold": best_thr, "best_static_threshold_ms": sweep_thr[best_thr],
+            "predict_ns_per_decision_mean": float(np.mean([r["predict_ns_per_decision"] for r in per_seed])),
             "threshold_sweep_ms": sweep_thr, "cost_model": {"timings": len(sw.rows), "final_mse_log2ns": float(loss[-1]),
                                                               "rmse_log2ns": rmse, "ns_per_byte": npb, "ns_per_copy": npc},
             "per_seed": per_seed}
