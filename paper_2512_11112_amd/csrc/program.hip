@@ -58,6 +58,7 @@ struct PNode {
   int block = -1;
   int64_t log_static = 0, opens = 0;  // position of its openings inside a block entry, values opened
   bool heavy = false, device = false;  // issued before light nodes; runs on the device
+  bool dev_use = false;  // a public value that a device kernel (or the output call) reads
   // buffers
   spdz_shares sh{};      // secret value: device [n][L][width] (values, MACs)
   u64 *dpub = nullptr;   // public value (or a secret node's public scratch): device [L][width]
@@ -370,8 +371,24 @@ spdz_status infer(spdz_prog *g) {
       B.opens += n.opens;
       n.heavy = ss || n.op == OP_OPEN || n.op == OP_LAYER;
       n.device = n.secret || n.op == OP_OPEN;
+      // public operands read on the device: secret + public, secret * public and
+      // public - secret (a public-operand kernel), the share of a public phi source;
+      // secret - public negates on the host
+      if (n.secret) {
+        if (n.op == OP_ADD || n.op == OP_MUL) {
+          for (int a : n.args)
+            if (!N[a].secret) N[a].dev_use = true;
+        } else if (n.op == OP_SUB && !N[n.args[0]].secret) {
+          N[n.args[0]].dev_use = true;
+        } else if (n.op == OP_PHI) {
+          for (auto &pv : n.phi)
+            if (!N[pv.first].secret) N[pv.first].dev_use = true;
+        }
+      }
     }
   }
+  for (int o : g->outputs)
+    if (!N[o].secret) N[o].dev_use = true;
   return SPDZ_OK;
 }
 
@@ -436,22 +453,19 @@ void find_loops(spdz_prog *g) {
 // --------------------------------------------------------------------------
 // buffers
 // --------------------------------------------------------------------------
+// values and MAC shares in one allocation: [values: n][L][w], then [MACs: n][L][w], so the
+// 2 n L planes of a node are equally spaced rows (one 2-D copy moves all of them)
 spdz_status alloc_shares(spdz_prog *g, spdz_shares &s, int64_t w) {
   const spdz_ctx *c = g->c;
   const size_t words = (size_t)c->n * c->L * w;
-  u64 *v = nullptr, *m = nullptr;
-  if (hipMalloc((void **)&v, words * 8) != hipSuccess) return SPDZ_E_NOMEM;
-  if (hipMalloc((void **)&m, words * 8) != hipSuccess) {
-    hipFree(v);
-    return SPDZ_E_NOMEM;
-  }
-  s = spdz_shares{v, m, w, c->L * w, w};
+  u64 *v = nullptr;
+  if (hipMalloc((void **)&v, 2 * words * 8) != hipSuccess) return SPDZ_E_NOMEM;
+  s = spdz_shares{v, v + words, w, c->L * w, w};
   return SPDZ_OK;
 }
 
 void free_shares(spdz_shares &s) {
   if (s.val) hipFree(s.val);
-  if (s.mac) hipFree(s.mac);
   s = spdz_shares{};
 }
 
@@ -610,15 +624,9 @@ spdz_status upload(spdz_prog *g, PNode &n) { return upload_words(g, n.dpub, n.hp
 
 spdz_status copy_shares(spdz_prog *g, const spdz_shares &src, int64_t first, spdz_shares &dst) {
   const spdz_ctx *c = g->c;
-  // planes [party][limb] are spaced by the node width in both buffers
-  for (u64 *const *pp : {&src.val, &src.mac}) {
-    const u64 *s = *pp + first;
-    u64 *d = pp == &src.val ? dst.val : dst.mac;
-    if (hipMemcpy2DAsync(d, dst.len * 8, s, src.len * 8, dst.len * 8, (size_t)c->n * c->L, hipMemcpyDeviceToDevice,
-                         c->stream) != hipSuccess)
-      return SPDZ_E_HIP;
-  }
-  return SPDZ_OK;
+  // the 2 n L planes (values, then MACs) are rows spaced by the node width in both buffers
+  return hip_status(hipMemcpy2DAsync(dst.val, dst.len * 8, src.val + first, src.len * 8, dst.len * 8,
+                                     (size_t)2 * c->n * c->L, hipMemcpyDeviceToDevice, c->stream));
 }
 
 bool is_product(spdz_prog *g, const PNode &n) {
@@ -672,7 +680,7 @@ spdz_status issue(spdz_prog *g, PNode &n) {
       PNode &a = N[n.args[0]], &b = N[n.args[1]];
       if (!n.secret) {
         host_visit([&](auto f) { host_binop<decltype(f)>(n.op, a.hpub, a.width, b.hpub, b.width, n.hpub, n.width); });
-        st = upload(g, n);
+        if (n.dev_use) st = upload(g, n);
       } else if (a.secret && b.secret) {
         if (n.op == OP_MUL) {
           spdz_triple *t = nullptr;
@@ -717,7 +725,7 @@ spdz_status issue(spdz_prog *g, PNode &n) {
     case OP_EQ: {
       PNode &a = N[n.args[0]], &b = N[n.args[1]];
       host_visit([&](auto f) { host_binop<decltype(f)>(n.op, a.hpub, a.width, b.hpub, b.width, n.hpub, n.width); });
-      st = upload(g, n);
+      if (n.dev_use) st = upload(g, n);
       break;
     }
     case OP_REDUCE: {
@@ -727,7 +735,7 @@ spdz_status issue(spdz_prog *g, PNode &n) {
         g->launches += 2;
       } else {
         host_visit([&](auto f) { host_reduce<decltype(f)>(a.hpub, a.width, n.hpub); });
-        st = upload(g, n);
+        if (n.dev_use) st = upload(g, n);
       }
       break;
     }
@@ -751,7 +759,7 @@ spdz_status issue(spdz_prog *g, PNode &n) {
       } else {
         for (int l = 0; l < L; l++)
           for (int64_t e = 0; e < n.width; e++) n.hpub[l * n.width + e] = base.hpub[l * base.width + s0 + e];
-        st = upload(g, n);
+        if (n.dev_use) st = upload(g, n);
       }
       break;
     }
@@ -759,7 +767,7 @@ spdz_status issue(spdz_prog *g, PNode &n) {
       PNode &s = N[n.phi_src];
       if (!n.secret) {
         std::memcpy(n.hpub, s.hpub, (size_t)L * n.width * 8);
-        st = upload(g, n);
+        if (n.dev_use) st = upload(g, n);
       } else if (s.secret) {
         st = copy_shares(g, s.sh, 0, n.sh);
       } else {
