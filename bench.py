@@ -335,13 +335,14 @@ def suite_matmul(args):
                 f"structured {rate['int8_mfma_register_tops_structured']:.0f} TOPS")
         else:
             log(f"mfma_rate failed: {r.stderr.strip()}")
+    cpu = None if args.no_cpu_baseline else cpu_baseline_matmul(2048)
     return {"metric": "matrix-triple mod-p multiply-adds per second (2 parties, p=2^61-1, N=4096)",
             "value": best["modp_mac_per_s"], "unit": "modp_mac/s", "higher_is_better": True, "n_gpus": 1,
             "dtype": "u64 (int8 digits on MFMA)", "data": "synthetic",
             "config": {"workload": "matrix_triple_n2_p61_N1024_N4096", "parties": 2, "modulus": "2^61-1"},
             "roofline": {"bound": "mfma", "achieved": best["int8_tops_equiv"], "peak": 5000.0, "unit": "TOPS (int8)",
                          "frac": best["int8_tops_equiv"] / 5000.0, "traffic": None},
-            "mfma_rate_calibration": rate,
+            "mfma_rate_calibration": rate, "cpu_baseline": cpu,
             "mfma_over_valu_N4096": res["N4096_valu"]["gemm_ms"] / res["N4096_mfma"]["gemm_ms"],
             "mfma_over_valu_N1024": res["N1024_valu"]["gemm_ms"] / res["N1024_mfma"]["gemm_ms"],
             "results": res}
@@ -441,6 +442,47 @@ def cpu_baseline_layer(tiles: int):
             "kind": "oracle", "sample": f"{rows} of the 8192 rows ({-(-rows // cfg.tile_rows)} tiles) of the d=8192 "
                                         f"layer, whole protocol (opens, products, MAC check) on the oracle, "
                                         f"{dt:.2f} s wall, scaled by 8192/{rows}; dealing excluded"}
+
+
+def cpu_baseline_matmul(N: int):
+    """The oracle's whole matrix-triple product (opens, 9 N^3 mod-p multiply-adds, MAC check)
+    at one size; its rate stands for the N = 4096 product (same arithmetic per multiply-add)."""
+    from oracle.pipelines import deal_matrices, matrix_triple_run
+    from workloads import P61
+    D = deal_matrices(P61, 2, N, N, N, 1)
+    t0 = time.perf_counter()
+    r = matrix_triple_run(D, check_seed=1)
+    dt = time.perf_counter() - t0
+    assert r["ok"]
+    return {"value": 9 * N ** 3 / dt, "unit": "modp_mac/s",
+            "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)), "kind": "oracle",
+            "sample": f"one N={N} matrix-triple product (2 parties, 2^61-1: opens, 9 N^3 mod-p multiply-adds with "
+                      f"128-bit products, MAC check) on the oracle, {dt:.2f} s wall, dealing excluded; "
+                      f"the N=4096 product does {(4096 // N) ** 3}x the multiply-adds at the same rate",
+            "cpu_model": cpu_model()}
+
+
+def cpu_baseline_dag(depth: int = 40):
+    """The oracle executing a DAG of `depth` levels drawn like the 200-level one, op by op."""
+    import numpy as np
+    from oracle.pipelines import dag_run
+    from workloads import P61
+    from workloads.dag import make_dag
+    dag = make_dag(SEEDS_DAG_CPU, P61, depth=depth)
+    elems = int(np.sum(dag.width))
+    t0 = time.perf_counter()
+    _, ok, _ = dag_run(dag, SEEDS_DAG_CPU, SEEDS_DAG_CPU, keep=[])
+    dt = time.perf_counter() - t0
+    assert ok
+    return {"value": elems / dt, "unit": "op-elements/s",
+            "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)), "kind": "oracle",
+            "sample": f"a {depth}-level DAG of the same generator (500 ops per level, {elems} op-elements, seed "
+                      f"{SEEDS_DAG_CPU}) run op by op on the oracle with its final MAC check, {dt:.2f} s wall, "
+                      f"dealing included; about {200 / depth:.0f}x this for the 200-level DAG",
+            "cpu_model": cpu_model()}
+
+
+SEEDS_DAG_CPU = 1
 
 
 def loop_program_bytes(n: int, L: int, W: int, trips: int):
@@ -578,6 +620,11 @@ def suite_dag(args):
         res[name] = _median(ts)
         log(f"dag {name}: {res[name]:.2f} ms")
     B = dag_alg_bytes(dag)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import numpy as np
+        cpu = cpu_baseline_dag(40)
+        cpu["full_dag_ms_at_this_rate"] = float(np.sum(dag.width)) / cpu["value"] * 1e3
     return {"metric": "end-to-end DAG time incl. MAC-check verdict (100k ops, depth 200, 2 parties, p=2^61-1)",
             "value": res["graph"], "unit": "ms", "higher_is_better": False, "n_gpus": 1, "dtype": "u64",
             "data": "synthetic", "config": {"workload": f"dag_100k_depth200_seed{seed}", "parties": 2,
@@ -587,7 +634,8 @@ def suite_dag(args):
             "autotune": {"tile": tile, "blocks_per_cu": bpc},
             "roofline": {"bound": "hbm", "achieved": B / (res["graph"] * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": B / (res["graph"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                         "alg_bytes": B, "traffic": None}}
+                         "alg_bytes": B, "traffic": None},
+            "cpu_baseline": cpu}
 
 
 def policy_time(ctx, g, policy):
