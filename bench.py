@@ -485,12 +485,14 @@ def cpu_baseline_dag(depth: int = 40):
 SEEDS_DAG_CPU = 1
 
 
-def loop_program_bytes(n: int, L: int, W: int, trips: int):
-    """Algorithmic bytes of the loop program's online device work: per iteration three
-    Beaver products (12 n L words per element each, triples read from HBM), two secret
-    additions (6 n L) and the phi copy of the accumulator (4 n L); dealing a product's
-    triple on the fly would write 6 n L more (reported apart)."""
-    per_iter = (3 * 12 + 2 * 6 + 4) * n * L * 8 * W
+def loop_program_bytes(n: int, L: int, W: int, trips: int, fused: bool = True):
+    """Algorithmic bytes of the loop program's online device work per run.  Fused (the
+    runtime's default), the body's chain of three products and two additions is one kernel:
+    it reads the three outside operands (acc, x, y: 2 n L words per element each) and the
+    three triples (6 n L each) and writes the accumulator (2 n L); the phi copy moves 4 n L.
+    Node by node, each product moves 12 n L words and each addition 6 n L.  Dealing a
+    product's triple on the fly would write 6 n L more (reported apart)."""
+    per_iter = ((3 * 2 + 3 * 6 + 2 + 4) if fused else (3 * 12 + 2 * 6 + 4)) * n * L * 8 * W
     deal = 3 * 6 * n * L * 8 * W
     return per_iter * trips, deal * trips
 
@@ -507,9 +509,10 @@ def suite_program(args):
     from workloads import P_PAPER, SEEDS_TIMING, programs as PR
     seed, n, p = SEEDS_TIMING[0], 2, P_PAPER
     res = {}
-    for W, trips, reps in ((1 << 22, 16, 5), (64, 2000, 3)):
+    for W, trips, reps, fuse in ((1 << 22, 16, 5, True), (64, 2000, 3, True), (1 << 22, 16, 3, False),
+                                 (64, 2000, 3, False)):
         ctx = S.Context(n, p, S.deal_alpha(p, n, seed), seed)
-        prog = S.Program(ctx, PR.loop_program(W, trips))
+        prog = S.Program(ctx, PR.loop_program(W, trips), fuse=fuse)
         ok, _, ms_deal = prog.run(seed)   # warm-up, triples dealt on the fly
         assert ok
         prog.predeal(seed, trips)         # fake preprocessing ahead of the timed online runs
@@ -524,21 +527,21 @@ def suite_program(args):
         ok, _, _ = prog.run(seed)
         assert ok
         kern = 0.0
-        for k in ("beaver", "linear", "public_op", "open", "reduce"):
+        for k in ("fused", "beaver", "linear", "public_op", "open", "reduce"):
             t, c = ctx.spdz_timing_get(k)
             kern += t
         ctx.spdz_timing_enable(False)
         reps = 1
         ms = _median(walls)
-        alg, deal = loop_program_bytes(n, 1, W, trips)
+        alg, deal = loop_program_bytes(n, 1, W, trips, fused=fuse)
         mults = 3 * W * trips
-        res[f"W{W}_trips{trips}"] = {
+        res[f"W{W}_trips{trips}" + ("" if fuse else "_node_by_node")] = {
             "wall_ms": ms, "kernel_ms_sum": kern / reps, "host_overhead_ms": ms - kern / reps,
             "block_entries": st["block_entries"], "launches": st["launches"], "host_syncs": st["host_syncs"],
             "us_per_block_entry": ms * 1e3 / st["block_entries"], "mults_per_s": mults / (ms * 1e-3),
             "alg_GBps": alg / (ms * 1e-3) / 1e9, "alg_bytes": alg,
             "wall_ms_dealing_on_the_fly": ms_deal, "dealing_bytes": deal}
-        log(f"program W={W} trips={trips}: {ms:.3f} ms wall, kernels {kern / reps:.3f} ms, "
+        log(f"program W={W} trips={trips} {'fused' if fuse else 'node by node'}: {ms:.3f} ms wall, kernels {kern / reps:.3f} ms, "
             f"{st['block_entries']} block entries ({ms * 1e3 / st['block_entries']:.1f} us each), "
             f"{st['launches']} launches, {st['host_syncs']} syncs, {mults / (ms * 1e-3) / 1e9:.2f} G mult/s")
         prog.close()
@@ -551,7 +554,7 @@ def suite_program(args):
            "steps": 5, "warmup": 1, "ms_per_step": big["wall_ms"], "vs_baseline": None,
            "dtype": "u64 words (residues < 2^32)", "data": "synthetic",
            "config": {"workload": "loop_program_n2_p32_w4194304_trips16", "parties": 2, "modulus": "2^32-5"},
-           "roofline": {"bound": "hbm", "kernel": "whole program (Beaver, linear, copies)",
+           "roofline": {"bound": "hbm", "kernel": "whole program (fused runs, phi copies)",
                         "achieved": big["alg_GBps"], "peak": 8000.0, "unit": "GB/s", "frac": big["alg_GBps"] / 8000.0,
                         "traffic": None},
            "results": res}

@@ -400,6 +400,17 @@ spdz_status spdz_prog_run(spdz_prog *prog, uint64_t seed, int *accepted, uint64_
  * executions beyond them.  Replaces earlier pools.  Synchronous. */
 spdz_status spdz_prog_predeal(spdz_prog *prog, uint64_t seed, int64_t executions);
 
+/* Fused execution of element-wise runs (vectorized nodes batched into one kernel,
+ * Sec. III-B "Vectorization is first-class"): consecutive secret +, - and *
+ * nodes of one block and one width (Beaver products, share sums and
+ * differences, sums and products with public values) run as one kernel whose
+ * intermediates stay on chip; a node's buffer is written only when something
+ * outside the run reads it.  Shares, opened values and sigma are bit-identical
+ * either way; only the device work changes.  On by default.  enable: 0 runs
+ * every node as its own kernel.  *n_groups (nullable): the number of fused
+ * runs the program has.  Not during a run. */
+spdz_status spdz_prog_set_fusion(spdz_prog *prog, int enable, int *n_groups);
+
 /* After a run: an output node's final value, into out_shares (secret; len =
  * the node's width, any strides) or out_pub (public; DEVICE [L][width]).
  * SPDZ_E_INVAL for a node that is not an output.  Synchronous. */

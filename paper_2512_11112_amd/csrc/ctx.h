@@ -147,6 +147,25 @@ spdz_status launch_linear(spdz_ctx *c, int nt, const spdz_shares *terms, const u
                           spdz_shares *out);
 spdz_status launch_reduce(spdz_ctx *c, const spdz_shares *x, spdz_shares *out);
 // out = x + v, x * v or share(v) for a public v of width out->len or 1 (mode SPDZ_PUB_*)
+// One instruction of a fused element-wise group of the program runtime (fused.hip).  Slots
+// are per-thread LDS registers holding one secret value (n value and n MAC shares); a
+// node buffer is the runtime's layout [values: n][L][W] then [MACs: n][L][W].
+enum FusedKind : uint8_t { FK_LOAD = 0, FK_BEAVER = 1, FK_LIN = 2, FK_PUBADD = 3, FK_PUBMUL = 4 };
+enum FusedFlag : uint8_t { FF_STORE = 1, FF_SUB = 2, FF_NEG_A = 4, FF_NEG_P = 8, FF_PUB_VEC = 16 };
+struct FusedIns {
+  uint8_t kind, dst, a, b, flags, pad[3];
+  const u64 *p0, *p1, *p2;  // LOAD: node buffer; BEAVER: triple a, b, c buffers; PUB*: public [L][W or 1]
+  u64 *out;                 // FF_STORE: node buffer the result is written to
+  int64_t j;                // BEAVER: log index of d_0 (e_0 at j + W)
+};
+constexpr int FUSED_MAX_INS = 24;
+constexpr int FUSED_LDS_BYTES = 61440;  // dynamic LDS of one group launch
+// bytes of one LDS word of a slot: residues below 2^32 take 4, others 8 per limb
+inline int fused_word_bytes(int fid) { return fid == FID_32 ? 4 : 8; }
+inline int fused_max_slots(int n, int L, int fid) { return FUSED_LDS_BYTES / (2 * n * L * fused_word_bytes(fid) * BLOCK); }
+// runs the group over W elements; Beaver instructions add to the MAC-check slots
+spdz_status launch_fused(spdz_ctx *c, const FusedIns *ins, int nins, int nslots, int64_t W);
+
 spdz_status launch_pubop(spdz_ctx *c, int mode, const spdz_shares *x, const u64 *v, int64_t vwidth,
                          spdz_shares *out);
 spdz_status launch_reduce_finalize(spdz_ctx *c, int grid, spdz_shares *out);

@@ -59,6 +59,7 @@ struct PNode {
   int64_t log_static = 0, opens = 0;  // position of its openings inside a block entry, values opened
   bool heavy = false, device = false;  // issued before light nodes; runs on the device
   bool dev_use = false;  // a public value that a device kernel (or the output call) reads
+  int group = -1;        // fused element-wise group (one kernel for the group's nodes)
   // buffers
   spdz_shares sh{};      // secret value: device [n][L][width] (values, MACs)
   u64 *dpub = nullptr;   // public value (or a secret node's public scratch): device [L][width]
@@ -88,6 +89,20 @@ struct Loop {
   int header = -1;
   std::vector<int> members;
   int64_t outstanding = 0;
+};
+
+// consecutive secret element-wise nodes of one block and width, run as one kernel
+struct FGroup {
+  struct Step {
+    uint8_t kind, dst, a, b, flags;
+    int node;  // LOAD: the external node; otherwise the member computed
+    int pub;   // public operand of FK_PUBADD / FK_PUBMUL
+  };
+  std::vector<int> members;  // program order; members[0] represents the group in the queues
+  std::vector<Step> plan;
+  int nslots = 0;
+  int64_t width = 0;
+  bool heavy = false, queued = false;
 };
 
 bool parse_int(const std::string &s, int64_t &v) {
@@ -121,6 +136,8 @@ struct spdz_prog {
   u64 *arena = nullptr;
   size_t arena_words = 0, arena_used = 0;
   u64 pool_seed = 0;
+  std::vector<FGroup> groups;
+  bool fuse = true;
 };
 
 namespace {
@@ -371,15 +388,12 @@ spdz_status infer(spdz_prog *g) {
       B.opens += n.opens;
       n.heavy = ss || n.op == OP_OPEN || n.op == OP_LAYER;
       n.device = n.secret || n.op == OP_OPEN;
-      // public operands read on the device: secret + public, secret * public and
-      // public - secret (a public-operand kernel), the share of a public phi source;
-      // secret - public negates on the host
+      // public operands read on the device: those of a secret +, - or * (public-operand
+      // kernels, fused groups) and the share of a public phi source
       if (n.secret) {
-        if (n.op == OP_ADD || n.op == OP_MUL) {
+        if (n.op == OP_ADD || n.op == OP_SUB || n.op == OP_MUL) {
           for (int a : n.args)
             if (!N[a].secret) N[a].dev_use = true;
-        } else if (n.op == OP_SUB && !N[n.args[0]].secret) {
-          N[n.args[0]].dev_use = true;
         } else if (n.op == OP_PHI) {
           for (auto &pv : n.phi)
             if (!N[pv.first].secret) N[pv.first].dev_use = true;
@@ -447,6 +461,120 @@ void find_loops(spdz_prog *g) {
     size_t best = SIZE_MAX;
     for (int l : B.loops)
       if (g->loops[l].members.size() < best) best = g->loops[l].members.size(), B.inner = l;
+  }
+}
+
+// --------------------------------------------------------------------------
+// fused element-wise groups
+// --------------------------------------------------------------------------
+bool fusable(const spdz_prog *g, const PNode &n) {
+  return n.secret && (n.op == OP_ADD || n.op == OP_SUB || n.op == OP_MUL);
+}
+
+// Compiles `run` (member ids in program order) into load and compute steps over at
+// most `maxs` LDS slots; false if it does not fit or a member reads a later member.
+bool compile_group(spdz_prog *g, const std::vector<int> &run, int maxs, FGroup &G) {
+  auto &N = g->nodes;
+  std::unordered_map<int, int> idx, last;  // member index; last member index reading a value
+  for (size_t k = 0; k < run.size(); k++) idx[run[k]] = (int)k;
+  for (size_t k = 0; k < run.size(); k++)
+    for (int a : N[run[k]].args) {
+      auto it = idx.find(a);
+      if (it != idx.end() && it->second >= (int)k) return false;
+      if (N[a].secret) last[a] = (int)k;
+    }
+  std::vector<int> free_slots;
+  for (int q = maxs - 1; q >= 0; q--) free_slots.push_back(q);
+  std::unordered_map<int, int> slot;  // value id -> slot
+  int used = 0;
+  auto take = [&](int &q) {
+    if (free_slots.empty()) return false;
+    q = free_slots.back();
+    free_slots.pop_back();
+    used = std::max(used, q + 1);
+    return true;
+  };
+  G = FGroup{};
+  for (size_t k = 0; k < run.size(); k++) {
+    const PNode &n = N[run[k]];
+    for (int a : n.args)
+      if (N[a].secret && !slot.count(a)) {  // an external secret operand: load it
+        int q;
+        if (!take(q)) return false;
+        slot[a] = q;
+        G.plan.push_back({FK_LOAD, (uint8_t)q, 0, 0, 0, a, -1});
+      }
+    int dst;
+    if (!take(dst)) return false;  // never an operand's slot: operands are read while it is written
+    FGroup::Step st{0, (uint8_t)dst, 0, 0, 0, n.id, -1};
+    const PNode &x = N[n.args[0]], &y = N[n.args[1]];
+    if (x.secret && y.secret) {
+      st.kind = n.op == OP_MUL ? FK_BEAVER : FK_LIN;
+      st.a = (uint8_t)slot[x.id];
+      st.b = (uint8_t)slot[y.id];
+      if (n.op == OP_SUB) st.flags |= FF_SUB;
+      G.heavy = G.heavy || n.op == OP_MUL;
+    } else {
+      const PNode &sec = x.secret ? x : y, &pub = x.secret ? y : x;
+      st.kind = n.op == OP_MUL ? FK_PUBMUL : FK_PUBADD;
+      st.a = (uint8_t)slot[sec.id];
+      st.pub = pub.id;
+      if (pub.width > 1) st.flags |= FF_PUB_VEC;
+      if (n.op == OP_SUB) st.flags |= x.secret ? FF_NEG_P : FF_NEG_A;
+    }
+    // stored when anything outside the group reads it (other blocks, phi, later nodes) or it is an output
+    bool store = std::find(g->outputs.begin(), g->outputs.end(), n.id) != g->outputs.end();
+    for (int u : n.users) store = store || !idx.count(u);
+    if (store) st.flags |= FF_STORE;
+    G.plan.push_back(st);
+    slot[n.id] = dst;
+    // release operands read for the last time here, and the result if nothing later reads it
+    for (int a : n.args)
+      if (N[a].secret && last.count(a) && last[a] == (int)k && slot.count(a)) {
+        free_slots.push_back(slot[a]);
+        slot.erase(a);
+      }
+    if (!last.count(n.id)) {
+      free_slots.push_back(dst);
+      slot.erase(n.id);
+    }
+  }
+  if ((int)G.plan.size() > FUSED_MAX_INS) return false;
+  G.members = run;
+  G.nslots = used;
+  G.width = N[run[0]].width;
+  return true;
+}
+
+// groups of two or more consecutive fusable nodes of one width in each block
+void build_groups(spdz_prog *g) {
+  auto &N = g->nodes;
+  const int maxs = std::min(fused_max_slots(g->c->n, g->c->L, g->c->fid), 255);
+  if (maxs < 3) return;  // a product needs its two operands and its result
+  for (int b : g->block_order) {
+    const std::vector<int> &lines = g->blocks[b].lines;
+    size_t i = 0;
+    while (i < lines.size()) {
+      if (!fusable(g, N[lines[i]])) {
+        i++;
+        continue;
+      }
+      std::vector<int> run;
+      FGroup G, trial;
+      for (size_t j = i; j < lines.size() && fusable(g, N[lines[j]]) && N[lines[j]].width == N[lines[i]].width; j++) {
+        run.push_back(lines[j]);
+        if (!compile_group(g, run, maxs, trial)) {
+          run.pop_back();
+          break;
+        }
+        G = trial;
+      }
+      if (run.size() >= 2) {
+        for (int m : run) N[m].group = (int)g->groups.size();
+        g->groups.push_back(G);
+      }
+      i += std::max<size_t>(run.size(), 1);
+    }
   }
 }
 
@@ -557,7 +685,25 @@ bool ready(spdz_prog *g, const PNode &n) {
   return true;
 }
 
+bool group_ready(spdz_prog *g, const FGroup &G) {
+  auto &N = g->nodes;
+  for (int m : G.members) {
+    const PNode &n = N[m];
+    if (!n.pending) return false;
+    for (int a : n.args)
+      if (N[a].group != n.group && !N[a].dev_ready) return false;
+  }
+  return true;
+}
+
 void enqueue(spdz_prog *g, PNode &n) {
+  if (g->fuse && n.group >= 0) {  // a member of a fused group: the group is queued once, when all its inputs are
+    FGroup &G = g->groups[n.group];
+    if (G.queued || !group_ready(g, G)) return;
+    G.queued = true;
+    (G.heavy ? g->heavy : g->light).push_back(G.members[0]);
+    return;
+  }
   if (!n.pending || n.queued || !ready(g, n)) return;
   n.queued = true;
   (n.heavy ? g->heavy : g->light).push_back(n.id);
@@ -586,6 +732,8 @@ spdz_status enter_block(spdz_prog *g, int dst, int pred) {
     g->pending_total++;
     for (int l : B.loops) g->loops[l].outstanding++;
   }
+  for (int id : B.lines)
+    if (N[id].group >= 0) g->groups[N[id].group].queued = false;
   g->log_cur += B.opens;
   g->cur = dst;
   for (int id : B.lines) enqueue(g, N[id]);
@@ -658,10 +806,58 @@ spdz_status node_triple(spdz_prog *g, PNode &n, spdz_triple *&t) {
   return deal_node_triple(g, n, k, g->seed, n.tri);
 }
 
+// one launch for a fused group: external operands loaded, intermediates in LDS,
+// results stored where anything outside the group reads them
+spdz_status issue_group(spdz_prog *g, FGroup &G) {
+  spdz_ctx *c = g->c;
+  auto &N = g->nodes;
+  G.queued = false;
+  FusedIns ins[FUSED_MAX_INS];
+  for (size_t q = 0; q < G.plan.size(); q++) {
+    const FGroup::Step &st = G.plan[q];
+    FusedIns &I = ins[q];
+    I = FusedIns{};
+    I.kind = st.kind;
+    I.dst = st.dst;
+    I.a = st.a;
+    I.b = st.b;
+    I.flags = st.flags;
+    PNode &m = N[st.node];
+    if (st.kind == FK_LOAD) {
+      I.p0 = m.sh.val;
+      continue;
+    }
+    if (st.kind == FK_BEAVER) {
+      spdz_triple *t = nullptr;
+      SPDZ_RET(node_triple(g, m, t));
+      I.p0 = t->a.val;
+      I.p1 = t->b.val;
+      I.p2 = t->c.val;
+      I.j = m.log_off;
+    } else if (st.kind == FK_PUBADD || st.kind == FK_PUBMUL) {
+      I.p0 = N[st.pub].dpub;
+    }
+    if (st.flags & FF_STORE) I.out = m.sh.val;
+  }
+  SPDZ_RET(launch_fused(c, ins, (int)G.plan.size(), G.nslots, G.width));
+  g->launches++;
+  for (int id : G.members) {
+    PNode &n = N[id];
+    n.pending = false;
+    g->pending_total--;
+    for (int l : g->blocks[n.block].loops) g->loops[l].outstanding--;
+    n.dev_ready = true;
+  }
+  for (int id : G.members)
+    for (int u : N[id].users) enqueue(g, N[u]);
+  return SPDZ_OK;
+}
+
 spdz_status issue(spdz_prog *g, PNode &n) {
   spdz_ctx *c = g->c;
   auto &N = g->nodes;
   const int L = c->L;
+  if (g->fuse && n.group >= 0) return issue_group(g, g->groups[n.group]);
   n.pending = false;
   g->pending_total--;
   for (int l : g->blocks[n.block].loops) g->loops[l].outstanding--;
@@ -929,6 +1125,7 @@ spdz_status spdz_prog_create(spdz_ctx *c, const char *text, spdz_prog **out, cha
   if (st == SPDZ_OK) st = infer(g);
   if (st == SPDZ_OK) {
     find_loops(g);
+    build_groups(g);
     st = alloc_buffers(g);
   }
   if (st != SPDZ_OK) {
@@ -998,6 +1195,13 @@ spdz_status spdz_prog_predeal(spdz_prog *g, uint64_t seed, int64_t executions) {
     }
   }
   return hip_status(hipStreamSynchronize(g->c->stream));
+}
+
+spdz_status spdz_prog_set_fusion(spdz_prog *g, int enable, int *n_groups) {
+  if (!g) return SPDZ_E_INVAL;
+  g->fuse = enable != 0;
+  if (n_groups) *n_groups = (int)g->groups.size();
+  return SPDZ_OK;
 }
 
 spdz_status spdz_prog_output(spdz_prog *g, int node, spdz_shares *out_shares, uint64_t *out_pub) {

@@ -33,17 +33,19 @@ PROGRAMS = [("pipeline", P.pipeline(3001)), ("branch", P.branch(777)), ("loop", 
             ("loop_program", P.loop_program(2048, 4))]
 
 
+@pytest.mark.parametrize("fuse", [True, False])
 @pytest.mark.parametrize("p,n", [(P_PAPER, 2), (P61, 3), (P127, 2)])
 @pytest.mark.parametrize("name,text", PROGRAMS)
-def test_program_matches_oracle(name, text, p, n):
+def test_program_matches_oracle(name, text, p, n, fuse):
+    """Fused element-wise runs (default) and node-by-node execution both match the oracle."""
     from paper_2512_11112_amd.spdz import Program
     if name == "layer" and p == P127:
         pytest.skip("layers need a single-limb field")
-    print(f"case {name} p-bits={p.bit_length()} n={n}", flush=True)
+    print(f"case {name} p-bits={p.bit_length()} n={n} fuse={fuse}", flush=True)
     seed, check = 21, 22
     ref = run_program(text, p, n, seed, check)
     ctx = ctx_for(p, n, seed, check)
-    prog = Program(ctx, text)
+    prog = Program(ctx, text, fuse=fuse)
     ok, sigma, ms = prog.run(seed)
     for o, v in ref["outputs"].items():
         got = prog.output(o)
@@ -129,3 +131,65 @@ def test_predealt_triples_give_the_same_run(pool_seed):
     assert np.array_equal(host(got.val), ref["outputs"][6].val)
     assert np.array_equal(host(got.mac), ref["outputs"][6].mac)
     assert ok and sigma == ints_of_sigma(ref["sigma"])
+
+
+@pytest.mark.parametrize("p,n", [(P_PAPER, 2), (P61, 4), (P127, 2), (P61, 8), (P_PAPER, 8)])
+def test_fused_groups_formed_and_identical(p, n):
+    """The loop body's chain (3 products, 2 additions) is one fused run where the slots fit
+    (none at 8 parties: a product needs 3 slots); fused and unfused runs give the same bits."""
+    from paper_2512_11112_amd.spdz import Program
+    text = P.loop_program(3001, 3)
+    # one context each: every run starts a new MAC-check epoch of its context
+    a, b = Program(ctx_for(p, n, 4, 5), text, fuse=True), Program(ctx_for(p, n, 4, 5), text, fuse=False)
+    word = 4 if p == P_PAPER else 8
+    assert (a.n_groups >= 1) == (n * (2 if p == P127 else 1) * 2 * word * 256 * 3 <= 61440)
+    ra, rb = a.run(4), b.run(4)
+    assert ra[0] and rb[0] and ra[1] == rb[1]
+    for o in (6, 15):
+        ga, gb = a.output(o), b.output(o)
+        if hasattr(ga, "val"):
+            assert np.array_equal(host(ga.val), host(gb.val)) and np.array_equal(host(ga.mac), host(gb.mac))
+        else:
+            assert np.array_equal(host(ga), host(gb))
+    if a.n_groups:
+        assert a.stats()["launches"] < b.stats()["launches"]
+    else:
+        assert a.stats()["launches"] == b.stats()["launches"]
+    ref = run_program(text, p, n, 4, 5)
+    assert ra[1] == ints_of_sigma(ref["sigma"])
+    a.close()
+    b.close()
+
+
+def test_fused_public_operands():
+    """Fused runs with public scalars and vectors on either side of +, - and *."""
+    from paper_2512_11112_amd.spdz import Program
+    W = 777
+    text = f"""
+input 1 private {W} 0
+input 2 private {W} 1
+input 3 public {W} 2
+const 4 1 7
+output 12
+block 0
+5 = mul 1 2
+6 = sub 5 3
+7 = sub 3 6
+8 = mul 7 4
+9 = add 4 8
+10 = sub 9 4
+11 = mul 3 10
+12 = mul 11 1
+ret
+"""
+    for p, n in [(P_PAPER, 2), (P61, 3), (P127, 2)]:
+        ref = run_program(text, p, n, 8, 9)
+        ctx = ctx_for(p, n, 8, 9)
+        prog = Program(ctx, text)
+        assert prog.n_groups == 1
+        ok, sigma, _ = prog.run(8)
+        got = prog.output(12)
+        assert np.array_equal(host(got.val), ref["outputs"][12].val)
+        assert np.array_equal(host(got.mac), ref["outputs"][12].mac)
+        assert ok and sigma == ints_of_sigma(ref["sigma"])
+        prog.close()
