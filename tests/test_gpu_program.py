@@ -193,3 +193,36 @@ ret
         assert np.array_equal(host(got.mac), ref["outputs"][12].mac)
         assert ok and sigma == ints_of_sigma(ref["sigma"])
         prog.close()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("fuse", [True, False])
+def test_program_full_size(fuse):
+    """The runtime at the benchmark's configuration (loop program, width 2^22, 16 iterations,
+    2 parties, p = 2^32 - 5, triples dealt ahead): every element of the accumulator
+    reconstructs to acc <- acc y + x iterated 16 times from acc = x (values below 2^32, so
+    uint64 arithmetic is exact), its MAC shares to alpha times it, the opened sum to the sum of
+    all elements, and the MAC check accepts."""
+    from paper_2512_11112_amd.spdz import Program
+    p, n, W, T, seed = P_PAPER, 2, 1 << 22, 16, 1
+    print(f"case loop program W={W} T={T} fuse={fuse}", flush=True)
+    ctx = ctx_for(p, n, seed, seed)
+    prog = Program(ctx, P.loop_program(W, T), fuse=fuse)
+    prog.predeal(seed, T)
+    ok, sigma, _ = prog.run(seed)
+    assert ok and sum(sigma) % p == 0
+    f = F.Field(p)
+    x = f.deal_values(seed, 0, W)[0]
+    y = f.deal_values(seed, 1, W)[0]
+    acc = x.copy()
+    P64 = np.uint64(p)
+    for _ in range(T):
+        acc = (acc * y + x) % P64
+    got = prog.output(6)
+    v, m = host(got.val).reshape(n, W), host(got.mac).reshape(n, W)
+    assert np.array_equal((v[0] + v[1]) % P64, acc)
+    alpha = np.uint64(sum(int(a) for a in f.alpha_shares(n, seed)[:, 0]) % p)
+    assert np.array_equal((m[0] + m[1]) % P64, (acc * alpha) % P64)
+    s = host(prog.output(15))
+    assert int(s.reshape(-1)[0]) == int(acc.astype(object).sum() % p)
+    prog.close()
