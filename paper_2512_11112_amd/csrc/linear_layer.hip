@@ -10,7 +10,7 @@
 // then y_t = Z_t + b_t.  Every opened value enters the MAC check.
 //
 // Two kernels.  k_ll_open_e opens every E_t (n_tiles * din values, small).
-// k_ll_rows streams W and A once: one block per output row, its threads over
+// k_ll_rows streams W and A once: one block per output row (or two rows of a tile), its threads over
 // the row's din elements; each element's D is opened in registers (stored
 // only if the caller asks), its MAC-check terms are accumulated, and the row
 // sums D B_i + A_i E (values and MACs, every party) and D E are formed; B_t
@@ -23,6 +23,10 @@
 #include "coef.h"
 
 namespace spdz {
+
+// rows of one tile per block of the row kernel: two share each E_t / B_t read where tiles are
+// tall and there are rows enough to fill the GPU, else one (measured at d = 2048 .. 8192)
+inline int ll_rows_per_block(int64_t dout, int64_t tile_rows) { return tile_rows >= 31 && dout >= 4096 ? 2 : 1; }
 
 template <class F, int N>
 struct LayerArgs {
@@ -76,92 +80,121 @@ __device__ __forceinline__ typename F::E wave_sum(typename F::E v) {
   return v;
 }
 
-// one block per row of W (grid-stride over rows), the row's elements strided by the
-// block size; at the end of a row the 2 N + 1 sums go through wave shuffles and LDS
-template <class F, int N>
+// one block per group of up to R consecutive rows of one tile (grid-stride over the groups),
+// the rows' elements strided by the block size: each element's E_t and B_t words are read
+// once for the R rows; at the end of a group the R (2 N + 1) row sums go through wave
+// shuffles and LDS
+template <class F, int N, int R>
 __global__ __launch_bounds__(BLOCK) void k_ll_rows(const LayerArgs<F, N> A) {
   using E = typename F::E;
   using Wd = typename F::Wide;
   constexpr int K = 2 * N + 1;  // row sums: D E, then D B_i + A_i E, then the MAC versions
-  // every Wide accumulator takes at most two products per element
-  constexpr int64_t CHUNK = (int64_t)BLOCK * (F::WIDE_TERMS / 2);
-  __shared__ E part[WAVES][K];
+  // a row-sum accumulator takes two products per element, a MAC-check one takes 2 R
+  constexpr int64_t CHUNK = (int64_t)BLOCK * (F::WIDE_TERMS / (2 * R));
+  static_assert(F::WIDE_TERMS >= 2 * R, "wide accumulators too narrow for R rows");
+  __shared__ E part[WAVES][R][K];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   E mc[N + 1];
 #pragma unroll
   for (int k = 0; k <= N; k++) mc[k] = F::zero();
+  const int64_t gpt = (A.tile_rows + R - 1) / R, ngroups = A.n_tiles * gpt;
 
-  for (int64_t r = blockIdx.x; r < A.dout; r += gridDim.x) {
-    const int64_t t = r / A.tile_rows;
-    const int64_t jrow = A.j0 + tile_base(t, A.tile_rows, A.din) + (r - t * A.tile_rows) * A.din;
-    const int64_t wrow = r * A.din, brow = t * A.din;
-    E sum[K];
+  for (int64_t gi = blockIdx.x; gi < ngroups; gi += gridDim.x) {
+    const int64_t t = gi / gpt;
+    const int64_t r0 = t * A.tile_rows + (gi - t * gpt) * R;
+    const int64_t tend = min(A.dout, (t + 1) * A.tile_rows);
+    const int nr = (int)min((int64_t)R, tend - r0);  // rows of this group (>= 1)
+    const int64_t jrow0 = A.j0 + tile_base(t, A.tile_rows, A.din) + (r0 - t * A.tile_rows) * A.din;
+    const int64_t brow = t * A.din;
+    E sum[R][K];
 #pragma unroll
-    for (int j = 0; j < K; j++) sum[j] = F::zero();
+    for (int q = 0; q < R; q++)
+#pragma unroll
+      for (int j = 0; j < K; j++) sum[q][j] = F::zero();
     for (int64_t k0 = 0; k0 < A.din; k0 += CHUNK) {
-      Wd w[K], wmc[N + 1];
+      Wd w[R][K], wmc[N + 1];
 #pragma unroll
-      for (int j = 0; j < K; j++) w[j] = F::wzero();
+      for (int q = 0; q < R; q++)
+#pragma unroll
+        for (int j = 0; j < K; j++) w[q][j] = F::wzero();
 #pragma unroll
       for (int i = 0; i <= N; i++) wmc[i] = F::wzero();
       const int64_t kend = min(A.din, k0 + CHUNK);
       for (int64_t k = k0 + threadIdx.x; k < kend; k += BLOCK) {
-        E av[N], am[N], wm[N], dv = F::zero();
-#pragma unroll
-        for (int i = 0; i < N; i++) {
-          const E wv = F::load(A.W.val + i * A.W.ps, 0, wrow + k);
-          wm[i] = F::load(A.W.mac + i * A.W.ps, 0, wrow + k);
-          av[i] = F::load(A.A.val + i * A.A.ps, 0, wrow + k);
-          am[i] = F::load(A.A.mac + i * A.A.ps, 0, wrow + k);
-          dv = F::add(dv, F::sub(wv, av[i]));
-        }
-        if (A.D_pub) F::store(A.D_pub, 0, wrow + k, dv);
         const E ev = F::load_cached(A.E, 0, brow + k);
-        const E rj = uniform_elem<F>(A.coef_state, (u64)(jrow + k));
-        F::wmac(wmc[0], rj, dv);
-        F::wmac(w[0], dv, ev);
+        E bv[N], bm[N];
 #pragma unroll
         for (int i = 0; i < N; i++) {
-          F::wmac(wmc[1 + i], rj, F::sub(wm[i], am[i]));
-          F::wmac(w[1 + i], dv, F::load_cached(A.B.val + i * A.B.ps, 0, brow + k));
-          F::wmac(w[1 + i], av[i], ev);
-          F::wmac(w[1 + N + i], dv, F::load_cached(A.B.mac + i * A.B.ps, 0, brow + k));
-          F::wmac(w[1 + N + i], am[i], ev);
+          bv[i] = F::load_cached(A.B.val + i * A.B.ps, 0, brow + k);
+          bm[i] = F::load_cached(A.B.mac + i * A.B.ps, 0, brow + k);
+        }
+#pragma unroll
+        for (int q = 0; q < R; q++) {
+          if (q >= nr) break;
+          const int64_t wi = (r0 + q) * A.din + k;
+          E av[N], am[N], wm[N], dv = F::zero();
+#pragma unroll
+          for (int i = 0; i < N; i++) {
+            const E wv = F::load(A.W.val + i * A.W.ps, 0, wi);
+            wm[i] = F::load(A.W.mac + i * A.W.ps, 0, wi);
+            av[i] = F::load(A.A.val + i * A.A.ps, 0, wi);
+            am[i] = F::load(A.A.mac + i * A.A.ps, 0, wi);
+            dv = F::add(dv, F::sub(wv, av[i]));
+          }
+          if (A.D_pub) F::store(A.D_pub, 0, wi, dv);
+          const E rj = uniform_elem<F>(A.coef_state, (u64)(jrow0 + q * A.din + k));
+          F::wmac(wmc[0], rj, dv);
+          F::wmac(w[q][0], dv, ev);
+#pragma unroll
+          for (int i = 0; i < N; i++) {
+            F::wmac(wmc[1 + i], rj, F::sub(wm[i], am[i]));
+            F::wmac(w[q][1 + i], dv, bv[i]);
+            F::wmac(w[q][1 + i], av[i], ev);
+            F::wmac(w[q][1 + N + i], dv, bm[i]);
+            F::wmac(w[q][1 + N + i], am[i], ev);
+          }
         }
       }
 #pragma unroll
-      for (int j = 0; j < K; j++) sum[j] = F::add(sum[j], F::wreduce(w[j]));
+      for (int q = 0; q < R; q++)
+#pragma unroll
+        for (int j = 0; j < K; j++) sum[q][j] = F::add(sum[q][j], F::wreduce(w[q][j]));
 #pragma unroll
       for (int i = 0; i <= N; i++) mc[i] = F::add(mc[i], F::wreduce(wmc[i]));
     }
 #pragma unroll
-    for (int j = 0; j < K; j++) sum[j] = wave_sum<F>(sum[j]);
+    for (int q = 0; q < R; q++)
+#pragma unroll
+      for (int j = 0; j < K; j++) sum[q][j] = wave_sum<F>(sum[q][j]);
     if (lane == 0) {
 #pragma unroll
-      for (int j = 0; j < K; j++) part[wave][j] = sum[j];
+      for (int q = 0; q < R; q++)
+#pragma unroll
+        for (int j = 0; j < K; j++) part[wave][q][j] = sum[q][j];
     }
     __syncthreads();
-    if (threadIdx.x < N) {  // thread i writes party i's y value and MAC share
-      const int i = threadIdx.x;
+    if (threadIdx.x < R * N && (int)(threadIdx.x / N) < nr) {  // thread q N + i: party i of row r0 + q
+      const int q = threadIdx.x / N, i = threadIdx.x - q * N;
+      const int64_t r = r0 + q;
       E de = F::zero(), zv = F::zero(), zm = F::zero();
 #pragma unroll
       for (int w = 0; w < WAVES; w++) {
-        de = F::add(de, part[w][0]);
-        zv = F::add(zv, part[w][1 + i]);
-        zm = F::add(zm, part[w][1 + N + i]);
+        de = F::add(de, part[w][q][0]);
+        zv = F::add(zv, part[w][q][1 + i]);
+        zm = F::add(zm, part[w][q][1 + N + i]);
       }
       E v = F::add(F::add(F::load_cached(A.C.val + i * A.C.ps, 0, r), zv), F::load_cached(A.b.val + i * A.b.ps, 0, r));
       if (i == 0) v = F::add(v, de);
       E al = F::zero();
 #pragma unroll
-      for (int q = 0; q < N; q++)  // constant indices into the argument block
-        if (q == i) al = A.alpha[q];
+      for (int p = 0; p < N; p++)  // constant indices into the argument block
+        if (p == i) al = A.alpha[p];
       const E m = F::add(F::add(F::load_cached(A.C.mac + i * A.C.ps, 0, r), zm),
                          F::add(F::mul(al, de), F::load_cached(A.b.mac + i * A.b.ps, 0, r)));
       F::store(A.y.val + i * A.y.ps, 0, r, v);
       F::store(A.y.mac + i * A.y.ps, 0, r, m);
     }
-    __syncthreads();  // part is reused by the next row
+    __syncthreads();  // part is reused by the next group
   }
   block_add_to_slot<F, N + 1>(mc, A.acc + (size_t)blockIdx.x * (N + 1) * F::L);
 }
@@ -237,11 +270,17 @@ spdz_status launch_linear_layer(spdz_ctx *c, int64_t dout, int64_t din, int64_t 
     }
     SPDZ_RET(hip_status(hipGetLastError()));
     if (g > c->slots) c->slots = g;
-    // one block per row
-    g = grid_for(c, (const void *)k_ll_rows<F, N>, dout, BLOCK, 1);
+    // one block per group of one or two rows of a tile
+    const int rpb = ll_rows_per_block(dout, tile_rows);
+    const int64_t groups = n_tiles * ((tile_rows + rpb - 1) / rpb);
+    const void *krow = rpb == 2 ? (const void *)k_ll_rows<F, N, 2> : (const void *)k_ll_rows<F, N, 1>;
+    g = grid_for(c, krow, groups, BLOCK, 1);
     {
       KTimer tm(c, "layer_rows");
-      hipLaunchKernelGGL((k_ll_rows<F, N>), dim3(g), dim3(BLOCK), 0, c->stream, A);
+      if (rpb == 2)
+        hipLaunchKernelGGL((k_ll_rows<F, N, 2>), dim3(g), dim3(BLOCK), 0, c->stream, A);
+      else
+        hipLaunchKernelGGL((k_ll_rows<F, N, 1>), dim3(g), dim3(BLOCK), 0, c->stream, A);
     }
     SPDZ_RET(hip_status(hipGetLastError()));
     if (g > c->slots) c->slots = g;
