@@ -103,6 +103,12 @@ __global__ __launch_bounds__(BLOCK) void k_beaver(const BeaverArgs<F, N> A) {
     };
     // phase A: value shares (and c) -> opened d, e; z and w values.  Every input word is loaded once.
     E d = R::zero(), ee = R::zero(), de, wsum = R::zero();
+    // single-limb fields request every input word of the element up front (outputs never alias
+    // inputs), so one memory round trip serves both phases; two-limb values stay phased to keep
+    // their registers low
+    constexpr bool EARLY = F::L == 1;
+    constexpr int NE = EARLY ? N : 1;
+    E cvE[NE], xmE[NE], ymE[NE], amE[NE], bmE[NE], cmE[NE];
     {
       E xv[N], yv[N], av[N], bv[N];
 #pragma unroll
@@ -111,6 +117,17 @@ __global__ __launch_bounds__(BLOCK) void k_beaver(const BeaverArgs<F, N> A) {
         av[i] = ld(A.a, A.a.val, i);
         yv[i] = ld(A.y, A.y.val, i);
         bv[i] = ld(A.b, A.b.val, i);
+      }
+      if constexpr (EARLY) {
+#pragma unroll
+        for (int i = 0; i < N; i++) {
+          cvE[i] = ld(A.c, A.c.val, i);
+          xmE[i] = ld(A.x, A.x.mac, i);
+          ymE[i] = ld(A.y, A.y.mac, i);
+          amE[i] = ld(A.a, A.a.mac, i);
+          bmE[i] = ld(A.b, A.b.mac, i);
+          cmE[i] = ld(A.c, A.c.mac, i);
+        }
       }
 #pragma unroll
       for (int i = 0; i < N; i++) {
@@ -123,7 +140,8 @@ __global__ __launch_bounds__(BLOCK) void k_beaver(const BeaverArgs<F, N> A) {
       static_for<0, N>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         Wd t = R::wzero();
-        R::wadd(t, ld(A.c, A.c.val, i));
+        if constexpr (EARLY) R::wadd(t, cvE[i]);
+        else R::wadd(t, ld(A.c, A.c.val, i));
         R::wmac(t, d, bv[i]);
         R::wmac(t, ee, av[i]);
         if (i == 0) R::wadd(t, de);
@@ -163,12 +181,12 @@ __global__ __launch_bounds__(BLOCK) void k_beaver(const BeaverArgs<F, N> A) {
     // phase B: per party, MAC shares; recombined MAC, MAC of w, MAC-check terms
     static_for<0, N>([&](auto ic) {
       constexpr int i = decltype(ic)::value;
-      const E xm = ld(A.x, A.x.mac, i);
-      const E ym = ld(A.y, A.y.mac, i);
-      const E am = ld(A.a, A.a.mac, i);
-      const E bm = ld(A.b, A.b.mac, i);
+      const E xm = EARLY ? xmE[i % NE] : ld(A.x, A.x.mac, i);
+      const E ym = EARLY ? ymE[i % NE] : ld(A.y, A.y.mac, i);
+      const E am = EARLY ? amE[i % NE] : ld(A.a, A.a.mac, i);
+      const E bm = EARLY ? bmE[i % NE] : ld(A.b, A.b.mac, i);
       Wd t = R::wzero();
-      R::wadd(t, ld(A.c, A.c.mac, i));
+      R::wadd(t, EARLY ? cmE[i % NE] : ld(A.c, A.c.mac, i));
       R::wmac(t, d, bm);
       R::wmac(t, ee, am);
       R::wmac(t, AR::in(A.alpha[i]), de);
@@ -259,8 +277,10 @@ spdz_status launch_beaver_field(spdz_ctx *c, const spdz_shares *x, const spdz_sh
     A.ls8 = o32 ? (u32)(x->limb_stride * 8) : 0;
     A.w8 = o32 ? (u32)(A.W * 8) : 0;
     int g;
+    // two resident blocks per CU: a more compact window of each stream in flight measured 4-6 %
+    // faster than filling the occupancy (2^61-1, 2^32-5 at 2 and 3 parties; 2^127-1 has room for 2)
     auto go = [&](auto kern, const char *name, int threads, int elems) {
-      g = grid_for(c, (const void *)kern, A.W, threads, elems);
+      g = grid_for(c, (const void *)kern, A.W, threads, elems, 2);
       KTimer tm(c, name);
       hipLaunchKernelGGL(kern, dim3(g), dim3(threads), 0, c->stream, A);
     };

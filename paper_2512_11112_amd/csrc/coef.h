@@ -104,7 +104,8 @@ void alpha_of(const spdz_ctx *c, typename F::E (&out)[N]) {
 
 // persistent grid for a kernel over W elements (resident capacity of the GPU, at most MAX_SLOTS
 // blocks); block_elems elements per block and iteration, block_threads threads per block
-int grid_for(const spdz_ctx *c, const void *kernel, int64_t W, int block_threads = BLOCK, int block_elems = BLOCK);
+int grid_for(const spdz_ctx *c, const void *kernel, int64_t W, int block_threads = BLOCK, int block_elems = BLOCK,
+             int max_per_cu = 0);
 int occupancy_blocks(const void *kernel, int block_threads = BLOCK);
 
 }  // namespace spdz

@@ -323,8 +323,10 @@ int occupancy_blocks(const void *kernel, int block_threads) {
   return nb;
 }
 
-int grid_for(const spdz_ctx *c, const void *kernel, int64_t W, int block_threads, int block_elems) {
-  int64_t per_cu = c->grid_mult > 0 ? c->grid_mult : occupancy_blocks(kernel, block_threads);
+int grid_for(const spdz_ctx *c, const void *kernel, int64_t W, int block_threads, int block_elems, int max_per_cu) {
+  int64_t per_cu = occupancy_blocks(kernel, block_threads);
+  if (max_per_cu > 0 && per_cu > max_per_cu) per_cu = max_per_cu;
+  if (c->grid_mult > 0) per_cu = c->grid_mult;
   int64_t g = (int64_t)c->num_cus * per_cu;
   int64_t need = (W + block_elems - 1) / block_elems;
   if (g > need) g = need;
