@@ -98,8 +98,17 @@ __global__ __launch_bounds__(BLOCK) void k_ll_rows(const LayerArgs<F, N> A) {
 #pragma unroll
   for (int k = 0; k <= N; k++) mc[k] = F::zero();
   const int64_t gpt = (A.tile_rows + R - 1) / R, ngroups = A.n_tiles * gpt;
+  // XCD-aware order: consecutive blocks go to the 8 XCDs in turn, and each XCD has its own L2;
+  // when the grid is a multiple of 8, the blocks of XCD x take the row groups of tiles
+  // x, x + 8, ..., so a tile's E_t and B_t are fetched into one L2 only.  Every group is
+  // still taken exactly once whichever XCD a block actually runs on.
+  constexpr int NX = 8;
+  const bool xcd = gridDim.x % NX == 0;
+  const int64_t xi = blockIdx.x % NX, bpx = gridDim.x / NX;
+  const int64_t mine = xcd ? (xi < A.n_tiles ? (A.n_tiles - xi + NX - 1) / NX : 0) * gpt : ngroups;
 
-  for (int64_t gi = blockIdx.x; gi < ngroups; gi += gridDim.x) {
+  for (int64_t li = xcd ? blockIdx.x / NX : blockIdx.x; li < mine; li += xcd ? bpx : gridDim.x) {
+    const int64_t gi = xcd ? (xi + (li / gpt) * NX) * gpt + li % gpt : li;
     const int64_t t = gi / gpt;
     const int64_t r0 = t * A.tile_rows + (gi - t * gpt) * R;
     const int64_t tend = min(A.dout, (t + 1) * A.tile_rows);
@@ -275,6 +284,7 @@ spdz_status launch_linear_layer(spdz_ctx *c, int64_t dout, int64_t din, int64_t 
     const int64_t groups = n_tiles * ((tile_rows + rpb - 1) / rpb);
     const void *krow = rpb == 2 ? (const void *)k_ll_rows<F, N, 2> : (const void *)k_ll_rows<F, N, 1>;
     g = grid_for(c, krow, groups, BLOCK, 1);
+    if (g >= 8) g -= g % 8;  // a multiple of the XCD count enables the XCD-aware group order
     {
       KTimer tm(c, "layer_rows");
       if (rpb == 2)
