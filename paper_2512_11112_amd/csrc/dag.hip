@@ -101,29 +101,42 @@ __global__ __launch_bounds__(BLOCK) void k_dag_level(const LevelArgs<N> A) {
     const int64_t e1 = min(e0 + (int64_t)A.tile, w);
     for (int64_t e = e0 + threadIdx.x; e < e1; e += BLOCK) {
       const uint32_t i1 = view_index(op.off1, e, op.w1);
+      // every op reads all of an element's input words before it writes any (an op's output
+      // node never overlaps its inputs), so each element costs one memory round trip
       if (op.kind == 2) {  // public-constant multiple
         const E c{op.konst};
+        E xv[N], xm[N];
 #pragma unroll
         for (int i = 0; i < N; i++) {
-          const E xv{A.nval[op.in1 + i * op.w1 + i1]}, xm{A.nmac[op.in1 + i * op.w1 + i1]};
-          A.nval[op.out + i * w + e] = F::canon(F::mul(c, xv)).v;
-          A.nmac[op.out + i * w + e] = F::canon(F::mul(c, xm)).v;
+          xv[i] = E{A.nval[op.in1 + i * op.w1 + i1]};
+          xm[i] = E{A.nmac[op.in1 + i * op.w1 + i1]};
+        }
+#pragma unroll
+        for (int i = 0; i < N; i++) {
+          A.nval[op.out + i * w + e] = F::canon(F::mul(c, xv[i])).v;
+          A.nmac[op.out + i * w + e] = F::canon(F::mul(c, xm[i])).v;
         }
         continue;
       }
       const uint32_t i2 = view_index(op.off2, e, op.w2);
       if (op.kind == 1) {  // addition
+        E xv[N], yv[N], xm[N], ym[N];
 #pragma unroll
         for (int i = 0; i < N; i++) {
-          const E xv{A.nval[op.in1 + i * op.w1 + i1]}, yv{A.nval[op.in2 + i * op.w2 + i2]};
-          const E xm{A.nmac[op.in1 + i * op.w1 + i1]}, ym{A.nmac[op.in2 + i * op.w2 + i2]};
-          A.nval[op.out + i * w + e] = F::canon(F::add(xv, yv)).v;
-          A.nmac[op.out + i * w + e] = F::canon(F::add(xm, ym)).v;
+          xv[i] = E{A.nval[op.in1 + i * op.w1 + i1]};
+          yv[i] = E{A.nval[op.in2 + i * op.w2 + i2]};
+          xm[i] = E{A.nmac[op.in1 + i * op.w1 + i1]};
+          ym[i] = E{A.nmac[op.in2 + i * op.w2 + i2]};
+        }
+#pragma unroll
+        for (int i = 0; i < N; i++) {
+          A.nval[op.out + i * w + e] = F::canon(F::add(xv[i], yv[i])).v;
+          A.nmac[op.out + i * w + e] = F::canon(F::add(xm[i], ym[i])).v;
         }
         continue;
       }
       // Beaver product with the op's triple
-      E xv[N], yv[N], av[N], bv[N];
+      E xv[N], yv[N], av[N], bv[N], xmv[N], ymv[N], amv[N], bmv[N], cvv[N], cmv[N];
       E d = F::zero(), ee = F::zero();
 #pragma unroll
       for (int i = 0; i < N; i++) {
@@ -131,6 +144,18 @@ __global__ __launch_bounds__(BLOCK) void k_dag_level(const LevelArgs<N> A) {
         yv[i] = E{A.nval[op.in2 + i * op.w2 + i2]};
         av[i] = E{A.tval[op.tri + i * w + e]};
         bv[i] = E{A.tval[op.tri + (N + i) * w + e]};
+      }
+#pragma unroll
+      for (int i = 0; i < N; i++) {
+        xmv[i] = E{A.nmac[op.in1 + i * op.w1 + i1]};
+        ymv[i] = E{A.nmac[op.in2 + i * op.w2 + i2]};
+        amv[i] = E{A.tmac[op.tri + i * w + e]};
+        bmv[i] = E{A.tmac[op.tri + (N + i) * w + e]};
+        cvv[i] = E{A.tval[op.tri + (2 * N + i) * w + e]};
+        cmv[i] = E{A.tmac[op.tri + (2 * N + i) * w + e]};
+      }
+#pragma unroll
+      for (int i = 0; i < N; i++) {
         d = F::add(d, F::sub(xv[i], av[i]));
         ee = F::add(ee, F::sub(yv[i], bv[i]));
       }
@@ -139,9 +164,7 @@ __global__ __launch_bounds__(BLOCK) void k_dag_level(const LevelArgs<N> A) {
       const E re = uniform_elem<F>(cstate, (u64)(jb + op.jlog + w + e));
 #pragma unroll
       for (int i = 0; i < N; i++) {
-        const E xm{A.nmac[op.in1 + i * op.w1 + i1]}, ym{A.nmac[op.in2 + i * op.w2 + i2]};
-        const E am{A.tmac[op.tri + i * w + e]}, bm{A.tmac[op.tri + (N + i) * w + e]};
-        const E cv{A.tval[op.tri + (2 * N + i) * w + e]}, cm{A.tmac[op.tri + (2 * N + i) * w + e]};
+        const E xm = xmv[i], ym = ymv[i], am = amv[i], bm = bmv[i], cv = cvv[i], cm = cmv[i];
         F::Wide t = F::wzero();
         F::wadd(t, cv);
         F::wmac(t, d, bv[i]);
