@@ -129,6 +129,15 @@ __global__ __launch_bounds__(BLOCK) void k_pubop(const PubArgs<F, N> A) {
   using E = typename F::E;
   for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < A.W; e += (int64_t)gridDim.x * BLOCK) {
     const E v = F::load_cached(A.v, A.vstride ? A.W : 1, e * A.vstride);  // limb stride W, or 1 for a scalar
+    // every party's words of the element are read before any is written (out may be x)
+    E xvs[N], xms[N];
+    if (A.mode != SPDZ_PUB_SHARE) {
+#pragma unroll
+      for (int i = 0; i < N; i++) {
+        xvs[i] = F::load_cached(A.x.val + i * A.x.ps, A.x.ls, e);
+        xms[i] = F::load_cached(A.x.mac + i * A.x.ps, A.x.ls, e);
+      }
+    }
 #pragma unroll
     for (int i = 0; i < N; i++) {
       E ov, om;
@@ -136,8 +145,7 @@ __global__ __launch_bounds__(BLOCK) void k_pubop(const PubArgs<F, N> A) {
         ov = i == 0 ? v : F::zero();
         om = F::mul(A.alpha[i], v);
       } else {
-        const E xv = F::load_cached(A.x.val + i * A.x.ps, A.x.ls, e);
-        const E xm = F::load_cached(A.x.mac + i * A.x.ps, A.x.ls, e);
+        const E xv = xvs[i], xm = xms[i];
         if (A.mode == SPDZ_PUB_MUL) {
           ov = F::mul(xv, v);
           om = F::mul(xm, v);
