@@ -279,6 +279,16 @@ def test_zero_width_and_shape_errors():
     with pytest.raises(SpdzError) as ei:
         ctx.spdz_mul_batch(xd, yd, triple_to_dev(D.t), xd)   # z aliases x
     assert ei.value.status == -1
+    td = triple_to_dev(D.t)
+    with pytest.raises(SpdzError) as ei:
+        ctx.spdz_mul_batch(xd, yd, td, td.c)                 # z aliases the triple
+    assert ei.value.status == -1
+    z, w = ShareTensor.empty(2, 1, 10), ShareTensor.empty(2, 1, 10)
+    for bad_w in (xd, yd, z):                                # w aliases x, y or z
+        with pytest.raises(SpdzError) as ei:
+            ctx.spdz_mul_fused(xd, yd, td, z, None, None, lin=(1, 3, P61 - 1, 0), w=bad_w)
+        assert ei.value.status == -1
+    assert ctx.opened_count() == 0
     ok, _ = ctx.spdz_mac_check()   # empty log accepts
     assert ok
 

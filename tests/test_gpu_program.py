@@ -101,6 +101,24 @@ def test_public_op_modes(p, n):
     assert np.array_equal(host(out.val), want.val) and np.array_equal(host(out.mac), want.mac)
 
 
+@pytest.mark.parametrize("p,n", [(P_PAPER, 3), (P127, 2)])
+def test_public_op_in_place(p, n):
+    """out may be x: x + v and x * v written over x give the same shares as into a fresh buffer."""
+    from paper_2512_11112_amd.spdz import SPDZ_PUB_ADD, SPDZ_PUB_MUL, ShareTensor, public_op
+    W = 3001
+    text = f"input 1 private {W} 0\ninput 2 public {W} 1\nblock 0\nret\n"
+    ex = Exec(parse(text, p), p, n, 9, 9)
+    ex.run()
+    x, v = ex.val[1], ex.val[2]
+    ctx = ctx_for(p, n, 9, 9)
+    vd = dev(v)
+    for mode, want in [(SPDZ_PUB_ADD, ex.add_pub(x, v)), (SPDZ_PUB_MUL, ex.mul_pub(x, v))]:
+        xd = share_to_dev(x)
+        out = public_op(ctx, mode, xd, vd, xd)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(out.val), want.val) and np.array_equal(host(out.mac), want.mac)
+
+
 def test_program_errors():
     from paper_2512_11112_amd.spdz import Program, ProgramError, SpdzError
     ctx = ctx_for(P_PAPER, 2, 1, 1)
