@@ -420,7 +420,8 @@ spdz_status spdz_prog_output(spdz_prog *prog, int node, spdz_shares *out_shares,
 spdz_status spdz_prog_node_info(spdz_prog *prog, int node, int *secret, int64_t *width);
 
 /* Counters of the last run: block entries, kernel launches (approximate:
- * product = dealer + product, layer = 6), host synchronisations, opened values. */
+ * a fused run counts 1, a product dealt during the run 2, a layer 6; 2-D copies
+ * of phi and load are not counted), host synchronisations, opened values. */
 spdz_status spdz_prog_stats(spdz_prog *prog, int64_t *block_entries, int64_t *launches, int64_t *host_syncs,
                             int64_t *opened);
 
