@@ -325,6 +325,9 @@ def suite_matmul(args):
     # the int8 MFMA rate this GPU holds with operands in registers (random vs structured
     # bytes): the power-limited ceiling of the GEMM, measured by a child process
     calib = os.path.join(ROOT, "paper_2512_11112_amd", "calib", "mfma_rate")
+    if not os.path.exists(calib):
+        from paper_2512_11112_amd.build import build_calib
+        build_calib()
     rate = None
     if os.path.exists(calib):
         r = subprocess.run([calib, "4096", "400"], capture_output=True, text=True, timeout=300)

@@ -14,8 +14,9 @@
  *   key alpha = sum_i alpha_i is itself additively shared.
  *
  *   Residues are canonical (in [0, p)) and stored as L little-endian 64-bit
- *   limbs: L = 1 for p = 2^61 - 1, L = 2 for p = 2^127 - 1.  These are the
- *   two supported moduli; any other returns SPDZ_E_MODULUS.
+ *   limbs: L = 1 for p = 2^61 - 1 and for p = 2^32 - 5 (the paper's field,
+ *   Sec. IV-A; residues zero-extended to 64 bits), L = 2 for p = 2^127 - 1.
+ *   These are the three supported moduli; any other returns SPDZ_E_MODULUS.
  *
  *   spdz_shares describes values and MAC shares of a batch of `len`
  *   elements (the paper's batched value/MAC buffers, Sec. III, Fig. 1, and
@@ -34,8 +35,14 @@
  *   - Negative status: the call did nothing.  SPDZ_MAC_REJECT: the protocol
  *     aborted (Sec. II-A, "Security model"); every later call except
  *     spdz_ctx_destroy returns SPDZ_E_ABORTED.
- *   - Inputs must be canonical residues; the library does not re-check them
- *     (a non-canonical input gives unspecified, but in-bounds, results).
+ *   - Inputs must be canonical residues.  By default the library does not
+ *     re-check them (a non-canonical input gives unspecified, but in-bounds,
+ *     results).  With validation on (spdz_ctx_set_validation, or the
+ *     environment variable SPDZ_VALIDATE=1 when the context is created), every
+ *     call of the online phase first checks each share array and public vector
+ *     it reads, on the device, and returns SPDZ_E_INVAL, with nothing else
+ *     enqueued and the log unchanged, if a word is not a canonical residue;
+ *     the check synchronises the stream (a debugging aid, not a fast path).
  *   - The opened-value log: spdz_open, spdz_mul_batch, spdz_mul_fused and
  *     spdz_matmul_triple append every value they open to the context's log
  *     (in the order documented per call); spdz_mac_check checks the whole log
@@ -61,7 +68,7 @@ typedef enum {
   SPDZ_OK = 0,
   SPDZ_MAC_REJECT = 1,   /* MAC check failed: protocol aborted */
   SPDZ_E_INVAL = -1,     /* bad argument (null pointer, bad count, aliasing) */
-  SPDZ_E_MODULUS = -2,   /* modulus other than 2^61-1 / 2^127-1, or limb count mismatch */
+  SPDZ_E_MODULUS = -2,   /* modulus other than 2^61-1 / 2^127-1 / 2^32-5, or limb count mismatch */
   SPDZ_E_SHAPE = -3,     /* operand lengths or matrix sizes do not match */
   SPDZ_E_NOMEM = -4,     /* device allocation failed */
   SPDZ_E_HIP = -5,       /* a HIP runtime call failed */
@@ -103,6 +110,12 @@ spdz_status spdz_ctx_destroy(spdz_ctx *ctx);
 /* Number of values opened since the last MAC check (the log length). */
 int64_t spdz_opened_count(const spdz_ctx *ctx);
 
+/* Turn input validation on (1) or off (0) for this context (see "Inputs must
+ * be canonical residues" above).  Validated calls: spdz_open, spdz_mul_batch,
+ * spdz_mul_fused, spdz_linear, spdz_public_op, spdz_reduce_add,
+ * spdz_matmul_triple, spdz_linear_layer. */
+spdz_status spdz_ctx_set_validation(spdz_ctx *ctx, int enable);
+
 /* ---------------------------------------------------------------------- */
 /* Online phase                                                             */
 /* ---------------------------------------------------------------------- */
@@ -138,9 +151,12 @@ spdz_status spdz_linear(spdz_ctx *ctx, int n_terms, const spdz_shares *terms,
  *   SPDZ_PUB_MUL   out = x * v   element by element (values and MAC shares times v)
  *   SPDZ_PUB_SHARE out = v as a shared value (party 0 holds v, MAC_i = alpha_i v);
  *                  x must be NULL.
+ *   SPDZ_PUB_SUB   out = x - v   (party 0: x_0 - v; MAC_i - alpha_i v)
  * v: DEVICE [L][vwidth] canonical residues, vwidth = out->len or 1 (a scalar
- * applied to every element).  out may alias x.  Opens nothing. */
-enum { SPDZ_PUB_ADD = 0, SPDZ_PUB_MUL = 1, SPDZ_PUB_SHARE = 2 };
+ * applied to every element), read by the kernel on the context stream (so v may
+ * be the output of an earlier call on that stream).  out may alias x.  Opens
+ * nothing. */
+enum { SPDZ_PUB_ADD = 0, SPDZ_PUB_MUL = 1, SPDZ_PUB_SHARE = 2, SPDZ_PUB_SUB = 3 };
 spdz_status spdz_public_op(spdz_ctx *ctx, int mode, const spdz_shares *x, const uint64_t *v, int64_t vwidth,
                            spdz_shares *out);
 

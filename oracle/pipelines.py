@@ -177,13 +177,18 @@ def matrix_triple_entries(D: DealtMat, E: np.ndarray, Fo: np.ndarray, rows, cols
 # ---------------------------------------------------------------------------
 # layered DAG (single-limb field): ops one at a time in op-id order
 # ---------------------------------------------------------------------------
-def dag_run(dag, seed: int, check_seed: int, epoch: int = 0, keep=None):
+def dag_run(dag, seed: int, check_seed: int, epoch: int = 0, keep=None, on_node=None, more_epochs=()):
     """Executes every op of `dag` (workloads.dag.Dag) on oracle-dealt inputs and triples.
 
     Inputs are arrays ARR_DAG_IN0 + i, the triple of Beaver op k is dealt with
     array id ARR_DAG_TRIPLE0 + 3 k.  Element j of an operand view reads
     src[(off + j) mod width(src)].  Returns (outputs {node: Shares} for the
-    nodes in `keep` (all if None), ok, sigma).
+    nodes in `keep` (all if None), ok, sigma).  on_node(node, shares), if
+    given, is called for the two inputs and then for every op's output as it is
+    produced (so a caller can compare every node without keeping them all).
+    more_epochs: further MAC-check numbers whose verdict and sigma over the same
+    opened values are wanted; then a fourth result {epoch: (ok, sigma)} is
+    returned.
     """
     from workloads import ARR_DAG_IN0
     from workloads.dag import OP_ADD, OP_MUL, triple_array_id
@@ -193,7 +198,9 @@ def dag_run(dag, seed: int, check_seed: int, epoch: int = 0, keep=None):
     nodes = {}
     for i in range(2):
         _, nodes[i] = f.deal_uniform_secret(n, seed, ARR_DAG_IN0 + i, dag.in_width, al)
-    log = F.MacLog(f, n, check_seed, epoch)
+        if on_node is not None:
+            on_node(i, nodes[i])
+    logs = [F.MacLog(f, n, check_seed, ep) for ep in (epoch, *more_epochs)]
     # last use of every node, to free memory early
     last = {}
     for k in range(dag.n_ops):
@@ -215,8 +222,9 @@ def dag_run(dag, seed: int, check_seed: int, epoch: int = 0, keep=None):
             y = view(int(dag.src2[k]), int(dag.off2[k]), w)
             t = f.deal_triple(n, seed, triple_array_id(k), w, al)
             z, d, e, dm, em = f.beaver(al, x, y, t)
-            log.add(d, dm)
-            log.add(e, em)
+            for log in logs:
+                log.add(d, dm)
+                log.add(e, em)
         elif kind == OP_ADD:
             y = view(int(dag.src2[k]), int(dag.off2[k]), w)
             z = f.linear(al, [x, y], [1, 1])
@@ -224,6 +232,8 @@ def dag_run(dag, seed: int, check_seed: int, epoch: int = 0, keep=None):
             z = f.linear(al, [x], [int(dag.const[k])])
         node = 2 + k
         nodes[node] = z
+        if on_node is not None:
+            on_node(node, z)
         if keep is None or node in keep:
             out[node] = z
         for src in (int(dag.src1[k]), int(dag.src2[k])):
@@ -232,8 +242,10 @@ def dag_run(dag, seed: int, check_seed: int, epoch: int = 0, keep=None):
     for i in range(2):
         if keep is None or i in keep:
             out[i] = nodes[i]
-    ok, sigma = log.check(al)
-    return out, ok, sigma
+    ok, sigma = logs[0].check(al)
+    if not more_epochs:
+        return out, ok, sigma
+    return out, ok, sigma, {ep: lg.check(al) for ep, lg in zip(more_epochs, logs[1:])}
 
 
 # ---------------------------------------------------------------------------

@@ -5,7 +5,9 @@
 Every .hip file under csrc/ is compiled to an object in _build/ (in
 parallel), then linked into paper_2512_11112_amd/libspdz.so.  The calibration
 program calib/mfma_rate.hip (the int8 MFMA rate this GPU sustains, reported
-beside the GEMM's measurements) is built next to its source.
+beside the GEMM's measurements) is a measurement probe, not part of the
+library: build_calib() compiles it next to its source, and a failure there
+never fails the library build.
 """
 from __future__ import annotations
 
@@ -53,14 +55,22 @@ def build(verbose: bool = True) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(tmp, OUT)
-    calib = os.path.join(PKG, "calib", "mfma_rate")
-    r = subprocess.run([HIPCC, *CFLAGS, os.path.join(PKG, "calib", "mfma_rate.hip"), "-o", calib],
-                       capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed for calib/mfma_rate.hip:\n{r.stderr}")
     if verbose:
         print(f"built {OUT} from {len(srcs)} sources", file=sys.stderr)
+    calib = build_calib()
+    if calib is None and verbose:
+        print("calib/mfma_rate not built (measurement probe only)", file=sys.stderr)
     return OUT
+
+
+CALIB = os.path.join(PKG, "calib", "mfma_rate")
+
+
+def build_calib():
+    """Compile the MFMA-rate probe; its path, or None if hipcc failed."""
+    r = subprocess.run([HIPCC, *CFLAGS, os.path.join(PKG, "calib", "mfma_rate.hip"), "-o", CALIB],
+                       capture_output=True, text=True)
+    return CALIB if r.returncode == 0 else None
 
 
 if __name__ == "__main__":

@@ -3,7 +3,9 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <initializer_list>
 #include <new>
+#include <utility>
 
 #include "ctx.h"
 
@@ -29,13 +31,17 @@ bool canonical(const u64 *v, int fid) {
 }
 
 // every element of a descriptor must stay inside the caller's buffers; only
-// the descriptor itself can be checked here
+// the descriptor itself can be checked here: the L limb planes of a party must
+// not overlap (limb_stride >= len) and the parties' planes must not overlap
+// (party_stride >= (L - 1) limb_stride + len)
 spdz_status check_sv(const spdz_ctx *c, const spdz_shares *s, int64_t len) {
   if (!s) return SPDZ_E_INVAL;
   if (s->len != len || len < 0) return SPDZ_E_SHAPE;
   if (len == 0) return SPDZ_OK;
   if (!s->val || !s->mac) return SPDZ_E_INVAL;
-  if (s->limb_stride < (c->L > 1 ? s->len : 0) || s->party_stride < c->L * s->len) return SPDZ_E_SHAPE;
+  if (c->L > 1 && s->limb_stride < s->len) return SPDZ_E_SHAPE;
+  const int64_t party_extent = (c->L > 1 ? (int64_t)(c->L - 1) * s->limb_stride : 0) + s->len;
+  if (s->party_stride < party_extent) return SPDZ_E_SHAPE;
   return SPDZ_OK;
 }
 
@@ -67,6 +73,20 @@ bool overlaps(const spdz_ctx *c, const spdz_shares *a, const spdz_shares *b) {
     if (!(c)) return SPDZ_E_INVAL;                \
     if ((c)->aborted) return SPDZ_E_ABORTED;      \
   } while (0)
+
+// With validation on (spdz_ctx_set_validation): every share array and public vector a call
+// reads is checked on the device for non-canonical words before anything else is enqueued;
+// SPDZ_E_INVAL if one is found.  Null entries are skipped.
+spdz_status validate_inputs(spdz_ctx *c, std::initializer_list<const spdz_shares *> shares,
+                            std::initializer_list<std::pair<const u64 *, int64_t>> pubs = {}) {
+  if (!c->validate) return SPDZ_OK;
+  SPDZ_CHECK(launch_validate_clear(c));
+  for (const spdz_shares *s : shares)
+    if (s) SPDZ_CHECK(launch_validate_shares(c, s));
+  for (auto &pv : pubs)
+    if (pv.first) SPDZ_CHECK(launch_validate_public(c, pv.first, pv.second));
+  return validate_result(c);
+}
 
 }  // namespace
 
@@ -110,6 +130,7 @@ spdz_status spdz_ctx_create(spdz_ctx **out, int n_parties, const uint64_t *p_lim
   c->check_seed = check_seed;
   c->stream = (hipStream_t)hip_stream;
   if (const char *g = getenv("SPDZ_GRID_PER_CU")) c->grid_mult = atoi(g);
+  if (const char *v = getenv("SPDZ_VALIDATE")) c->validate = atoi(v) != 0;
   hipDeviceProp_t prop;
   if (hipGetDevice(&c->device) != hipSuccess || hipGetDeviceProperties(&prop, c->device) != hipSuccess) {
     delete c;
@@ -121,7 +142,9 @@ spdz_status spdz_ctx_create(spdz_ctx **out, int n_parties, const uint64_t *p_lim
   if (hipMalloc((void **)&c->d_acc, acc_words * 8) != hipSuccess ||
       hipMalloc((void **)&c->d_red, red_words * 8) != hipSuccess ||
       hipMalloc((void **)&c->d_sigma, (size_t)(n_parties + 1) * n_limbs * 8) != hipSuccess ||
-      hipHostMalloc((void **)&c->h_sigma, (size_t)(n_parties + 1) * n_limbs * 8, hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc((void **)&c->h_sigma, (size_t)(n_parties + 1) * n_limbs * 8, hipHostMallocDefault) != hipSuccess ||
+      hipMalloc((void **)&c->d_bad, 256) != hipSuccess ||
+      hipHostMalloc((void **)&c->h_bad, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
     spdz_ctx_destroy(c);
     return SPDZ_E_NOMEM;
   }
@@ -147,17 +170,26 @@ spdz_status spdz_ctx_destroy(spdz_ctx *c) {
   if (c->d_sigma) hipFree(c->d_sigma);
   if (c->ws) hipFree(c->ws);
   if (c->h_sigma) hipHostFree(c->h_sigma);
+  if (c->d_bad) hipFree(c->d_bad);
+  if (c->h_bad) hipHostFree(c->h_bad);
   delete c;
   return SPDZ_OK;
 }
 
 int64_t spdz_opened_count(const spdz_ctx *c) { return c ? c->log_count : -1; }
 
+spdz_status spdz_ctx_set_validation(spdz_ctx *c, int enable) {
+  if (!c) return SPDZ_E_INVAL;
+  c->validate = enable != 0;
+  return SPDZ_OK;
+}
+
 spdz_status spdz_open(spdz_ctx *c, const spdz_shares *x, uint64_t *out_pub) {
   SPDZ_LIVE(c);
   if (!x || !out_pub) return SPDZ_E_INVAL;
   SPDZ_CHECK(check_sv(c, x, x->len));
   if (x->len == 0) return SPDZ_OK;
+  SPDZ_CHECK(validate_inputs(c, {x}));
   return launch_open(c, x, out_pub);
 }
 
@@ -183,6 +215,7 @@ spdz_status spdz_mul_batch(spdz_ctx *c, const spdz_shares *x, const spdz_shares 
   SPDZ_LIVE(c);
   SPDZ_CHECK(check_mul_operands(c, x, y, t, z));
   if (x->len == 0) return SPDZ_OK;
+  SPDZ_CHECK(validate_inputs(c, {x, y, &t->a, &t->b, &t->c}));
   return launch_beaver(c, x, y, t, z, d_pub, e_pub, nullptr, nullptr, nullptr, nullptr);
 }
 
@@ -202,6 +235,7 @@ spdz_status spdz_mul_fused(spdz_ctx *c, const spdz_shares *x, const spdz_shares 
   }
   if (s) SPDZ_CHECK(check_sv(c, s, 1));
   if (x->len == 0) return SPDZ_OK;
+  SPDZ_CHECK(validate_inputs(c, {x, y, &t->a, &t->b, &t->c}));
   return launch_beaver(c, x, y, t, z, d_pub, e_pub, lin, w, w_pub, s);
 }
 
@@ -215,18 +249,24 @@ spdz_status spdz_linear(spdz_ctx *c, int n_terms, const spdz_shares *terms, cons
   for (int k = 0; k < n_terms; k++) SPDZ_CHECK(check_sv(c, &terms[k], out->len));
   SPDZ_CHECK(check_sv(c, out, out->len));
   if (out->len == 0) return SPDZ_OK;
+  if (c->validate) {
+    SPDZ_CHECK(launch_validate_clear(c));
+    for (int k = 0; k < n_terms; k++) SPDZ_CHECK(launch_validate_shares(c, &terms[k]));
+    SPDZ_CHECK(validate_result(c));
+  }
   return launch_linear(c, n_terms, terms, coeffs, c0, out);
 }
 
 spdz_status spdz_public_op(spdz_ctx *c, int mode, const spdz_shares *x, const uint64_t *v, int64_t vwidth,
                            spdz_shares *out) {
   SPDZ_LIVE(c);
-  if (!out || !v || mode < SPDZ_PUB_ADD || mode > SPDZ_PUB_SHARE) return SPDZ_E_INVAL;
+  if (!out || !v || mode < SPDZ_PUB_ADD || mode > SPDZ_PUB_SUB) return SPDZ_E_INVAL;
   if ((mode == SPDZ_PUB_SHARE) != (x == nullptr)) return SPDZ_E_INVAL;
   SPDZ_CHECK(check_sv(c, out, out->len));
   if (x) SPDZ_CHECK(check_sv(c, x, out->len));
   if (vwidth != 1 && vwidth != out->len) return SPDZ_E_SHAPE;
   if (out->len == 0) return SPDZ_OK;
+  SPDZ_CHECK(validate_inputs(c, {x}, {{v, vwidth}}));
   return launch_pubop(c, mode, x, v, vwidth, out);
 }
 
@@ -235,6 +275,7 @@ spdz_status spdz_reduce_add(spdz_ctx *c, const spdz_shares *x, spdz_shares *out)
   if (!x || !out) return SPDZ_E_INVAL;
   SPDZ_CHECK(check_sv(c, x, x->len));
   SPDZ_CHECK(check_sv(c, out, 1));
+  SPDZ_CHECK(validate_inputs(c, {x}));
   return launch_reduce(c, x, out);
 }
 
@@ -257,6 +298,7 @@ spdz_status spdz_matmul_triple(spdz_ctx *c, int64_t M, int64_t K, int64_t N, con
   if (overlaps(c, Z, X) || overlaps(c, Z, Y) || overlaps(c, Z, &T->a) || overlaps(c, Z, &T->b) ||
       overlaps(c, Z, &T->c))
     return SPDZ_E_INVAL;
+  SPDZ_CHECK(validate_inputs(c, {X, Y, &T->a, &T->b, &T->c}));
   return launch_matmul_triple(c, M, K, N, X, Y, T, Z, E_pub, F_pub, variant);
 }
 
@@ -278,6 +320,7 @@ spdz_status spdz_linear_layer(spdz_ctx *c, int64_t dout, int64_t din, int64_t ti
   if (overlaps(c, y, W) || overlaps(c, y, x) || overlaps(c, y, b) || overlaps(c, y, &T->a) ||
       overlaps(c, y, &T->b) || overlaps(c, y, &T->c))
     return SPDZ_E_INVAL;
+  SPDZ_CHECK(validate_inputs(c, {W, x, b, &T->a, &T->b, &T->c}));
   return launch_linear_layer(c, dout, din, tile_rows, W, x, b, T, y, D_pub, E_pub);
 }
 

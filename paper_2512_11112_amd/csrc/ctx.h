@@ -56,6 +56,10 @@ struct spdz_ctx {
   // MAC-check sums contributed by ops that ran on the CPU back end ([0] = A, [1 + i] = G_i), canonical
   spdz::u64 host_acc[spdz::MAX_PARTIES + 1][2] = {};
   int grid_mult = 0;            // blocks per CU for streaming kernels (0 = from occupancy)
+  // input validation (spdz_ctx_set_validation): device flag of a non-canonical word, pinned copy
+  bool validate = false;
+  uint32_t *d_bad = nullptr;
+  uint32_t *h_bad = nullptr;
   // workspace of the matrix-triple product (digit planes, E F), grown on demand
   void *ws = nullptr;
   size_t ws_bytes = 0;
@@ -146,7 +150,7 @@ spdz_status launch_beaver(spdz_ctx *c, const spdz_shares *x, const spdz_shares *
 spdz_status launch_linear(spdz_ctx *c, int nt, const spdz_shares *terms, const u64 *coeffs, const u64 *c0,
                           spdz_shares *out);
 spdz_status launch_reduce(spdz_ctx *c, const spdz_shares *x, spdz_shares *out);
-// out = x + v, x * v or share(v) for a public v of width out->len or 1 (mode SPDZ_PUB_*)
+// out = x + v, x * v, share(v) or x - v for a public v of width out->len or 1 (mode SPDZ_PUB_*)
 // One instruction of a fused element-wise group of the program runtime (fused.hip).  Slots
 // are per-thread LDS registers holding one secret value (n value and n MAC shares); a
 // node buffer is the runtime's layout [values: n][L][W] then [MACs: n][L][W].
@@ -174,6 +178,12 @@ spdz_status launch_deal_secret(spdz_ctx *c, u64 seed, u64 array_id, const u64 *v
                                u64 *values_out);
 spdz_status launch_deal_triple(spdz_ctx *c, u64 seed, u64 array_id, spdz_triple *t);
 spdz_status launch_copy(u64 *dst, const u64 *src, int64_t words, hipStream_t stream);
+// input validation: clear the flag, check share arrays (values and MAC shares, every party and
+// limb) and public vectors [L][len] for words that are not canonical residues, then read the flag
+spdz_status launch_validate_clear(spdz_ctx *c);
+spdz_status launch_validate_shares(spdz_ctx *c, const spdz_shares *s);
+spdz_status launch_validate_public(spdz_ctx *c, const u64 *v, int64_t len);
+spdz_status validate_result(spdz_ctx *c);
 // matmul.hip
 spdz_status launch_matmul_triple(spdz_ctx *c, int64_t M, int64_t K, int64_t N, const spdz_shares *X,
                                  const spdz_shares *Y, const spdz_triple *T, spdz_shares *Z, u64 *E_pub, u64 *F_pub,

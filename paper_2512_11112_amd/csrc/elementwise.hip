@@ -111,16 +111,17 @@ __global__ __launch_bounds__(BLOCK) void k_linear(const LinArgs<F, N> A) {
 // --------------------------------------------------------------------------
 // secret and public values together (Sec. II-A, local operations with a public
 // operand): out = x + v (party 0 adds v, every party alpha_i v to its MAC
-// share), out = x * v element by element (values and MACs scaled), or
-// out = share(v) (party 0 holds v, MAC shares alpha_i v).  v is [L][W], or a
-// public scalar broadcast when vstride = 0.
+// share), out = x * v element by element (values and MACs scaled),
+// out = share(v) (party 0 holds v, MAC shares alpha_i v), or out = x - v
+// (party 0 subtracts v, every party alpha_i v from its MAC share).  v is
+// [L][W], or a public scalar broadcast when vstride = 0.
 // --------------------------------------------------------------------------
 template <class F, int N>
 struct PubArgs {
   SV x, out;
   const u64 *v;
   int64_t vstride, W;
-  int mode;  // SPDZ_PUB_ADD, SPDZ_PUB_MUL, SPDZ_PUB_SHARE
+  int mode;  // SPDZ_PUB_ADD, SPDZ_PUB_MUL, SPDZ_PUB_SHARE, SPDZ_PUB_SUB
   typename F::E alpha[N];
 };
 
@@ -149,6 +150,9 @@ __global__ __launch_bounds__(BLOCK) void k_pubop(const PubArgs<F, N> A) {
         if (A.mode == SPDZ_PUB_MUL) {
           ov = F::mul(xv, v);
           om = F::mul(xm, v);
+        } else if (A.mode == SPDZ_PUB_SUB) {
+          ov = i == 0 ? F::sub(xv, v) : xv;
+          om = F::sub(xm, F::mul(A.alpha[i], v));
         } else {
           ov = i == 0 ? F::add(xv, v) : xv;
           om = F::add(xm, F::mul(A.alpha[i], v));
@@ -306,6 +310,36 @@ __global__ __launch_bounds__(BLOCK) void k_deal_triple(const DealTripleArgs<F, N
 }
 
 // --------------------------------------------------------------------------
+// input validation: flags any word of the given planes that is not a canonical
+// residue (for two limbs, the pair as a 128-bit value)
+// --------------------------------------------------------------------------
+template <class F>
+__device__ __forceinline__ bool canonical_words(const u64 *plane, int64_t ls, int64_t e) {
+  if constexpr (F::L == 1) {
+    return plane[e] < F::P;
+  } else {
+    const u64 lo = plane[e], hi = plane[ls + e];
+    return hi < F127::PHI || (hi == F127::PHI && lo != ~0ull);
+  }
+}
+
+template <class F>
+__global__ __launch_bounds__(BLOCK) void k_validate(SV s, int n, int64_t W, uint32_t *bad) {
+  bool ok = true;
+  for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < W; e += (int64_t)gridDim.x * BLOCK) {
+    for (int i = 0; i < n; i++) {
+      ok = ok && canonical_words<F>(s.val + i * s.ps, s.ls, e);
+      if (s.mac) ok = ok && canonical_words<F>(s.mac + i * s.ps, s.ls, e);
+    }
+  }
+  if (!ok) *bad = 1u;  // every writer stores the same value
+}
+
+__global__ void k_set_flag(uint32_t *flag, uint32_t v) {
+  if (threadIdx.x == 0) *flag = v;
+}
+
+// --------------------------------------------------------------------------
 // plain copy (bandwidth reference): 16-byte vector loads and stores
 // --------------------------------------------------------------------------
 typedef u64 u64x2 __attribute__((ext_vector_type(2)));
@@ -380,6 +414,41 @@ spdz_status launch_copy(u64 *dst, const u64 *src, int64_t words, hipStream_t str
   if (g < 1) g = 1;
   hipLaunchKernelGGL(k_copy, dim3((unsigned)g), dim3(BLOCK), 0, stream, src, dst, words);
   return hip_status(hipGetLastError());
+}
+
+spdz_status launch_validate_clear(spdz_ctx *c) {
+  hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(64), 0, c->stream, c->d_bad, 0u);
+  return hip_status(hipGetLastError());
+}
+
+static spdz_status launch_validate_sv(spdz_ctx *c, SV s, int n, int64_t W) {
+  if (W <= 0) return SPDZ_OK;
+  auto go = [&](auto f) {
+    using F = decltype(f);
+    const int g = grid_for(c, (const void *)k_validate<F>, W);
+    hipLaunchKernelGGL(k_validate<F>, dim3(g), dim3(BLOCK), 0, c->stream, s, n, W, c->d_bad);
+  };
+  switch (c->fid) {
+    case FID_61: go(F61{}); break;
+    case FID_127: go(F127{}); break;
+    default: go(F32{}); break;
+  }
+  return hip_status(hipGetLastError());
+}
+
+spdz_status launch_validate_shares(spdz_ctx *c, const spdz_shares *s) {
+  return launch_validate_sv(c, sv_of(s), c->n, s->len);
+}
+
+spdz_status launch_validate_public(spdz_ctx *c, const u64 *v, int64_t len) {
+  return launch_validate_sv(c, SV{const_cast<u64 *>(v), nullptr, 0, len}, 1, len);
+}
+
+spdz_status validate_result(spdz_ctx *c) {
+  if (hipMemcpyAsync(c->h_bad, c->d_bad, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return SPDZ_E_HIP;
+  return *c->h_bad ? SPDZ_E_INVAL : SPDZ_OK;
 }
 
 spdz_status launch_open(spdz_ctx *c, const spdz_shares *x, u64 *out_pub) {

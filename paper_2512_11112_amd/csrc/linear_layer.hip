@@ -101,9 +101,11 @@ __global__ __launch_bounds__(BLOCK) void k_ll_rows(const LayerArgs<F, N> A) {
   // XCD-aware order: consecutive blocks go to the 8 XCDs in turn, and each XCD has its own L2;
   // when the grid is a multiple of 8, the blocks of XCD x take the row groups of tiles
   // x, x + 8, ..., so a tile's E_t and B_t are fetched into one L2 only.  Every group is
-  // still taken exactly once whichever XCD a block actually runs on.
+  // still taken exactly once whichever XCD a block actually runs on.  Only where the tiles
+  // spread evenly over the 8 groups of blocks (a multiple of 8 tiles, or at least 32 so that
+  // no group holds more than 1.25 x the mean); a layer of a few tiles keeps the plain order.
   constexpr int NX = 8;
-  const bool xcd = gridDim.x % NX == 0;
+  const bool xcd = gridDim.x % NX == 0 && (A.n_tiles % NX == 0 || A.n_tiles >= 4 * NX);
   const int64_t xi = blockIdx.x % NX, bpx = gridDim.x / NX;
   const int64_t mine = xcd ? (xi < A.n_tiles ? (A.n_tiles - xi + NX - 1) / NX : 0) * gpt : ngroups;
 

@@ -62,7 +62,7 @@ struct PNode {
   int group = -1;        // fused element-wise group (one kernel for the group's nodes)
   // buffers
   spdz_shares sh{};      // secret value: device [n][L][width] (values, MACs)
-  u64 *dpub = nullptr;   // public value (or a secret node's public scratch): device [L][width]
+  u64 *dpub = nullptr;   // public value: device [L][width]
   u64 *hpub = nullptr;   // public value: pinned host [L][width]
   spdz_triple tri{};     // product / layer triples dealt during the run
   std::vector<spdz_triple> pool;  // triples dealt ahead (spdz_prog_predeal), by execution number
@@ -602,8 +602,8 @@ spdz_status alloc_buffers(spdz_prog *g) {
   for (auto &kv : g->nodes) {
     PNode &n = kv.second;
     if (n.secret) SPDZ_RET(alloc_shares(g, n.sh, n.width));
-    // public values, and a public scratch for secret nodes with a public operand
-    if (hipMalloc((void **)&n.dpub, (size_t)c->L * n.width * 8) != hipSuccess) return SPDZ_E_NOMEM;
+    // public values: device and pinned host words
+    if (!n.secret && hipMalloc((void **)&n.dpub, (size_t)c->L * n.width * 8) != hipSuccess) return SPDZ_E_NOMEM;
     if (!n.secret && hipHostMalloc((void **)&n.hpub, (size_t)c->L * n.width * 8, hipHostMallocDefault) != hipSuccess)
       return SPDZ_E_NOMEM;
     const bool ss = n.op == OP_MUL && g->nodes[n.args[0]].secret && g->nodes[n.args[1]].secret;
@@ -900,13 +900,8 @@ spdz_status issue(spdz_prog *g, PNode &n) {
           st = launch_pubop(c, SPDZ_PUB_MUL, &s.sh, pb.dpub, pb.width, &n.sh);
         } else if (n.op == OP_ADD) {
           st = launch_pubop(c, SPDZ_PUB_ADD, &s.sh, pb.dpub, pb.width, &n.sh);
-        } else if (a.secret) {  // secret - public: add the negated public value (host, then upload)
-          std::vector<u64> neg((size_t)L * pb.width, 0);
-          host_visit([&](auto f) {
-            host_binop<decltype(f)>(OP_SUB, neg.data(), pb.width, pb.hpub, pb.width, neg.data(), pb.width);
-          });
-          st = upload_words(g, n.dpub, neg.data(), neg.size());
-          if (st == SPDZ_OK) st = launch_pubop(c, SPDZ_PUB_ADD, &s.sh, n.dpub, pb.width, &n.sh);
+        } else if (a.secret) {  // secret - public: the device words of the public operand, on the stream
+          st = launch_pubop(c, SPDZ_PUB_SUB, &s.sh, pb.dpub, pb.width, &n.sh);
         } else {  // public - secret = -secret + public
           u64 cf[2];
           p_minus_1(c, cf);

@@ -55,6 +55,7 @@ def lib() -> ctypes.CDLL:
             "spdz_ctx_create": (i32, [ctypes.POINTER(vp), i32, u64p, i32, u64p, ctypes.c_uint64, vp]),
             "spdz_ctx_destroy": (i32, [vp]),
             "spdz_opened_count": (i64, [vp]),
+            "spdz_ctx_set_validation": (i32, [vp, i32]),
             "spdz_open": (i32, [vp, ctypes.POINTER(Shares), vp]),
             "spdz_mul_batch": (i32, [vp, ctypes.POINTER(Shares), ctypes.POINTER(Shares),
                                      ctypes.POINTER(Triple), ctypes.POINTER(Shares), vp, vp]),
@@ -258,6 +259,10 @@ class Context:
     def opened_count(self) -> int:
         return int(lib().spdz_opened_count(self._h))
 
+    def set_validation(self, enable: bool = True):
+        """Check every input of the online-phase calls for non-canonical words (SPDZ_E_INVAL)."""
+        _check(lib().spdz_ctx_set_validation(self._h, int(bool(enable))), "spdz_ctx_set_validation")
+
     # -- online phase ----------------------------------------------------------
     def spdz_open(self, x: ShareTensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         out = self.new_public(x.width) if out is None else out
@@ -401,7 +406,7 @@ def dag_op_dtype():
     return DAG_OP_DTYPE
 
 
-SPDZ_PUB_ADD, SPDZ_PUB_MUL, SPDZ_PUB_SHARE = 0, 1, 2
+SPDZ_PUB_ADD, SPDZ_PUB_MUL, SPDZ_PUB_SHARE, SPDZ_PUB_SUB = 0, 1, 2, 3
 
 
 def public_op(ctx: "Context", mode: int, x: Optional[ShareTensor], v: torch.Tensor, out: ShareTensor) -> ShareTensor:
@@ -501,6 +506,7 @@ class Dag:
                                      ctypes.byref(h)), "spdz_dag_create")
         self._h = h
         self.n_inputs = len(input_widths)
+        self.input_widths = list(input_widths)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -540,6 +546,22 @@ class Dag:
         _check(lib().spdz_copy_probe(ctypes.c_void_p(out.mac.data_ptr()), ctypes.c_void_p(d.mac), n * d.len, st),
                "spdz_copy_probe")
         return out
+
+    def node_arena(self):
+        """Copies of the whole value and MAC arenas (int64 device tensors of n * sum(widths) words):
+        node k's [n][width] shares start at n * (sum of the widths of nodes before k)."""
+        d = Shares()
+        _check(lib().spdz_dag_node(self._h, 0, ctypes.byref(d)), "spdz_dag_node")
+        widths = [int(w) for w in self.input_widths] + [int(w) for w in self._ops["width"]]
+        words = self.ctx.n * sum(widths)
+        st = ctypes.c_void_p(self.ctx.stream.cuda_stream)
+        val = torch.empty(words, dtype=torch.int64, device="cuda")
+        mac = torch.empty(words, dtype=torch.int64, device="cuda")
+        _check(lib().spdz_copy_probe(ctypes.c_void_p(val.data_ptr()), ctypes.c_void_p(d.val), words, st),
+               "spdz_copy_probe")
+        _check(lib().spdz_copy_probe(ctypes.c_void_p(mac.data_ptr()), ctypes.c_void_p(d.mac), words, st),
+               "spdz_copy_probe")
+        return val, mac
 
     def set_launch(self, tile: int, blocks_per_cu: int):
         _check(lib().spdz_dag_set_launch(self._h, tile, blocks_per_cu), "spdz_dag_set_launch")

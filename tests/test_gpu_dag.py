@@ -110,20 +110,60 @@ def test_dag_time_level():
     assert q == 16
 
 
-@pytest.mark.timeout(1200)
-def test_dag_full_size_graph_mode():
-    """The 100k-op, depth-200 workload (seed 0), all ops on the GPU, hipGraph replay."""
+class ArenaCheck:
+    """Compares every node the oracle produces with host copies of device node arenas."""
+
+    def __init__(self, dag, arenas):
+        widths = np.concatenate(([dag.in_width, dag.in_width], dag.width)).astype(np.int64)
+        self.off = np.concatenate(([0], np.cumsum(dag.n_parties * widths)[:-1]))
+        self.widths, self.n, self.arenas = widths, dag.n_parties, arenas
+        self.bad, self.seen = [], 0
+
+    def __call__(self, node, z):
+        o, w = int(self.off[node]), int(self.widths[node])
+        for name, (v, m) in self.arenas.items():
+            if not (np.array_equal(v[o:o + self.n * w].reshape(self.n, 1, w), z.val) and
+                    np.array_equal(m[o:o + self.n * w].reshape(self.n, 1, w), z.mac)):
+                self.bad.append((name, node))
+        self.seen += 1
+
+
+def arena_host(g):
+    v, m = g.node_arena()
+    out = host(v), host(m)
+    del v, m
+    torch.cuda.empty_cache()
+    return out
+
+
+@pytest.mark.timeout(1500)
+def test_dag_full_size_every_node():
+    """The 100k-op, depth-200 workload (seed 0).  Run 1: every op on the GPU, hipGraph replay.
+    Run 2: the static policy at MIN_KERNEL_SIZE = 65535 (slice 262140 / 4), where the CPU back
+    end runs about 99.4k of the ops.  Every node of both runs (values and MAC shares) equals the
+    oracle's, and so do both MAC checks' sigma (check numbers 0 and 1)."""
     from paper_2512_11112_amd import spdz as S
-    print("case full-size DAG", flush=True)
     dag = make_dag(0, P61)
     assert dag.n_ops == 100000
-    rng = np.random.default_rng(0)
-    sample = set((2 + rng.choice(dag.n_ops, 300, replace=False)).tolist()) | {0, 1, dag.n_ops + 1}
-    sample |= set((2 + np.arange(dag.n_ops - 500, dag.n_ops)).tolist())   # the whole last level
-    ref, ok, sigma = dag_run(dag, seed=0, check_seed=0, keep=sample)
-    print("oracle done", flush=True)
     ctx, g = build(dag, 0)
+    print("case full-size DAG: graph mode, all on the GPU", flush=True)
     g.run(S.MODE_GRAPH, S.POLICY_ALL_GPU)
-    ok_d, sig_d = ctx.spdz_mac_check()
-    assert ok and ok_d and sig_d == ints_of_sigma(sigma)
-    check_nodes(g, ref, sorted(sample))
+    ok0, sig0 = ctx.spdz_mac_check()
+    arenas = {"graph": arena_host(g)}
+    print("case full-size DAG: static policy at 65535", flush=True)
+    g.set_threshold(65535)
+    g.run(S.MODE_PER_LEVEL, S.POLICY_STATIC)
+    st = g.last_stats()
+    assert st["cpu_ops"] > 99000, st
+    g.fetch_host_outputs()
+    ok1, sig1 = ctx.spdz_mac_check()
+    arenas["static"] = arena_host(g)
+    g.close()
+    ctx.close()
+    print("oracle", flush=True)
+    chk = ArenaCheck(dag, arenas)
+    _, ok, sigma, more = dag_run(dag, seed=0, check_seed=0, keep=set(), on_node=chk, more_epochs=(1,))
+    assert chk.seen == dag.n_ops + 2
+    assert not chk.bad, chk.bad[:10]
+    assert ok and ok0 and sig0 == ints_of_sigma(sigma)
+    assert more[1][0] and ok1 and sig1 == ints_of_sigma(more[1][1])

@@ -362,3 +362,70 @@ def test_edge_values_fused(p, n):
     o = ctx2.spdz_linear([share_to_dev(D.x), share_to_dev(D.y), share_to_dev(D.t.c)], c, p - 2)
     torch.cuda.synchronize()
     eq_shares(o, refl, "linear")
+
+
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("p,n", [(P61, 2), (P127, 3), (P_PAPER, 2)])
+def test_validation_rejects_non_canonical_inputs(p, n):
+    """With validation on, a share word equal to p (not a canonical residue) makes the call
+    return SPDZ_E_INVAL with nothing enqueued and the log unchanged; clean inputs still
+    give the oracle's results."""
+    from paper_2512_11112_amd.spdz import ShareTensor, SpdzError, public_op, SPDZ_PUB_ADD
+    W = 777
+    D = deal_elementwise(p, n, W, 3)
+    ref = beaver_run(D, check_seed=3)
+    ctx = make_ctx(D, 3)
+    ctx.set_validation(True)
+    x, y, t = share_to_dev(D.x), share_to_dev(D.y), triple_to_dev(D.t)
+    L = D.f.L
+    pl = [(p >> (64 * l)) & ((1 << 64) - 1) for l in range(L)]
+
+    def poke(tensor, party, e):
+        for l in range(L):
+            tensor[party, l, e] = int(np.array([pl[l]], dtype=np.uint64).view(np.int64)[0])
+
+    bad = ShareTensor(x.val.clone(), x.mac.clone())
+    poke(bad.val, n - 1, W // 2)
+    z = ShareTensor.empty(n, L, W)
+    with pytest.raises(SpdzError) as ei:
+        ctx.spdz_mul_batch(bad, y, t, z)
+    assert ei.value.status == -1
+    assert ctx.opened_count() == 0
+    badm = ShareTensor(x.val.clone(), x.mac.clone())
+    poke(badm.mac, 0, 0)
+    for call in (lambda: ctx.spdz_open(badm), lambda: ctx.spdz_reduce_add(badm),
+                 lambda: ctx.spdz_linear([y, badm], [1, 1])):
+        with pytest.raises(SpdzError) as ei:
+            call()
+        assert ei.value.status == -1
+    assert ctx.opened_count() == 0
+    vbad = torch.zeros((L, W), dtype=torch.int64, device="cuda")
+    for l in range(L):
+        vbad[l, 5] = int(np.array([pl[l]], dtype=np.uint64).view(np.int64)[0])
+    with pytest.raises(SpdzError) as ei:
+        public_op(ctx, SPDZ_PUB_ADD, x, vbad, ShareTensor.empty(n, L, W))
+    assert ei.value.status == -1
+    # clean inputs pass the check and match the oracle
+    ctx.spdz_mul_batch(x, y, t, z)
+    ok, sigma = ctx.spdz_mac_check()
+    assert ok and sigma == ints_of_sigma(ref["sigma"])
+    eq_shares(z, ref["z"], "z")
+    ctx.close()
+
+
+def test_overlapping_party_and_limb_planes_rejected():
+    """Two limbs: a descriptor whose party planes overlap a limb plane (party_stride smaller than
+    limb_stride + len) is rejected with SPDZ_E_SHAPE before any work."""
+    import ctypes
+    from paper_2512_11112_amd import spdz
+    D = deal_elementwise(P127, 2, 64, 1)
+    ctx = make_ctx(D, 1)
+    buf_v = torch.zeros(4 * 64, dtype=torch.int64, device="cuda")
+    buf_m = torch.zeros(4 * 64, dtype=torch.int64, device="cuda")
+    d = spdz.Shares(buf_v.data_ptr(), buf_m.data_ptr(), 64, 128, 128)   # party 1 limb 0 = party 0 limb 1
+    out = ctx.new_public(64)
+    st = spdz.lib().spdz_open(ctx._h, ctypes.byref(d), ctypes.c_void_p(out.data_ptr()))
+    assert st == -3
+    d_ok = spdz.Shares(buf_v.data_ptr(), buf_m.data_ptr(), 64, 128, 64)
+    assert spdz.lib().spdz_open(ctx._h, ctypes.byref(d_ok), ctypes.c_void_p(out.data_ptr())) == 0
+    ctx.close()

@@ -49,7 +49,10 @@ LAYER_CASES = [(P_PAPER, 2, 37, 64, 8),      # ragged last tile
                (P_PAPER, 2, 5, 10, 8),       # one partial tile
                (P_PAPER, 2, 1, 1, 1),
                (P61, 2, 50, 3000, 7),        # rows longer than one accumulation chunk
-               (P_PAPER, 8, 12, 777, 5)]
+               (P_PAPER, 8, 12, 777, 5),
+               (P_PAPER, 2, 4096, 96, 63),   # two rows per block, XCD-aware tile order (66 tiles)
+               (P61, 2, 4100, 40, 64),       # the same with a ragged last tile (65 tiles)
+               (P_PAPER, 2, 4096, 64, 2048)] # two tall tiles: plain order
 
 
 @pytest.mark.parametrize("p,n,dout,din,tr", LAYER_CASES)
@@ -128,8 +131,8 @@ def test_linear_layer_shape_errors():
 # the paper's layer at full size: 8192 x 8192, 2 parties, p = 2^32 - 5, slice
 # 524280 (63-row tiles), launched as the benchmark launches it.  Inputs are
 # dealt on the device by the library and, independently, on the host by the
-# oracle's dealer; sampled tiles are compared in full, the MAC check over all
-# opened values bit for bit.
+# oracle's dealer; every tile's E_t and output shares are compared, and the MAC
+# check over all opened values bit for bit.
 # --------------------------------------------------------------------------
 @pytest.mark.timeout(900)
 def test_linear_layer_full_size_paper_config():
@@ -150,8 +153,8 @@ def test_linear_layer_full_size_paper_config():
     yv, ym, Eh = host(y.val), host(y.mac), host(Ep)
     del W, x, b, T
     torch.cuda.empty_cache()
-    # sampled tiles: first, middle, last (ragged)
-    for t in (0, cfg.n_tiles // 2, cfg.n_tiles - 1):
+    # every tile (the last one is ragged): opened E_t, output shares and MAC shares
+    for t in range(cfg.n_tiles):
         Dt, Et, yt = linear_layer_tile(D, t)
         r0, r1 = D.tile(t)
         assert np.array_equal(Eh[:, t * din:(t + 1) * din], Et), f"E of tile {t} differs"

@@ -29,7 +29,8 @@ def ctx_for(p, n, seed, check_seed):
 
 PROGRAMS = [("pipeline", P.pipeline(3001)), ("branch", P.branch(777)), ("loop", P.loop(1000, 5)),
             ("nested", P.nested(257, 3)), ("select_shl_load", P.select_shl_load(4099, 1000, 77)),
-            ("revealed_branch", P.revealed_branch(513)), ("layer", P.layer(300, 70, 16)),
+            ("revealed_branch", P.revealed_branch(513)), ("opened_operand", P.opened_operand(3001)),
+            ("layer", P.layer(300, 70, 16)),
             ("loop_program", P.loop_program(2048, 4))]
 
 

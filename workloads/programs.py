@@ -224,6 +224,29 @@ ret
 """
 
 
+def opened_operand(W: int) -> str:
+    """Secret and public operands where the public one was opened just before:
+    r = x - open(reduce(x)), q = open(reduce(y)) - y, u = r q, opened (the opened
+    value is read by the next node while its host copy may still be in flight)."""
+    return f"""
+input 1 private {W} 0
+input 2 private {W} 1
+output 5
+output 8
+output 10
+block 0
+3 = reduce 1
+4 = open 3
+5 = sub 1 4
+6 = reduce 2
+7 = open 6
+8 = sub 7 2
+9 = mul 5 8
+10 = open 9
+ret
+"""
+
+
 def layer(din: int, dout: int, tile_rows: int) -> str:
     """y = W x + b (private linear layer), then z = y y opened."""
     return f"""
