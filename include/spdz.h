@@ -73,7 +73,8 @@ typedef enum {
   SPDZ_E_NOMEM = -4,     /* device allocation failed */
   SPDZ_E_HIP = -5,       /* a HIP runtime call failed */
   SPDZ_E_ABORTED = -6,   /* context aborted by an earlier failed MAC check */
-  SPDZ_E_UNSUPPORTED = -7 /* party count outside 2..8, or variant not built */
+  SPDZ_E_UNSUPPORTED = -7, /* party count outside 2..8, or variant not built */
+  SPDZ_E_TOO_LARGE = -8    /* input exceeds the fixed scratch of a no-allocation entry point */
 } spdz_status;
 
 typedef struct {
@@ -198,6 +199,27 @@ spdz_status spdz_mul_fused(spdz_ctx *ctx, const spdz_shares *x, const spdz_share
 spdz_status spdz_linear_layer(spdz_ctx *ctx, int64_t dout, int64_t din, int64_t tile_rows, const spdz_shares *W,
                               const spdz_shares *x, const spdz_shares *b, const spdz_triple *T, spdz_shares *y,
                               uint64_t *D_pub, uint64_t *E_pub);
+
+/* spdz_linear_layer without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Arguments, layout, log order, results and errors are
+ * those of spdz_linear_layer.  When E_pub is NULL the opened E_t are kept in a
+ * fixed per-GPU scratch array of SPDZ_NOALLOC_SCRATCH_WORDS 64-bit words
+ * (32 MiB; every GPU the library runs on holds it until the process ends)
+ * instead of the context workspace; a layer with n_tiles * din above that
+ * returns SPDZ_E_TOO_LARGE with nothing enqueued (with E_pub given, any size is
+ * accepted).  The call itself makes no device or host allocation (kernel
+ * timing, off unless spdz_timing_enable is called, may create HIP events).
+ * Every call on one GPU shares that GPU's scratch array, which keeps the last
+ * call's contents: calls on one stream are ordered by it, but calls that
+ * overlap in time on one GPU (several streams or host threads, several
+ * contexts) race on the array and must be serialised by the caller.  Nothing in
+ * the scratch needs to start at zero (every E_t word is written before it is
+ * read).  Asynchronous. */
+#define SPDZ_NOALLOC_SCRATCH_WORDS (1 << 22)
+spdz_status spdz_linear_layer_noalloc(spdz_ctx *ctx, int64_t dout, int64_t din, int64_t tile_rows,
+                                      const spdz_shares *W, const spdz_shares *x, const spdz_shares *b,
+                                      const spdz_triple *T, spdz_shares *y, uint64_t *D_pub, uint64_t *E_pub);
 
 /* Matrix-triple product (Sec. III-D, "MPC-specific optimization": one
  * matrix triple (A, B, C = A B) per product, D = X - A and E = Y - B opened,

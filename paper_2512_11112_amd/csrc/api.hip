@@ -103,6 +103,7 @@ const char *spdz_status_str(spdz_status s) {
     case SPDZ_E_HIP: return "HIP runtime error";
     case SPDZ_E_ABORTED: return "context aborted by a failed MAC check";
     case SPDZ_E_UNSUPPORTED: return "unsupported party count or variant";
+    case SPDZ_E_TOO_LARGE: return "input exceeds the fixed scratch of a no-allocation entry point";
   }
   return "unknown status";
 }
@@ -137,6 +138,11 @@ spdz_status spdz_ctx_create(spdz_ctx **out, int n_parties, const uint64_t *p_lim
     return SPDZ_E_HIP;
   }
   c->num_cus = prop.multiProcessorCount;
+  // the no-allocation entry point's fixed workspace on this device (once per device)
+  if (noalloc_scratch_init(c->device) != SPDZ_OK) {
+    delete c;
+    return SPDZ_E_HIP;
+  }
   const size_t acc_words = (size_t)MAX_SLOTS * (n_parties + 1) * n_limbs;
   const size_t red_words = (size_t)MAX_SLOTS * 2 * n_parties * n_limbs;
   if (hipMalloc((void **)&c->d_acc, acc_words * 8) != hipSuccess ||
@@ -302,9 +308,8 @@ spdz_status spdz_matmul_triple(spdz_ctx *c, int64_t M, int64_t K, int64_t N, con
   return launch_matmul_triple(c, M, K, N, X, Y, T, Z, E_pub, F_pub, variant);
 }
 
-spdz_status spdz_linear_layer(spdz_ctx *c, int64_t dout, int64_t din, int64_t tile_rows, const spdz_shares *W,
-                              const spdz_shares *x, const spdz_shares *b, const spdz_triple *T, spdz_shares *y,
-                              uint64_t *D_pub, uint64_t *E_pub) {
+static spdz_status check_layer(spdz_ctx *c, int64_t dout, int64_t din, int64_t tile_rows, const spdz_shares *W,
+                               const spdz_shares *x, const spdz_shares *b, const spdz_triple *T, spdz_shares *y) {
   SPDZ_LIVE(c);
   if (!W || !x || !b || !T || !y) return SPDZ_E_INVAL;
   if (c->L != 1) return SPDZ_E_UNSUPPORTED;
@@ -320,8 +325,28 @@ spdz_status spdz_linear_layer(spdz_ctx *c, int64_t dout, int64_t din, int64_t ti
   if (overlaps(c, y, W) || overlaps(c, y, x) || overlaps(c, y, b) || overlaps(c, y, &T->a) ||
       overlaps(c, y, &T->b) || overlaps(c, y, &T->c))
     return SPDZ_E_INVAL;
-  SPDZ_CHECK(validate_inputs(c, {W, x, b, &T->a, &T->b, &T->c}));
-  return launch_linear_layer(c, dout, din, tile_rows, W, x, b, T, y, D_pub, E_pub);
+  return validate_inputs(c, {W, x, b, &T->a, &T->b, &T->c});
+}
+
+spdz_status spdz_linear_layer(spdz_ctx *c, int64_t dout, int64_t din, int64_t tile_rows, const spdz_shares *W,
+                              const spdz_shares *x, const spdz_shares *b, const spdz_triple *T, spdz_shares *y,
+                              uint64_t *D_pub, uint64_t *E_pub) {
+  SPDZ_CHECK(check_layer(c, dout, din, tile_rows, W, x, b, T, y));
+  return launch_linear_layer(c, dout, din, tile_rows, W, x, b, T, y, D_pub, E_pub, nullptr);
+}
+
+spdz_status spdz_linear_layer_noalloc(spdz_ctx *c, int64_t dout, int64_t din, int64_t tile_rows,
+                                      const spdz_shares *W, const spdz_shares *x, const spdz_shares *b,
+                                      const spdz_triple *T, spdz_shares *y, uint64_t *D_pub, uint64_t *E_pub) {
+  SPDZ_LIVE(c);
+  // the size limit first (din and tile_rows positive, so n_tiles * din >= din): nothing is enqueued
+  if (!E_pub && dout > 0 && din > 0 && tile_rows > 0 &&
+      (din > SPDZ_NOALLOC_SCRATCH_WORDS || (dout - 1) / tile_rows + 1 > SPDZ_NOALLOC_SCRATCH_WORDS / din))
+    return SPDZ_E_TOO_LARGE;
+  SPDZ_CHECK(check_layer(c, dout, din, tile_rows, W, x, b, T, y));
+  u64 *scratch = noalloc_scratch(c->device);
+  if (!scratch) return SPDZ_E_HIP;
+  return launch_linear_layer(c, dout, din, tile_rows, W, x, b, T, y, D_pub, E_pub, scratch);
 }
 
 spdz_status spdz_mac_check(spdz_ctx *c, int *accepted, uint64_t *sigma_out) {

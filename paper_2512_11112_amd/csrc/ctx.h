@@ -192,9 +192,15 @@ spdz_status launch_public_matmul(spdz_ctx *c, int64_t M, int64_t K, int64_t N, c
 // grows the context workspace to at least `bytes` (waits for the stream before freeing the old one)
 spdz_status ensure_ws(spdz_ctx *c, size_t bytes);
 // linear_layer.hip
+// E_scratch: where the opened E_t go when E_pub is null (null: the context workspace, grown on demand)
 spdz_status launch_linear_layer(spdz_ctx *c, int64_t dout, int64_t din, int64_t tile_rows, const spdz_shares *W,
                                 const spdz_shares *x, const spdz_shares *b, const spdz_triple *T, spdz_shares *y,
-                                u64 *D_pub, u64 *E_pub);
+                                u64 *D_pub, u64 *E_pub, u64 *E_scratch);
+// the fixed per-GPU workspace of spdz_linear_layer_noalloc: resolved once per device (with that
+// device current) by spdz_ctx_create; the device address for `device`, null if not resolved
+constexpr int MAX_DEVICES = 64;
+spdz_status noalloc_scratch_init(int device);
+u64 *noalloc_scratch(int device);
 spdz_status launch_public_matvec(spdz_ctx *c, int64_t dout, int64_t din, int64_t tile_rows, const u64 *A,
                                  const u64 *B, u64 *C);
 

@@ -19,6 +19,8 @@
 // element of W (values and MACs of W and A).  A block per row (rather than a
 // wave per row) keeps a quarter as many rows in flight, which reads the same
 // arrays about 20 % faster.
+#include <mutex>
+
 #include "blockred.h"
 #include "coef.h"
 
@@ -244,11 +246,36 @@ static spdz_status visit_single_limb(const spdz_ctx *c, Fn &&fn) {
   return SPDZ_E_UNSUPPORTED;
 }
 
+// Fixed workspace of the no-allocation entry point: the opened E_t of every tile.  Each GPU
+// holds its own copy for the life of the process.  Host code never uses this name as an
+// address: it reaches the array only through the pointer hipGetSymbolAddress returns for the
+// current device (kept per device in scratch_ptr).
+static __device__ __align__(256) u64 scratch[SPDZ_NOALLOC_SCRATCH_WORDS];
+
+static std::mutex scratch_mu;
+static u64 *scratch_ptr[MAX_DEVICES] = {};
+
+spdz_status noalloc_scratch_init(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return SPDZ_E_HIP;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (scratch_ptr[device]) return SPDZ_OK;
+  void *p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SPDZ_E_HIP;
+  scratch_ptr[device] = (u64 *)p;
+  return SPDZ_OK;
+}
+
+u64 *noalloc_scratch(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  return scratch_ptr[device];
+}
+
 spdz_status launch_linear_layer(spdz_ctx *c, int64_t dout, int64_t din, int64_t tile_rows, const spdz_shares *W,
                                 const spdz_shares *x, const spdz_shares *b, const spdz_triple *T, spdz_shares *y,
-                                u64 *D_pub, u64 *E_pub) {
+                                u64 *D_pub, u64 *E_pub, u64 *E_scratch) {
   const int64_t n_tiles = (dout + tile_rows - 1) / tile_rows;
-  u64 *Ebuf = E_pub;
+  u64 *Ebuf = E_pub ? E_pub : E_scratch;
   if (!Ebuf) {
     SPDZ_RET(ensure_ws(c, (size_t)(n_tiles * din) * 8));
     Ebuf = (u64 *)c->ws;

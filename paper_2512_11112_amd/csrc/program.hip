@@ -973,7 +973,7 @@ spdz_status issue(spdz_prog *g, PNode &n) {
       spdz_triple *t = nullptr;
       st = node_triple(g, n, t);
       c->log_count = n.log_off;
-      if (st == SPDZ_OK) st = launch_linear_layer(c, dout, din, tr, &W.sh, &x.sh, &b.sh, t, &n.sh, nullptr, nullptr);
+      if (st == SPDZ_OK) st = launch_linear_layer(c, dout, din, tr, &W.sh, &x.sh, &b.sh, t, &n.sh, nullptr, nullptr, nullptr);
       g->launches += 2;
       break;
     }

@@ -21,6 +21,8 @@ P127 = (1 << 127) - 1
 
 SPDZ_OK = 0
 SPDZ_MAC_REJECT = 1
+SPDZ_E_TOO_LARGE = -8
+NOALLOC_SCRATCH_WORDS = 1 << 22   # SPDZ_NOALLOC_SCRATCH_WORDS of spdz.h
 
 
 class SpdzError(RuntimeError):
@@ -74,6 +76,9 @@ def lib() -> ctypes.CDLL:
             "spdz_linear_layer": (i32, [vp, i64, i64, i64, ctypes.POINTER(Shares), ctypes.POINTER(Shares),
                                         ctypes.POINTER(Shares), ctypes.POINTER(Triple), ctypes.POINTER(Shares),
                                         vp, vp]),
+            "spdz_linear_layer_noalloc": (i32, [vp, i64, i64, i64, ctypes.POINTER(Shares), ctypes.POINTER(Shares),
+                                                ctypes.POINTER(Shares), ctypes.POINTER(Triple),
+                                                ctypes.POINTER(Shares), vp, vp]),
             "spdz_deal_matvec_triple": (i32, [vp, ctypes.c_uint64, ctypes.c_uint64, i64, i64, i64,
                                               ctypes.POINTER(Triple)]),
             "spdz_deal_matrix_triple": (i32, [vp, ctypes.c_uint64, ctypes.c_uint64, i64, i64, i64,
@@ -334,6 +339,18 @@ class Context:
         _check(lib().spdz_linear_layer(self._h, dout, din, tile_rows, ctypes.byref(dW), ctypes.byref(dx),
                                        ctypes.byref(db), ctypes.byref(dt), ctypes.byref(dy), _ptr(D_pub),
                                        _ptr(E_pub)), "spdz_linear_layer")
+        return y
+
+    def spdz_linear_layer_noalloc(self, dout: int, din: int, tile_rows: int, W: ShareTensor, x: ShareTensor,
+                                  b: ShareTensor, T: TripleTensor, y: ShareTensor,
+                                  D_pub: Optional[torch.Tensor] = None,
+                                  E_pub: Optional[torch.Tensor] = None) -> ShareTensor:
+        """spdz_linear_layer with no allocation: y must be given; without E_pub the opened E_t use
+        the library's fixed per-GPU scratch (n_tiles * din <= NOALLOC_SCRATCH_WORDS)."""
+        dW, dx, db, dt, dy = W.desc(), x.desc(), b.desc(), T.desc(), y.desc()
+        _check(lib().spdz_linear_layer_noalloc(self._h, dout, din, tile_rows, ctypes.byref(dW), ctypes.byref(dx),
+                                               ctypes.byref(db), ctypes.byref(dt), ctypes.byref(dy), _ptr(D_pub),
+                                               _ptr(E_pub)), "spdz_linear_layer_noalloc")
         return y
 
     def spdz_mac_check(self):
