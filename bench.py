@@ -40,7 +40,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "beaver_fused_n3_p127_w16777216_tr
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2512_11112_amd", "csrc", f) for f in ("beaver.h", "coef.h", "blockred.h", "field.h", "field127r.h")]
 
 
-LAYER_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "linear_layer_rows_n2_p32_d8192_s524280_traffic.md")
+LAYER_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "linear_layer_rows_packed32_n2_p32_d8192_s524280_traffic.md")
 LAYER_SOURCES = [os.path.join(ROOT, "paper_2512_11112_amd", "csrc", f) for f in ("linear_layer.hip", "coef.h", "blockred.h", "field.h")]
 
 
@@ -122,6 +122,8 @@ def main():
                          "linear layer at p = 2^32-5 (input sizes 2048-8192, slice sizes 131070-1048560); "
                          "program: the control-flow runtime on loop programs (throughput and per-entry latency)")
     ap.add_argument("--seeds", type=int, default=20, help="held-out DAG seeds of the dispatch suite")
+    ap.add_argument("--main-only", action="store_true",
+                    help="layer suite: only the d = 8192, slice 524280 configuration (for profiler runs)")
     ap.add_argument("--cpu-only", type=int, default=0, metavar="W",
                     help="time only the oracle on a W-element sample of the headline pipeline (no GPU)")
     args = ap.parse_args()
@@ -158,12 +160,15 @@ def main():
     ctx.spdz_deal_triple(seed, ARR_A, t)
     d_pub, e_pub, w_pub = ctx.new_public(W), ctx.new_public(W), ctx.new_public(W)
     lin = (1, 3, p - 1, 0)
+    s_pub = ctx.new_public(1)
+    # arguments marshalled once; each step enqueues the fused kernel (whose last block also
+    # finishes the ReduceAdd and opens s) and the MAC check, whose verdict is read back
+    mul = ctx.bind_mul_fused(x, y, t, z, d_pub, e_pub, lin=lin, w=w, w_pub=w_pub, s=s, s_pub=s_pub)
+    check = ctx.bind_mac_check()
 
     def step():
-        ctx.spdz_mul_fused(x, y, t, z, d_pub, e_pub, lin=lin, w=w, w_pub=w_pub, s=s)
-        ctx.spdz_open(s)
-        ok, _ = ctx.spdz_mac_check()
-        if not ok:
+        mul()
+        if not check():
             raise RuntimeError("MAC check rejected an honest run")
 
     for _ in range(args.warmup):
@@ -205,7 +210,7 @@ def main():
                      "traffic": traffic, "kernel_ms": k_avg_ms, "launches": k_cnt,
                      "alg_bytes_per_launch": alg_bytes},
     }
-    del x, y, z, w, t, d_pub, e_pub, w_pub
+    del x, y, z, w, t, d_pub, e_pub, w_pub, s_pub, mul, check
     ctx.close()
     torch.cuda.empty_cache()
 
@@ -245,10 +250,11 @@ def extras(torch, S):
         ctx.spdz_deal_secret(seed, ARR_Y, y)
         ctx.spdz_deal_triple(seed, ARR_A, t)
 
+        mul, check = ctx.bind_mul_batch(x, y, t, z), ctx.bind_mac_check()
+
         def step():
-            ctx.spdz_mul_batch(x, y, t, z)
-            ok, _ = ctx.spdz_mac_check()
-            assert ok
+            mul()
+            assert check()
         for _ in range(3):
             step()
         torch.cuda.synchronize()
@@ -266,6 +272,7 @@ def extras(torch, S):
         res[f"beaver_{tag}_mults_per_s"] = W / (ms * 1e-3)
         res[f"beaver_{tag}_kernel_ms"] = kavg
         res[f"beaver_{tag}_kernel_GBps"] = beaver_bytes_per_elem(n, 1) * W / (kavg * 1e-3) / 1e9
+        del mul, check
         ctx.close()
         del x, y, z, t
         torch.cuda.empty_cache()
@@ -351,26 +358,42 @@ def suite_matmul(args):
             "results": res}
 
 
-def layer_bytes(n: int, dout: int, din: int, n_tiles: int):
+def layer_bytes(n: int, dout: int, din: int, n_tiles: int, wb: int = 8):
     """Algorithmic HBM bytes of one private linear layer (one limb, values and MACs of every
-    party): W and A read once (32 n dout din), B and x once per tile / once (16 n n_tiles din,
-    16 n din), E written and read (16 n_tiles din), b and C read and y written (48 n dout).
+    party, wb bytes per residue: 8 in the 64-bit layout, 4 packed): W and A read once
+    (4 wb n dout din), B and x once per tile / once (2 wb n n_tiles din, 2 wb n din), E written
+    and read (2 wb n_tiles din), b and C read and y written (6 wb n dout).
     The row kernel's share: W, A, b, C, y."""
-    total = 32 * n * dout * din + 16 * n * n_tiles * din + 16 * n * din + 16 * n_tiles * din + 48 * n * dout
-    rows = 32 * n * dout * din + 48 * n * dout
+    total = wb * (4 * n * dout * din + 2 * n * n_tiles * din + 2 * n * din + 2 * n_tiles * din + 6 * n * dout)
+    rows = wb * (4 * n * dout * din + 6 * n * dout)
     return total, rows
+
+
+def pack32(S, s):
+    """64-bit device shares [n][1][len] of residues below 2^32 -> packed ShareTensor32 [n][len]
+    (input preparation: the packed layout holds the low word of each residue)."""
+    return S.ShareTensor32(s.val[:, 0, :].to(torch_int32()), s.mac[:, 0, :].to(torch_int32()))
+
+
+def torch_int32():
+    import torch
+    return torch.int32
 
 
 def suite_layer(args):
     """The paper's private linear layer y = W x + b (Sec. III-D, IV): 2 parties, p = 2^32 - 5,
     W d x d with d = 2048, 4096, 8192 at slice 524280 (Sec. IV-E), and slices 131070 .. 1048560
     at d = 8192 (Sec. IV-D).  A step is the layer (open of every E_t, the row kernel) plus the
-    MAC check over everything it opened, verdict read back."""
+    MAC check over everything it opened, verdict read back.  Each configuration runs on both
+    storage layouts: residues packed one per 32-bit word (spdz_linear_layer32, the headline)
+    and 64-bit words (spdz_linear_layer)."""
     import torch
     from paper_2512_11112_amd import spdz as S
     from workloads import ARR_LA, ARR_LB, ARR_LW, ARR_LX, LAYER_DIMS, LAYER_SLICES, SEEDS_TIMING, layer_config
     seed = SEEDS_TIMING[0]
     cfgs = [layer_config(d) for d in LAYER_DIMS] + [layer_config(8192, sl) for sl in LAYER_SLICES if sl != 524280]
+    if args.main_only:
+        cfgs = [layer_config(8192)]
     res = {}
     for cfg in cfgs:
         n, p, dout, din, tr = cfg.n, cfg.p, cfg.dout, cfg.din, cfg.tile_rows
@@ -381,45 +404,53 @@ def suite_layer(args):
         ctx.spdz_deal_secret(seed, ARR_LB, b)
         T = ctx.spdz_deal_matvec_triple(seed, ARR_LA, dout, din, tr, S.TripleTensor.empty_layer(n, dout, din, tr))
         y = ctx.new_shares(dout)
-        for _ in range(args.warmup):
-            ctx.spdz_linear_layer(dout, din, tr, W, x, b, T, y)
-            ok, _ = ctx.spdz_mac_check()
-            assert ok
-        torch.cuda.synchronize()
-        ctx.spdz_timing_enable(True)
-        ts = []
-        for _ in range(args.steps):
-            t0 = time.perf_counter()
-            ctx.spdz_linear_layer(dout, din, tr, W, x, b, T, y)
-            ok, _ = ctx.spdz_mac_check()
-            ts.append((time.perf_counter() - t0) * 1e3)
-            assert ok
-        rows_ms, rc = ctx.spdz_timing_get("layer_rows")
-        e_ms, ec = ctx.spdz_timing_get("layer_open_e")
-        ctx.spdz_timing_enable(False)
-        total_b, rows_b = layer_bytes(n, dout, din, cfg.n_tiles)
-        ms = _median(ts)
-        res[cfg.name] = {"d": din, "slice": cfg.slice, "tile_rows": tr, "tiles": cfg.n_tiles, "step_ms": ms,
-                         "rows_kernel_ms": rows_ms / rc, "open_e_kernel_ms": e_ms / ec,
-                         "alg_bytes": total_b, "rows_kernel_GBps": rows_b / (rows_ms / rc) / 1e6,
-                         "step_GBps": total_b / ms / 1e6}
-        log(f"layer d={din} slice={cfg.slice} ({tr}-row tiles): {ms:.3f} ms/step, row kernel {rows_ms / rc:.3f} ms "
-            f"({rows_b / (rows_ms / rc) / 1e6:.0f} GB/s), E kernel {e_ms / ec:.3f} ms")
+        W32, x32, b32 = pack32(S, W), pack32(S, x), pack32(S, b)
+        T32 = S.TripleTensor32(pack32(S, T.a), pack32(S, T.b), pack32(S, T.c))
+        y32 = S.ShareTensor32.empty(n, dout)
+        layouts = {"packed32": (lambda: ctx.spdz_linear_layer32(dout, din, tr, W32, x32, b32, T32, y32),
+                                "layer_rows_u32", 4),
+                   "u64": (lambda: ctx.spdz_linear_layer(dout, din, tr, W, x, b, T, y), "layer_rows", 8)}
+        for lay, (run, kname, wb) in layouts.items():
+            for _ in range(args.warmup):
+                run()
+                ok, _ = ctx.spdz_mac_check()
+                assert ok
+            torch.cuda.synchronize()
+            ctx.spdz_timing_enable(True)
+            ts = []
+            for _ in range(args.steps):
+                t0 = time.perf_counter()
+                run()
+                ok, _ = ctx.spdz_mac_check()
+                ts.append((time.perf_counter() - t0) * 1e3)
+                assert ok
+            rows_ms, rc = ctx.spdz_timing_get(kname)
+            e_ms, ec = ctx.spdz_timing_get("layer_open_e")
+            ctx.spdz_timing_enable(False)
+            total_b, rows_b = layer_bytes(n, dout, din, cfg.n_tiles, wb)
+            ms = _median(ts)
+            res[f"{cfg.name}_{lay}"] = {"d": din, "slice": cfg.slice, "tile_rows": tr, "tiles": cfg.n_tiles,
+                                        "layout": lay, "step_ms": ms, "rows_kernel_ms": rows_ms / rc,
+                                        "open_e_kernel_ms": e_ms / ec, "alg_bytes": total_b,
+                                        "rows_kernel_GBps": rows_b / (rows_ms / rc) / 1e6, "step_GBps": total_b / ms / 1e6}
+            log(f"layer d={din} slice={cfg.slice} ({tr}-row tiles) {lay}: {ms:.3f} ms/step, row kernel "
+                f"{rows_ms / rc:.3f} ms ({rows_b / (rows_ms / rc) / 1e6:.0f} GB/s), E kernel {e_ms / ec:.3f} ms")
         ctx.close()
-        del W, x, b, T, y
+        del W, x, b, T, y, W32, x32, b32, T32, y32
         torch.cuda.empty_cache()
-    main = res[layer_config(8192).name]
+    main = res[layer_config(8192).name + "_packed32"]
     out = {"metric": "private linear layer y = W x + b latency (2 parties, p = 2^32-5, d = 8192, slice 524280, "
                      "incl. MAC check)",
            "value": main["step_ms"], "unit": "ms", "higher_is_better": False, "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": main["step_ms"], "vs_baseline": None,
-           "dtype": "u64 words (residues < 2^32)", "data": "synthetic",
+           "dtype": "u32 (residues of 2^32-5 packed one per 32-bit word)", "data": "synthetic",
            "config": {"workload": layer_config(8192).name, "parties": 2, "modulus": "2^32-5", "din": 8192,
-                      "dout": 8192, "slice": 524280, "tile_rows": main["tile_rows"]},
-           "roofline": {"bound": "hbm", "kernel": "k_ll_rows<F32,2>", "achieved": main["rows_kernel_GBps"],
+                      "dout": 8192, "slice": 524280, "tile_rows": main["tile_rows"], "layout": "packed32"},
+           "roofline": {"bound": "hbm", "kernel": "k_ll_rows<F32,2,2,u32,4>", "achieved": main["rows_kernel_GBps"],
                         "peak": 8000.0, "unit": "GB/s", "frac": main["rows_kernel_GBps"] / 8000.0,
                         "traffic": read_traffic(8192 * 8192, LAYER_TRAFFIC_FILE, LAYER_SOURCES),
-                        "kernel_ms": main["rows_kernel_ms"], "alg_bytes_per_launch": layer_bytes(2, 8192, 8192, 131)[1]},
+                        "kernel_ms": main["rows_kernel_ms"],
+                        "alg_bytes_per_launch": layer_bytes(2, 8192, 8192, 131, 4)[1]},
            # the paper's own GPU back end on this layer (Sec. IV-D text, 8 threads, another machine): context only
            "paper_context": {"gpu_backend_s_slice131070_T8": 13.37, "gpu_backend_s_slice1048560_T8": 11.07},
            "results": res}

@@ -114,7 +114,7 @@ int64_t spdz_opened_count(const spdz_ctx *ctx);
 /* Turn input validation on (1) or off (0) for this context (see "Inputs must
  * be canonical residues" above).  Validated calls: spdz_open, spdz_mul_batch,
  * spdz_mul_fused, spdz_linear, spdz_public_op, spdz_reduce_add,
- * spdz_matmul_triple, spdz_linear_layer. */
+ * spdz_matmul_triple, spdz_linear_layer, spdz_linear_layer32. */
 spdz_status spdz_ctx_set_validation(spdz_ctx *ctx, int enable);
 
 /* ---------------------------------------------------------------------- */
@@ -166,17 +166,21 @@ spdz_status spdz_public_op(spdz_ctx *ctx, int mode, const spdz_shares *x, const 
 spdz_status spdz_reduce_add(spdz_ctx *ctx, const spdz_shares *x, spdz_shares *out);
 
 /* One pass that fuses a Beaver product with a linear op and a reduction
- * (the same results as spdz_mul_batch, then spdz_linear, spdz_open of w and
- * spdz_reduce_add of z, in that order):
+ * (the same results as spdz_mul_batch, then spdz_linear, spdz_open of w,
+ * spdz_reduce_add of z and spdz_open of its result, in that order):
  *   z = x * y                                   (as spdz_mul_batch)
  *   w = lin[0] z + lin[1] x + lin[2] y + lin[3] (if w != NULL; lin HOST [4][L])
  *   w_pub = open(w)                             (if w_pub != NULL; needs w)
  *   s = ReduceAdd(z)                            (if s != NULL; s->len == 1)
- * Log order: d, e, then w (if opened).  d_pub / e_pub may be NULL. */
+ *   s_pub = open(s)                             (if s_pub != NULL, device [L];
+ *                                                needs s)
+ * One kernel launch: its last block to finish sums the ReduceAdd partials and
+ * opens s.  Log order: d, e, then w (if opened), then s (if opened).  d_pub /
+ * e_pub may be NULL. */
 spdz_status spdz_mul_fused(spdz_ctx *ctx, const spdz_shares *x, const spdz_shares *y,
                            const spdz_triple *t, spdz_shares *z, uint64_t *d_pub,
                            uint64_t *e_pub, const uint64_t *lin, spdz_shares *w,
-                           uint64_t *w_pub, spdz_shares *s);
+                           uint64_t *w_pub, spdz_shares *s, uint64_t *s_pub);
 
 /* Private linear layer y = W x + b (Sec. III-D, "Data slicing" and
  * "MPC-specific optimization"): W is cut into tiles of tile_rows consecutive
@@ -220,6 +224,40 @@ spdz_status spdz_linear_layer(spdz_ctx *ctx, int64_t dout, int64_t din, int64_t 
 spdz_status spdz_linear_layer_noalloc(spdz_ctx *ctx, int64_t dout, int64_t din, int64_t tile_rows,
                                       const spdz_shares *W, const spdz_shares *x, const spdz_shares *b,
                                       const spdz_triple *T, spdz_shares *y, uint64_t *D_pub, uint64_t *E_pub);
+
+/* Shares of a batch over the paper's field p = 2^32 - 5 (Sec. IV-A: 32-bit
+ * inputs) with residues packed one per 32-bit word, half the bytes of the
+ * 64-bit layout: party i's value shares are val[i * party_stride + e], its MAC
+ * shares mac[i * party_stride + e] (strides in uint32 words, party_stride >=
+ * len).  Both pointers are DEVICE memory owned by the caller; words must be
+ * canonical residues (below p). */
+typedef struct {
+  uint32_t *val;          /* device */
+  uint32_t *mac;          /* device */
+  int64_t len;            /* elements */
+  int64_t party_stride;   /* in uint32 words */
+} spdz_shares32;
+
+typedef struct {
+  spdz_shares32 a, b, c;  /* c = a * b; consumed once */
+} spdz_triple32;
+
+/* spdz_linear_layer on packed 32-bit words (spdz_shares32): the same
+ * operation (Sec. III-D, "Data slicing" and "MPC-specific optimization"),
+ * tiles, opened values, log order, aliasing rules and results, residue for
+ * residue, as spdz_linear_layer with 64-bit words, for a context over
+ * p = 2^32 - 5 only (any other returns SPDZ_E_UNSUPPORTED).  Layout per party
+ * as in spdz_linear_layer: W and T->a dout * din row-major, x din, b, T->c and
+ * y dout, T->b n_tiles * din.  D_pub (device uint32 [dout * din]) and E_pub
+ * (device uint32 [n_tiles * din]) receive the opened values and may be NULL
+ * (E then lives in the library workspace, grown on first use).  The row kernel
+ * reads four elements per lane when din, the party strides of W, T->a and T->b
+ * are multiples of 4 and those arrays (and E_pub, D_pub) start on 16-byte
+ * boundaries; other layouts are accepted and read one element per lane.
+ * Asynchronous. */
+spdz_status spdz_linear_layer32(spdz_ctx *ctx, int64_t dout, int64_t din, int64_t tile_rows,
+                                const spdz_shares32 *W, const spdz_shares32 *x, const spdz_shares32 *b,
+                                const spdz_triple32 *T, spdz_shares32 *y, uint32_t *D_pub, uint32_t *E_pub);
 
 /* Matrix-triple product (Sec. III-D, "MPC-specific optimization": one
  * matrix triple (A, B, C = A B) per product, D = X - A and E = Y - B opened,

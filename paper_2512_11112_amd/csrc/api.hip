@@ -147,14 +147,17 @@ spdz_status spdz_ctx_create(spdz_ctx **out, int n_parties, const uint64_t *p_lim
   const size_t red_words = (size_t)MAX_SLOTS * 2 * n_parties * n_limbs;
   if (hipMalloc((void **)&c->d_acc, acc_words * 8) != hipSuccess ||
       hipMalloc((void **)&c->d_red, red_words * 8) != hipSuccess ||
-      hipMalloc((void **)&c->d_sigma, (size_t)(n_parties + 1) * n_limbs * 8) != hipSuccess ||
-      hipHostMalloc((void **)&c->h_sigma, (size_t)(n_parties + 1) * n_limbs * 8, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void **)&c->h_sigma, (size_t)(n_parties + 1) * n_limbs * 8,
+                    hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+      hipHostGetDevicePointer((void **)&c->d_sigma, c->h_sigma, 0) != hipSuccess ||
+      hipMalloc((void **)&c->d_count, 256) != hipSuccess ||
       hipMalloc((void **)&c->d_bad, 256) != hipSuccess ||
       hipHostMalloc((void **)&c->h_bad, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
     spdz_ctx_destroy(c);
     return SPDZ_E_NOMEM;
   }
   if (hipMemset(c->d_acc, 0, acc_words * 8) != hipSuccess || hipMemset(c->d_red, 0, red_words * 8) != hipSuccess ||
+      hipMemset(c->d_count, 0, 256) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess) {
     spdz_ctx_destroy(c);
     return SPDZ_E_HIP;
@@ -173,7 +176,7 @@ spdz_status spdz_ctx_destroy(spdz_ctx *c) {
   for (hipEvent_t e : c->event_pool) hipEventDestroy(e);
   if (c->d_acc) hipFree(c->d_acc);
   if (c->d_red) hipFree(c->d_red);
-  if (c->d_sigma) hipFree(c->d_sigma);
+  if (c->d_count) hipFree(c->d_count);
   if (c->ws) hipFree(c->ws);
   if (c->h_sigma) hipHostFree(c->h_sigma);
   if (c->d_bad) hipFree(c->d_bad);
@@ -222,12 +225,12 @@ spdz_status spdz_mul_batch(spdz_ctx *c, const spdz_shares *x, const spdz_shares 
   SPDZ_CHECK(check_mul_operands(c, x, y, t, z));
   if (x->len == 0) return SPDZ_OK;
   SPDZ_CHECK(validate_inputs(c, {x, y, &t->a, &t->b, &t->c}));
-  return launch_beaver(c, x, y, t, z, d_pub, e_pub, nullptr, nullptr, nullptr, nullptr);
+  return launch_beaver(c, x, y, t, z, d_pub, e_pub, nullptr, nullptr, nullptr, nullptr, nullptr);
 }
 
 spdz_status spdz_mul_fused(spdz_ctx *c, const spdz_shares *x, const spdz_shares *y, const spdz_triple *t,
                            spdz_shares *z, uint64_t *d_pub, uint64_t *e_pub, const uint64_t *lin, spdz_shares *w,
-                           uint64_t *w_pub, spdz_shares *s) {
+                           uint64_t *w_pub, spdz_shares *s, uint64_t *s_pub) {
   SPDZ_LIVE(c);
   SPDZ_CHECK(check_mul_operands(c, x, y, t, z));
   if (w) {
@@ -240,9 +243,10 @@ spdz_status spdz_mul_fused(spdz_ctx *c, const spdz_shares *x, const spdz_shares 
     return SPDZ_E_INVAL;
   }
   if (s) SPDZ_CHECK(check_sv(c, s, 1));
+  else if (s_pub) return SPDZ_E_INVAL;
   if (x->len == 0) return SPDZ_OK;
   SPDZ_CHECK(validate_inputs(c, {x, y, &t->a, &t->b, &t->c}));
-  return launch_beaver(c, x, y, t, z, d_pub, e_pub, lin, w, w_pub, s);
+  return launch_beaver(c, x, y, t, z, d_pub, e_pub, lin, w, w_pub, s, s_pub);
 }
 
 spdz_status spdz_linear(spdz_ctx *c, int n_terms, const spdz_shares *terms, const uint64_t *coeffs,
@@ -349,15 +353,62 @@ spdz_status spdz_linear_layer_noalloc(spdz_ctx *c, int64_t dout, int64_t din, in
   return launch_linear_layer(c, dout, din, tile_rows, W, x, b, T, y, D_pub, E_pub, scratch);
 }
 
+// packed 32-bit descriptors: len as expected, party planes disjoint
+static spdz_status check_sv32(const spdz_shares32 *s, int64_t len) {
+  if (!s) return SPDZ_E_INVAL;
+  if (s->len != len || len < 0) return SPDZ_E_SHAPE;
+  if (len == 0) return SPDZ_OK;
+  if (!s->val || !s->mac) return SPDZ_E_INVAL;
+  if (s->party_stride < s->len) return SPDZ_E_SHAPE;
+  return SPDZ_OK;
+}
+
+static bool overlaps32(int n, const spdz_shares32 *a, const spdz_shares32 *b) {
+  const uint32_t *pa[2] = {a->val, a->mac}, *pb[2] = {b->val, b->mac};
+  for (const uint32_t *x : pa)
+    for (const uint32_t *y : pb) {
+      const uint32_t *xe = x + (int64_t)(n - 1) * a->party_stride + a->len;
+      const uint32_t *ye = y + (int64_t)(n - 1) * b->party_stride + b->len;
+      if (x < ye && y < xe) return true;
+    }
+  return false;
+}
+
+spdz_status spdz_linear_layer32(spdz_ctx *c, int64_t dout, int64_t din, int64_t tile_rows, const spdz_shares32 *W,
+                                const spdz_shares32 *x, const spdz_shares32 *b, const spdz_triple32 *T,
+                                spdz_shares32 *y, uint32_t *D_pub, uint32_t *E_pub) {
+  SPDZ_LIVE(c);
+  if (!W || !x || !b || !T || !y) return SPDZ_E_INVAL;
+  if (c->fid != FID_32) return SPDZ_E_UNSUPPORTED;
+  if (dout <= 0 || din <= 0 || tile_rows <= 0 || dout > (INT64_MAX / 4) / din) return SPDZ_E_SHAPE;
+  const int64_t n_tiles = (dout + tile_rows - 1) / tile_rows;
+  SPDZ_CHECK(check_sv32(W, dout * din));
+  SPDZ_CHECK(check_sv32(&T->a, dout * din));
+  SPDZ_CHECK(check_sv32(x, din));
+  SPDZ_CHECK(check_sv32(&T->b, n_tiles * din));
+  SPDZ_CHECK(check_sv32(b, dout));
+  SPDZ_CHECK(check_sv32(&T->c, dout));
+  SPDZ_CHECK(check_sv32(y, dout));
+  for (const spdz_shares32 *in : {W, x, b, &T->a, &T->b, &T->c})
+    if (overlaps32(c->n, y, in)) return SPDZ_E_INVAL;
+  if (c->validate) {
+    SPDZ_CHECK(launch_validate_clear(c));
+    for (const spdz_shares32 *in : {W, x, b, &T->a, &T->b, &T->c}) {
+      SPDZ_CHECK(launch_validate_u32(c, in->val, c->n, in->party_stride, in->len));
+      SPDZ_CHECK(launch_validate_u32(c, in->mac, c->n, in->party_stride, in->len));
+    }
+    SPDZ_CHECK(validate_result(c));
+  }
+  return launch_linear_layer32(c, dout, din, tile_rows, W, x, b, T, y, D_pub, E_pub);
+}
+
 spdz_status spdz_mac_check(spdz_ctx *c, int *accepted, uint64_t *sigma_out) {
   SPDZ_LIVE(c);
   if (!accepted) return SPDZ_E_INVAL;
   *accepted = 0;
+  // the finalisation kernel writes the totals straight into pinned host memory: one wait, no copy
   SPDZ_CHECK(launch_maccheck_finalize(c));
-  const size_t bytes = (size_t)(c->n + 1) * c->L * 8;
-  if (hipMemcpyAsync(c->h_sigma, c->d_sigma, bytes, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
-      hipStreamSynchronize(c->stream) != hipSuccess)
-    return SPDZ_E_HIP;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return SPDZ_E_HIP;
   // a = sum_j r_j a_j and G_i = sum_j r_j gamma_i(a_j), device slots plus the CPU back end's sums;
   // sigma_i = G_i - alpha_i a, accept iff sum_i sigma_i = 0
   bool zero;

@@ -36,7 +36,11 @@ struct BeaverArgs {
   typename F::E alin3[N];   // alpha_i * lin3
   SV w;
   u64 *w_pub;
-  u64 *red;
+  u64 *red;          // ReduceAdd slots (null: no ReduceAdd)
+  SV s;              // ReduceAdd result, written by the last block to finish
+  u64 *s_pub;        // nullable: the result opened, at log index js
+  int64_t js;
+  unsigned *count;   // blocks finished (the last one resets it to zero)
   // 32-bit offset addressing (all share arrays with one layout): byte strides
   u32 ps8, ls8, w8;
 };
@@ -226,6 +230,20 @@ __global__ __launch_bounds__(BLOCK) void k_beaver(const BeaverArgs<F, N> A) {
 #pragma unroll
       for (int k = 0; k < 2 * N; k++) rso[k] = AR::out(R::norm(rs[k]));
       block_add_to_slot<F, 2 * N>(rso, A.red + (size_t)blockIdx.x * 2 * N * F::L);
+      // the last block to finish sums every block's ReduceAdd slot (and opens the result), so no
+      // separate finalisation launch follows: each block's slot writes are made visible device
+      // wide before it counts itself, the last block acquires them after its count
+      __shared__ int last;
+      __threadfence();
+      __syncthreads();
+      if (threadIdx.x == 0) last = atomicAdd(A.count, 1u) == gridDim.x - 1;
+      __syncthreads();
+      if (last) {
+        __threadfence();
+        reduce_finalize_block<F, N>(A.red, gridDim.x, A.s, A.s_pub, A.coef_state, A.js,
+                                    A.acc + (size_t)blockIdx.x * (N + 1) * F::L);
+        if (threadIdx.x == 0) atomicExch(A.count, 0u);
+      }
     }
   }
 }
@@ -247,7 +265,7 @@ static bool offsets_fit32(const spdz_shares *const *arrs, int k, int n, int L, i
 template <class F>
 spdz_status launch_beaver_field(spdz_ctx *c, const spdz_shares *x, const spdz_shares *y, const spdz_triple *t,
                           spdz_shares *z, u64 *d_pub, u64 *e_pub, const u64 *lin, spdz_shares *w, u64 *w_pub,
-                          spdz_shares *s) {
+                          spdz_shares *s, u64 *s_pub) {
   const bool fused = (w != nullptr) || (s != nullptr);
   return visit_n<F>(c->n, [&](auto, auto nn) -> spdz_status {
     constexpr int N = decltype(nn)::value;
@@ -271,6 +289,10 @@ spdz_status launch_beaver_field(spdz_ctx *c, const spdz_shares *x, const spdz_sh
     A.w = w ? sv_of(w) : SV{nullptr, nullptr, 0, 0};
     A.w_pub = w ? w_pub : nullptr;
     A.red = s ? c->d_red : nullptr;
+    A.s = s ? sv_of(s) : SV{nullptr, nullptr, 0, 0};
+    A.s_pub = s ? s_pub : nullptr;
+    A.js = A.j0 + 2 * A.W + (A.w_pub ? A.W : 0);
+    A.count = c->d_count;
     const spdz_shares *arrs[7] = {x, y, &t->a, &t->b, &t->c, z, w};
     const bool o32 = offsets_fit32(arrs, 7, N, F::L, A.W);
     A.ps8 = o32 ? (u32)(x->party_stride * 8) : 0;
@@ -295,9 +317,8 @@ spdz_status launch_beaver_field(spdz_ctx *c, const spdz_shares *x, const spdz_sh
     }
     spdz_status st = hip_status(hipGetLastError());
     if (st != SPDZ_OK) return st;
-    c->log_count += 2 * A.W + (A.w_pub ? A.W : 0);
+    c->log_count += 2 * A.W + (A.w_pub ? A.W : 0) + (A.s_pub ? 1 : 0);
     if (g > c->slots) c->slots = g;
-    if (s) st = launch_reduce_finalize(c, g, s);
     return st;
   });
 }

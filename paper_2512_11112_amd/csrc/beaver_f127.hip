@@ -4,5 +4,5 @@
 namespace spdz {
 template spdz_status launch_beaver_field<F127>(spdz_ctx *, const spdz_shares *, const spdz_shares *,
                                                const spdz_triple *, spdz_shares *, u64 *, u64 *, const u64 *,
-                                               spdz_shares *, u64 *, spdz_shares *);
+                                               spdz_shares *, u64 *, spdz_shares *, u64 *);
 }  // namespace spdz

@@ -52,4 +52,56 @@ __device__ __forceinline__ void block_add_to_slot(typename F::E (&v)[K], u64 *sl
   }
 }
 
+// ReduceAdd finalisation by one block: sums slots [0, nslots) of red ([slot][2 N][L], the
+// values then the MAC shares of the N parties), clears them and writes the width-1 result to
+// out.  With s_pub the result is also opened: s_pub receives sum_i s_i, and the MAC-check
+// terms r s and r m(s)_i of log index js are added to acc_slot ([N + 1][L], a slot this block
+// owns).  Contains __syncthreads(): call from every thread of the block.
+template <class F, int N>
+__device__ void reduce_finalize_block(u64 *red, int nslots, SV out, u64 *s_pub, u64 coef_state, int64_t js,
+                                      u64 *acc_slot) {
+  using E = typename F::E;
+  E s[2 * N];
+#pragma unroll
+  for (int k = 0; k < 2 * N; k++) s[k] = F::zero();
+  for (int b = threadIdx.x; b < nslots; b += BLOCK) {
+    u64 *p = red + (size_t)b * 2 * N * F::L;
+#pragma unroll
+    for (int k = 0; k < 2 * N; k++) {
+      s[k] = F::add(s[k], F::from_words(p + k * F::L));
+#pragma unroll
+      for (int l = 0; l < F::L; l++) p[k * F::L + l] = 0;
+    }
+  }
+  const E t = block_sum<F, 2 * N>(s);
+  __shared__ E tot[2 * N];
+  if (threadIdx.x < 2 * N) {
+    const int i = threadIdx.x % N;
+    u64 *base = (threadIdx.x < N ? out.val : out.mac) + i * out.ps;
+    u64 w[F::L];
+    F::to_words(t, w);
+#pragma unroll
+    for (int l = 0; l < F::L; l++) base[l * out.ls] = w[l];
+    tot[threadIdx.x] = t;
+  }
+  if (!s_pub) return;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    E v = F::zero();
+#pragma unroll
+    for (int i = 0; i < N; i++) v = F::add(v, tot[i]);
+    u64 w[F::L];
+    F::to_words(v, w);
+#pragma unroll
+    for (int l = 0; l < F::L; l++) s_pub[l] = w[l];
+    const E r = uniform_elem<F>(coef_state, (u64)js);
+    F::to_words(F::add(F::from_words(acc_slot), F::mul(r, v)), acc_slot);
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+      u64 *q = acc_slot + (1 + i) * F::L;
+      F::to_words(F::add(F::from_words(q), F::mul(r, tot[N + i])), q);
+    }
+  }
+}
+
 }  // namespace spdz

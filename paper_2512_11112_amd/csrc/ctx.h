@@ -51,8 +51,9 @@ struct spdz_ctx {
   int slots = 0;                // accumulator slots in use (= max grid of accumulating kernels)
   spdz::u64 *d_acc = nullptr;   // MAC-check partial sums [MAX_SLOTS][n + 1][L]
   spdz::u64 *d_red = nullptr;   // ReduceAdd partial sums [MAX_SLOTS][2 n][L]
-  spdz::u64 *d_sigma = nullptr; // [n][L]
-  spdz::u64 *h_sigma = nullptr; // pinned host copy of d_sigma
+  spdz::u64 *h_sigma = nullptr; // [n + 1][L] MAC-check totals, pinned host memory the finalisation kernel writes
+  spdz::u64 *d_sigma = nullptr; // device address of h_sigma
+  unsigned *d_count = nullptr;  // blocks finished of the fused Beaver kernel (zero between launches)
   // MAC-check sums contributed by ops that ran on the CPU back end ([0] = A, [1 + i] = G_i), canonical
   spdz::u64 host_acc[spdz::MAX_PARTIES + 1][2] = {};
   int grid_mult = 0;            // blocks per CU for streaming kernels (0 = from occupancy)
@@ -144,9 +145,11 @@ struct KTimer {
 spdz_status launch_open(spdz_ctx *c, const spdz_shares *x, u64 *out_pub);
 // opens sum_i (x_i - sub_i) (the mask step of a Beaver product), logging it with MAC shares m(x)_i - m(sub)_i
 spdz_status launch_open_diff(spdz_ctx *c, const spdz_shares *x, const spdz_shares *sub, u64 *out_pub);
+// s (with w or alone: the fused kernel) = ReduceAdd(z), finalised by the kernel's last block, which
+// also opens it into s_pub (nullable)
 spdz_status launch_beaver(spdz_ctx *c, const spdz_shares *x, const spdz_shares *y, const spdz_triple *t,
                           spdz_shares *z, u64 *d_pub, u64 *e_pub, const u64 *lin, spdz_shares *w, u64 *w_pub,
-                          spdz_shares *s);
+                          spdz_shares *s, u64 *s_pub);
 spdz_status launch_linear(spdz_ctx *c, int nt, const spdz_shares *terms, const u64 *coeffs, const u64 *c0,
                           spdz_shares *out);
 spdz_status launch_reduce(spdz_ctx *c, const spdz_shares *x, spdz_shares *out);
@@ -183,6 +186,8 @@ spdz_status launch_copy(u64 *dst, const u64 *src, int64_t words, hipStream_t str
 spdz_status launch_validate_clear(spdz_ctx *c);
 spdz_status launch_validate_shares(spdz_ctx *c, const spdz_shares *s);
 spdz_status launch_validate_public(spdz_ctx *c, const u64 *v, int64_t len);
+// n rows of len packed 32-bit words at v + i * stride
+spdz_status launch_validate_u32(spdz_ctx *c, const u32 *v, int n, int64_t stride, int64_t len);
 spdz_status validate_result(spdz_ctx *c);
 // matmul.hip
 spdz_status launch_matmul_triple(spdz_ctx *c, int64_t M, int64_t K, int64_t N, const spdz_shares *X,
@@ -196,6 +201,10 @@ spdz_status ensure_ws(spdz_ctx *c, size_t bytes);
 spdz_status launch_linear_layer(spdz_ctx *c, int64_t dout, int64_t din, int64_t tile_rows, const spdz_shares *W,
                                 const spdz_shares *x, const spdz_shares *b, const spdz_triple *T, spdz_shares *y,
                                 u64 *D_pub, u64 *E_pub, u64 *E_scratch);
+// the same layer on packed 32-bit words (p = 2^32 - 5 only)
+spdz_status launch_linear_layer32(spdz_ctx *c, int64_t dout, int64_t din, int64_t tile_rows, const spdz_shares32 *W,
+                                  const spdz_shares32 *x, const spdz_shares32 *b, const spdz_triple32 *T,
+                                  spdz_shares32 *y, u32 *D_pub, u32 *E_pub);
 // the fixed per-GPU workspace of spdz_linear_layer_noalloc: resolved once per device (with that
 // device current) by spdz_ctx_create; the device address for `device`, null if not resolved
 constexpr int MAX_DEVICES = 64;

@@ -186,28 +186,7 @@ __global__ __launch_bounds__(BLOCK) void k_reduce(SV x, int64_t W, u64 *red) {
 // sums slots [0, nslots) of red, writes the width-1 result to out, clears the slots
 template <class F, int N>
 __global__ __launch_bounds__(BLOCK) void k_reduce_finalize(u64 *red, int nslots, SV out) {
-  using E = typename F::E;
-  E s[2 * N];
-#pragma unroll
-  for (int k = 0; k < 2 * N; k++) s[k] = F::zero();
-  for (int b = threadIdx.x; b < nslots; b += BLOCK) {
-    u64 *p = red + (size_t)b * 2 * N * F::L;
-#pragma unroll
-    for (int k = 0; k < 2 * N; k++) {
-      s[k] = F::add(s[k], F::from_words(p + k * F::L));
-#pragma unroll
-      for (int l = 0; l < F::L; l++) p[k * F::L + l] = 0;
-    }
-  }
-  E t = block_sum<F, 2 * N>(s);
-  if (threadIdx.x < 2 * N) {
-    const int i = threadIdx.x % N;
-    u64 *base = (threadIdx.x < N ? out.val : out.mac) + i * out.ps;
-    u64 w[F::L];
-    F::to_words(t, w);
-#pragma unroll
-    for (int l = 0; l < F::L; l++) base[l * out.ls] = w[l];
-  }
+  reduce_finalize_block<F, N>(red, nslots, out, nullptr, 0, 0, nullptr);
 }
 
 // --------------------------------------------------------------------------
@@ -217,7 +196,7 @@ template <class F, int N>
 struct FinArgs {
   u64 *acc;
   int nslots;
-  u64 *sigma;  // receives the N + 1 totals
+  u64 *sigma;  // receives the N + 1 totals (device address of pinned host memory)
 };
 
 template <class F, int N>
@@ -235,9 +214,12 @@ __global__ __launch_bounds__(BLOCK) void k_mac_finalize(const FinArgs<F, N> A) {
       for (int l = 0; l < F::L; l++) p[k * F::L + l] = 0;
     }
   }
-  // totals of the device slots: [0] = sum r a, [1 + i] = sum r gamma_i
+  // totals of the device slots: [0] = sum r a, [1 + i] = sum r gamma_i, stored to pinned host memory
   E t = block_sum<F, N + 1>(s);
-  if (threadIdx.x <= N) F::to_words(t, A.sigma + threadIdx.x * F::L);
+  if (threadIdx.x <= N) {
+    F::to_words(t, A.sigma + threadIdx.x * F::L);
+    __threadfence_system();
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -332,6 +314,15 @@ __global__ __launch_bounds__(BLOCK) void k_validate(SV s, int n, int64_t W, uint
       if (s.mac) ok = ok && canonical_words<F>(s.mac + i * s.ps, s.ls, e);
     }
   }
+  if (!ok) *bad = 1u;  // every writer stores the same value
+}
+
+// n rows of len packed 32-bit residues of 2^32 - 5 at v + i * stride
+__global__ __launch_bounds__(BLOCK) void k_validate_u32(const u32 *v, int n, int64_t stride, int64_t len,
+                                                        uint32_t *bad) {
+  bool ok = true;
+  for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < len; e += (int64_t)gridDim.x * BLOCK)
+    for (int i = 0; i < n; i++) ok = ok && v[i * stride + e] < (u32)F32::P;
   if (!ok) *bad = 1u;  // every writer stores the same value
 }
 
@@ -444,6 +435,13 @@ spdz_status launch_validate_public(spdz_ctx *c, const u64 *v, int64_t len) {
   return launch_validate_sv(c, SV{const_cast<u64 *>(v), nullptr, 0, len}, 1, len);
 }
 
+spdz_status launch_validate_u32(spdz_ctx *c, const u32 *v, int n, int64_t stride, int64_t len) {
+  if (len <= 0 || !v) return SPDZ_OK;
+  const int g = grid_for(c, (const void *)k_validate_u32, len);
+  hipLaunchKernelGGL(k_validate_u32, dim3(g), dim3(BLOCK), 0, c->stream, v, n, stride, len, c->d_bad);
+  return hip_status(hipGetLastError());
+}
+
 spdz_status validate_result(spdz_ctx *c) {
   if (hipMemcpyAsync(c->h_bad, c->d_bad, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess)
@@ -483,15 +481,15 @@ spdz_status launch_open_diff(spdz_ctx *c, const spdz_shares *x, const spdz_share
 template <class F>
 spdz_status launch_beaver_field(spdz_ctx *c, const spdz_shares *x, const spdz_shares *y, const spdz_triple *t,
                                 spdz_shares *z, u64 *d_pub, u64 *e_pub, const u64 *lin, spdz_shares *w, u64 *w_pub,
-                                spdz_shares *s);
+                                spdz_shares *s, u64 *s_pub);
 
 spdz_status launch_beaver(spdz_ctx *c, const spdz_shares *x, const spdz_shares *y, const spdz_triple *t,
                           spdz_shares *z, u64 *d_pub, u64 *e_pub, const u64 *lin, spdz_shares *w, u64 *w_pub,
-                          spdz_shares *s) {
+                          spdz_shares *s, u64 *s_pub) {
   switch (c->fid) {
-    case FID_61: return launch_beaver_field<F61>(c, x, y, t, z, d_pub, e_pub, lin, w, w_pub, s);
-    case FID_127: return launch_beaver_field<F127>(c, x, y, t, z, d_pub, e_pub, lin, w, w_pub, s);
-    default: return launch_beaver_field<F32>(c, x, y, t, z, d_pub, e_pub, lin, w, w_pub, s);
+    case FID_61: return launch_beaver_field<F61>(c, x, y, t, z, d_pub, e_pub, lin, w, w_pub, s, s_pub);
+    case FID_127: return launch_beaver_field<F127>(c, x, y, t, z, d_pub, e_pub, lin, w, w_pub, s, s_pub);
+    default: return launch_beaver_field<F32>(c, x, y, t, z, d_pub, e_pub, lin, w, w_pub, s, s_pub);
   }
 }
 

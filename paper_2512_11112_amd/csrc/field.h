@@ -247,9 +247,11 @@ struct F32 {
   struct E {
     u32 v;
   };
-  // sum of once-folded products (each < 6 * 2^32) and residues: exact below 2^64
+  // exact sum hi 2^64 + lo of products (each < 2^64) and residues: one carry per term at most,
+  // so hi counts at most 2^32 - 1 of them
   struct Wide {
-    u64 v;
+    u64 lo;
+    u32 hi;
   };
   static constexpr int WIDE_TERMS = 1 << 28;
 
@@ -280,10 +282,21 @@ struct F32 {
     return smask ? neg(t) : t;
   }
   SPDZ_HD static E norm(E a) { return a; }
-  SPDZ_HD static Wide wzero() { return {0}; }
-  SPDZ_HD static void wmac(Wide &w, E a, E b) { w.v += fold((u64)a.v * b.v); }
-  SPDZ_HD static void wadd(Wide &w, E a) { w.v += a.v; }
-  SPDZ_HD static E wreduce(Wide w) { return reduce(w.v); }
+  SPDZ_HD static Wide wzero() { return {0, 0}; }
+  // a 32 x 32 -> 64-bit product added with its carry: one multiply-add and one add-with-carry
+  SPDZ_HD static void wmac(Wide &w, E a, E b) {
+    const u64 p = (u64)a.v * b.v;
+    const u64 s = w.lo + p;
+    w.hi += s < p;
+    w.lo = s;
+  }
+  SPDZ_HD static void wadd(Wide &w, E a) {
+    const u64 s = w.lo + a.v;
+    w.hi += s < a.v;
+    w.lo = s;
+  }
+  // 2^64 = 25 (mod p): hi 2^64 + lo = 25 hi + (lo mod p), below 2^37
+  SPDZ_HD static E wreduce(Wide w) { return reduce((u64)reduce(w.lo).v + 25ull * w.hi); }
 
   __device__ __forceinline__ static E load(const u64 *base, int64_t /*limb_stride*/, int64_t idx) {
     return {(u32)__builtin_nontemporal_load(base + idx)};
@@ -322,10 +335,16 @@ SPDZ_HD u64 sm_out(u64 state, u64 i) { return mix64(state + (i + 1) * GOLDEN); }
 template <class F>
 SPDZ_HD typename F::E uniform_elem(u64 state, u64 e);
 
+// The first attempt is accepted for all but a 2^-61 (2^-127, 5 2^-32) fraction of elements;
+// later attempts sit in a loop the compiler must not unroll, so that the common path costs one
+// generator output per word instead of several computed side by side.
 template <>
 SPDZ_HD F61::E uniform_elem<F61>(u64 state, u64 e) {
   const u64 base = e * 32u;
-  for (int k = 0; k < 16; k++) {
+  const u64 u0 = sm_out(state, base) & F61::P;
+  if (__builtin_expect(u0 < F61::P, 1)) return {u0};
+#pragma unroll 1
+  for (int k = 1; k < 16; k++) {
     u64 u = sm_out(state, base + k) & F61::P;
     if (u < F61::P) return {u};
   }
@@ -335,10 +354,13 @@ SPDZ_HD F61::E uniform_elem<F61>(u64 state, u64 e) {
 template <>
 SPDZ_HD F127::E uniform_elem<F127>(u64 state, u64 e) {
   const u64 base = e * 32u;
-  for (int k = 0; k < 16; k++) {
+  // below p unless every one of the 127 bits is set
+  const u64 lo0 = sm_out(state, base), hi0 = sm_out(state, base + 1) & F127::PHI;
+  if (__builtin_expect(!(hi0 == F127::PHI && lo0 == ~0ull), 1)) return {lo0, hi0};
+#pragma unroll 1
+  for (int k = 1; k < 16; k++) {
     u64 lo = sm_out(state, base + 2 * k);
     u64 hi = sm_out(state, base + 2 * k + 1) & F127::PHI;
-    // below p unless every one of the 127 bits is set
     if (!(hi == F127::PHI && lo == ~0ull)) return {lo, hi};
   }
   return {0, 0};
@@ -347,7 +369,10 @@ SPDZ_HD F127::E uniform_elem<F127>(u64 state, u64 e) {
 template <>
 SPDZ_HD F32::E uniform_elem<F32>(u64 state, u64 e) {
   const u64 base = e * 32u;
-  for (int k = 0; k < 16; k++) {
+  const u64 u0 = sm_out(state, base) & 0xffffffffull;
+  if (__builtin_expect(u0 < F32::P, 1)) return {(u32)u0};
+#pragma unroll 1
+  for (int k = 1; k < 16; k++) {
     const u64 u = sm_out(state, base + k) & 0xffffffffull;
     if (u < F32::P) return {(u32)u};
   }

@@ -19,6 +19,11 @@
 // element of W (values and MACs of W and A).  A block per row (rather than a
 // wave per row) keeps a quarter as many rows in flight, which reads the same
 // arrays about 20 % faster.
+//
+// Storage: 64-bit words (any single-limb field) or, for p = 2^32 - 5, residues
+// packed one per 32-bit word, which halves the bytes the row kernel streams.
+// The packed kernels take four consecutive elements per lane (16-byte loads)
+// when the row length and the party strides allow it.
 #include <mutex>
 
 #include "blockred.h"
@@ -30,12 +35,70 @@ namespace spdz {
 // tall and there are rows enough to fill the GPU, else one (measured at d = 2048 .. 8192)
 inline int ll_rows_per_block(int64_t dout, int64_t tile_rows) { return tile_rows >= 31 && dout >= 4096 ? 2 : 1; }
 
-template <class F, int N>
+// a share array in words of type Wt: party i's words at val / mac + i * ps
+template <class Wt>
+struct SVW {
+  Wt *val, *mac;
+  int64_t ps;
+};
+
+// residue access to words of type Wt: 64-bit words (every single-limb field) or packed 32-bit
+// words (residues of 2^32 - 5); V consecutive elements per call (V = 4 needs 16-byte alignment)
+template <class F, class Wt>
+struct LMem;
+
+template <class F>
+struct LMem<F, u64> {
+  using E = typename F::E;
+  template <int V>
+  __device__ __forceinline__ static void ld(const u64 *p, int64_t i, E (&o)[V]) {
+#pragma unroll
+    for (int v = 0; v < V; v++) o[v] = F::load(p, 0, i + v);
+  }
+  template <int V>
+  __device__ __forceinline__ static void ldc(const u64 *p, int64_t i, E (&o)[V]) {
+#pragma unroll
+    for (int v = 0; v < V; v++) o[v] = F::load_cached(p, 0, i + v);
+  }
+  __device__ __forceinline__ static E ldc1(const u64 *p, int64_t i) { return F::load_cached(p, 0, i); }
+  __device__ __forceinline__ static void st(u64 *p, int64_t i, E x) { F::store(p, 0, i, x); }
+};
+
+typedef u32 u32x4 __attribute__((ext_vector_type(4)));
+
+template <>
+struct LMem<F32, u32> {
+  using E = F32::E;
+  template <int V>
+  __device__ __forceinline__ static void ld(const u32 *p, int64_t i, E (&o)[V]) {
+    if constexpr (V == 4) {
+      const u32x4 w = __builtin_nontemporal_load((const u32x4 *)(p + i));
+      o[0] = {w.x}, o[1] = {w.y}, o[2] = {w.z}, o[3] = {w.w};
+    } else {
+#pragma unroll
+      for (int v = 0; v < V; v++) o[v] = {__builtin_nontemporal_load(p + i + v)};
+    }
+  }
+  template <int V>
+  __device__ __forceinline__ static void ldc(const u32 *p, int64_t i, E (&o)[V]) {
+    if constexpr (V == 4) {
+      const u32x4 w = *(const u32x4 *)(p + i);
+      o[0] = {w.x}, o[1] = {w.y}, o[2] = {w.z}, o[3] = {w.w};
+    } else {
+#pragma unroll
+      for (int v = 0; v < V; v++) o[v] = {p[i + v]};
+    }
+  }
+  __device__ __forceinline__ static E ldc1(const u32 *p, int64_t i) { return {p[i]}; }
+  __device__ __forceinline__ static void st(u32 *p, int64_t i, E x) { __builtin_nontemporal_store(x.v, p + i); }
+};
+
+template <class F, int N, class Wt>
 struct LayerArgs {
-  SV W, x, b, A, B, C, y;  // W, A: dout*din; x: din; B: n_tiles*din; b, C, y: dout (one limb)
+  SVW<Wt> W, x, b, A, B, C, y;  // W, A: dout*din; x: din; B: n_tiles*din; b, C, y: dout (one limb)
   int64_t dout, din, tile_rows, n_tiles;
-  u64 *E;      // opened E_t at t*din + k
-  u64 *D_pub;  // nullable: opened D at r*din + k
+  Wt *E;      // opened E_t at t*din + k
+  Wt *D_pub;  // nullable: opened D at r*din + k
   typename F::E alpha[N];
   u64 coef_state;
   int64_t j0;  // log index of D_0[0, 0]
@@ -49,9 +112,10 @@ __host__ __device__ __forceinline__ int64_t tile_base(int64_t t, int64_t tile_ro
 
 // E_t = sum_i (x_i - B_t,i) for every tile; element e = t din + k sits at log index
 // j0 + base_t + rows_t din + k
-template <class F, int N>
-__global__ __launch_bounds__(BLOCK) void k_ll_open_e(const LayerArgs<F, N> A) {
+template <class F, int N, class Wt>
+__global__ __launch_bounds__(BLOCK) void k_ll_open_e(const LayerArgs<F, N, Wt> A) {
   using E = typename F::E;
+  using M = LMem<F, Wt>;
   E mc[N + 1];
 #pragma unroll
   for (int k = 0; k <= N; k++) mc[k] = F::zero();
@@ -62,11 +126,14 @@ __global__ __launch_bounds__(BLOCK) void k_ll_open_e(const LayerArgs<F, N> A) {
     E s = F::zero(), m[N];
 #pragma unroll
     for (int i = 0; i < N; i++) {
-      const E v = F::sub(F::load_cached(A.x.val + i * A.x.ps, 0, k), F::load(A.B.val + i * A.B.ps, 0, e));
-      m[i] = F::sub(F::load_cached(A.x.mac + i * A.x.ps, 0, k), F::load(A.B.mac + i * A.B.ps, 0, e));
+      E bv[1], bm[1];
+      M::template ld<1>(A.B.val + i * A.B.ps, e, bv);
+      M::template ld<1>(A.B.mac + i * A.B.ps, e, bm);
+      const E v = F::sub(M::ldc1(A.x.val + i * A.x.ps, k), bv[0]);
+      m[i] = F::sub(M::ldc1(A.x.mac + i * A.x.ps, k), bm[0]);
       s = F::add(s, v);
     }
-    F::store(A.E, 0, e, s);
+    M::st(A.E, e, s);
     const E r = uniform_elem<F>(A.coef_state, (u64)(A.j0 + tile_base(t, A.tile_rows, A.din) + rows * A.din + k));
     mc[0] = F::add(mc[0], F::mul(r, s));
 #pragma unroll
@@ -83,17 +150,19 @@ __device__ __forceinline__ typename F::E wave_sum(typename F::E v) {
 }
 
 // one block per group of up to R consecutive rows of one tile (grid-stride over the groups),
-// the rows' elements strided by the block size: each element's E_t and B_t words are read
-// once for the R rows; at the end of a group the R (2 N + 1) row sums go through wave
-// shuffles and LDS
-template <class F, int N, int R>
-__global__ __launch_bounds__(BLOCK) void k_ll_rows(const LayerArgs<F, N> A) {
+// the rows' elements strided by the block size, V consecutive elements per lane (V = 4 needs
+// din, the party strides and the base addresses to be multiples of 4 words): each element's
+// E_t and B_t words are read once for the R rows; at the end of a group the R (2 N + 1) row
+// sums go through wave shuffles and LDS
+template <class F, int N, int R, class Wt, int V>
+__global__ __launch_bounds__(BLOCK) void k_ll_rows(const LayerArgs<F, N, Wt> A) {
   using E = typename F::E;
   using Wd = typename F::Wide;
+  using M = LMem<F, Wt>;
   constexpr int K = 2 * N + 1;  // row sums: D E, then D B_i + A_i E, then the MAC versions
-  // a row-sum accumulator takes two products per element, a MAC-check one takes 2 R
+  // per element a row-sum accumulator takes two products, a MAC-check one takes 2 R
   constexpr int64_t CHUNK = (int64_t)BLOCK * (F::WIDE_TERMS / (2 * R));
-  static_assert(F::WIDE_TERMS >= 2 * R, "wide accumulators too narrow for R rows");
+  static_assert(F::WIDE_TERMS >= 2 * R * V, "wide accumulators too narrow for R rows");
   __shared__ E part[WAVES][R][K];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   E mc[N + 1];
@@ -133,38 +202,43 @@ __global__ __launch_bounds__(BLOCK) void k_ll_rows(const LayerArgs<F, N> A) {
 #pragma unroll
       for (int i = 0; i <= N; i++) wmc[i] = F::wzero();
       const int64_t kend = min(A.din, k0 + CHUNK);
-      for (int64_t k = k0 + threadIdx.x; k < kend; k += BLOCK) {
-        const E ev = F::load_cached(A.E, 0, brow + k);
-        E bv[N], bm[N];
+      for (int64_t k = k0 + (int64_t)threadIdx.x * V; k < kend; k += (int64_t)BLOCK * V) {
+        E ev[V], bv[N][V], bm[N][V];
+        M::template ldc<V>(A.E, brow + k, ev);
 #pragma unroll
         for (int i = 0; i < N; i++) {
-          bv[i] = F::load_cached(A.B.val + i * A.B.ps, 0, brow + k);
-          bm[i] = F::load_cached(A.B.mac + i * A.B.ps, 0, brow + k);
+          M::template ldc<V>(A.B.val + i * A.B.ps, brow + k, bv[i]);
+          M::template ldc<V>(A.B.mac + i * A.B.ps, brow + k, bm[i]);
         }
 #pragma unroll
         for (int q = 0; q < R; q++) {
           if (q >= nr) break;
           const int64_t wi = (r0 + q) * A.din + k;
-          E av[N], am[N], wm[N], dv = F::zero();
+          E wv[N][V], wm[N][V], av[N][V], am[N][V];
 #pragma unroll
           for (int i = 0; i < N; i++) {
-            const E wv = F::load(A.W.val + i * A.W.ps, 0, wi);
-            wm[i] = F::load(A.W.mac + i * A.W.ps, 0, wi);
-            av[i] = F::load(A.A.val + i * A.A.ps, 0, wi);
-            am[i] = F::load(A.A.mac + i * A.A.ps, 0, wi);
-            dv = F::add(dv, F::sub(wv, av[i]));
+            M::template ld<V>(A.W.val + i * A.W.ps, wi, wv[i]);
+            M::template ld<V>(A.W.mac + i * A.W.ps, wi, wm[i]);
+            M::template ld<V>(A.A.val + i * A.A.ps, wi, av[i]);
+            M::template ld<V>(A.A.mac + i * A.A.ps, wi, am[i]);
           }
-          if (A.D_pub) F::store(A.D_pub, 0, wi, dv);
-          const E rj = uniform_elem<F>(A.coef_state, (u64)(jrow0 + q * A.din + k));
-          F::wmac(wmc[0], rj, dv);
-          F::wmac(w[q][0], dv, ev);
 #pragma unroll
-          for (int i = 0; i < N; i++) {
-            F::wmac(wmc[1 + i], rj, F::sub(wm[i], am[i]));
-            F::wmac(w[q][1 + i], dv, bv[i]);
-            F::wmac(w[q][1 + i], av[i], ev);
-            F::wmac(w[q][1 + N + i], dv, bm[i]);
-            F::wmac(w[q][1 + N + i], am[i], ev);
+          for (int v = 0; v < V; v++) {
+            E dv = F::zero();
+#pragma unroll
+            for (int i = 0; i < N; i++) dv = F::add(dv, F::sub(wv[i][v], av[i][v]));
+            if (A.D_pub) M::st(A.D_pub, wi + v, dv);
+            const E rj = uniform_elem<F>(A.coef_state, (u64)(jrow0 + q * A.din + k + v));
+            F::wmac(wmc[0], rj, dv);
+            F::wmac(w[q][0], dv, ev[v]);
+#pragma unroll
+            for (int i = 0; i < N; i++) {
+              F::wmac(wmc[1 + i], rj, F::sub(wm[i][v], am[i][v]));
+              F::wmac(w[q][1 + i], dv, bv[i][v]);
+              F::wmac(w[q][1 + i], av[i][v], ev[v]);
+              F::wmac(w[q][1 + N + i], dv, bm[i][v]);
+              F::wmac(w[q][1 + N + i], am[i][v], ev[v]);
+            }
           }
         }
       }
@@ -196,16 +270,16 @@ __global__ __launch_bounds__(BLOCK) void k_ll_rows(const LayerArgs<F, N> A) {
         zv = F::add(zv, part[w][q][1 + i]);
         zm = F::add(zm, part[w][q][1 + N + i]);
       }
-      E v = F::add(F::add(F::load_cached(A.C.val + i * A.C.ps, 0, r), zv), F::load_cached(A.b.val + i * A.b.ps, 0, r));
+      E v = F::add(F::add(M::ldc1(A.C.val + i * A.C.ps, r), zv), M::ldc1(A.b.val + i * A.b.ps, r));
       if (i == 0) v = F::add(v, de);
       E al = F::zero();
 #pragma unroll
       for (int p = 0; p < N; p++)  // constant indices into the argument block
         if (p == i) al = A.alpha[p];
-      const E m = F::add(F::add(F::load_cached(A.C.mac + i * A.C.ps, 0, r), zm),
-                         F::add(F::mul(al, de), F::load_cached(A.b.mac + i * A.b.ps, 0, r)));
-      F::store(A.y.val + i * A.y.ps, 0, r, v);
-      F::store(A.y.mac + i * A.y.ps, 0, r, m);
+      const E m = F::add(F::add(M::ldc1(A.C.mac + i * A.C.ps, r), zm),
+                         F::add(F::mul(al, de), M::ldc1(A.b.mac + i * A.b.ps, r)));
+      M::st(A.y.val + i * A.y.ps, r, v);
+      M::st(A.y.mac + i * A.y.ps, r, m);
     }
     __syncthreads();  // part is reused by the next group
   }
@@ -271,6 +345,53 @@ u64 *noalloc_scratch(int device) {
   return scratch_ptr[device];
 }
 
+// both storage forms: the launch sequence of one layer (E_t opened, then the row kernel)
+template <class F, int N, class Wt>
+static spdz_status layer_launch(spdz_ctx *c, LayerArgs<F, N, Wt> &A, bool vec4) {
+  int g = grid_for(c, (const void *)k_ll_open_e<F, N, Wt>, A.n_tiles * A.din);
+  {
+    KTimer tm(c, "layer_open_e");
+    hipLaunchKernelGGL((k_ll_open_e<F, N, Wt>), dim3(g), dim3(BLOCK), 0, c->stream, A);
+  }
+  SPDZ_RET(hip_status(hipGetLastError()));
+  if (g > c->slots) c->slots = g;
+  // one block per group of one or two rows of a tile
+  const int rpb = ll_rows_per_block(A.dout, A.tile_rows);
+  const int64_t groups = A.n_tiles * ((A.tile_rows + rpb - 1) / rpb);
+  auto go = [&](auto rr, auto vv) -> spdz_status {
+    constexpr int R = decltype(rr)::value, V = decltype(vv)::value;
+    const void *krow = (const void *)k_ll_rows<F, N, R, Wt, V>;
+    g = grid_for(c, krow, groups, BLOCK, 1);
+    if (g >= 8) g -= g % 8;  // a multiple of the XCD count enables the XCD-aware group order
+    {
+      KTimer tm(c, sizeof(Wt) == 4 ? "layer_rows_u32" : "layer_rows");
+      hipLaunchKernelGGL((k_ll_rows<F, N, R, Wt, V>), dim3(g), dim3(BLOCK), 0, c->stream, A);
+    }
+    return hip_status(hipGetLastError());
+  };
+  using I1 = std::integral_constant<int, 1>;
+  using I2 = std::integral_constant<int, 2>;
+  using I4 = std::integral_constant<int, 4>;
+  spdz_status st;
+  if constexpr (sizeof(Wt) == 4) {
+    if (vec4)
+      st = rpb == 2 ? go(I2{}, I4{}) : go(I1{}, I4{});
+    else
+      st = rpb == 2 ? go(I2{}, I1{}) : go(I1{}, I1{});
+  } else {
+    st = rpb == 2 ? go(I2{}, I1{}) : go(I1{}, I1{});
+  }
+  SPDZ_RET(st);
+  if (g > c->slots) c->slots = g;
+  c->log_count += A.dout * A.din + A.n_tiles * A.din;
+  return SPDZ_OK;
+}
+
+template <class Wt>
+static SVW<Wt> svw(Wt *val, Wt *mac, int64_t ps) {
+  return SVW<Wt>{val, mac, ps};
+}
+
 spdz_status launch_linear_layer(spdz_ctx *c, int64_t dout, int64_t din, int64_t tile_rows, const spdz_shares *W,
                                 const spdz_shares *x, const spdz_shares *b, const spdz_triple *T, spdz_shares *y,
                                 u64 *D_pub, u64 *E_pub, u64 *E_scratch) {
@@ -283,14 +404,15 @@ spdz_status launch_linear_layer(spdz_ctx *c, int64_t dout, int64_t din, int64_t 
   return visit_single_limb(c, [&](auto f, auto nn) -> spdz_status {
     using F = decltype(f);
     constexpr int N = decltype(nn)::value;
-    LayerArgs<F, N> A;
-    A.W = sv_of(W);
-    A.x = sv_of(x);
-    A.b = sv_of(b);
-    A.A = sv_of(&T->a);
-    A.B = sv_of(&T->b);
-    A.C = sv_of(&T->c);
-    A.y = sv_of(y);
+    auto sv = [](const spdz_shares *s) { return svw<u64>(s->val, s->mac, s->party_stride); };
+    LayerArgs<F, N, u64> A;
+    A.W = sv(W);
+    A.x = sv(x);
+    A.b = sv(b);
+    A.A = sv(&T->a);
+    A.B = sv(&T->b);
+    A.C = sv(&T->c);
+    A.y = sv(y);
     A.dout = dout;
     A.din = din;
     A.tile_rows = tile_rows;
@@ -301,30 +423,48 @@ spdz_status launch_linear_layer(spdz_ctx *c, int64_t dout, int64_t din, int64_t 
     A.coef_state = coef_state(c);
     A.j0 = c->log_count;
     A.acc = c->d_acc;
-    int g = grid_for(c, (const void *)k_ll_open_e<F, N>, n_tiles * din);
-    {
-      KTimer tm(c, "layer_open_e");
-      hipLaunchKernelGGL((k_ll_open_e<F, N>), dim3(g), dim3(BLOCK), 0, c->stream, A);
-    }
-    SPDZ_RET(hip_status(hipGetLastError()));
-    if (g > c->slots) c->slots = g;
-    // one block per group of one or two rows of a tile
-    const int rpb = ll_rows_per_block(dout, tile_rows);
-    const int64_t groups = n_tiles * ((tile_rows + rpb - 1) / rpb);
-    const void *krow = rpb == 2 ? (const void *)k_ll_rows<F, N, 2> : (const void *)k_ll_rows<F, N, 1>;
-    g = grid_for(c, krow, groups, BLOCK, 1);
-    if (g >= 8) g -= g % 8;  // a multiple of the XCD count enables the XCD-aware group order
-    {
-      KTimer tm(c, "layer_rows");
-      if (rpb == 2)
-        hipLaunchKernelGGL((k_ll_rows<F, N, 2>), dim3(g), dim3(BLOCK), 0, c->stream, A);
-      else
-        hipLaunchKernelGGL((k_ll_rows<F, N, 1>), dim3(g), dim3(BLOCK), 0, c->stream, A);
-    }
-    SPDZ_RET(hip_status(hipGetLastError()));
-    if (g > c->slots) c->slots = g;
-    c->log_count += dout * din + n_tiles * din;
-    return SPDZ_OK;
+    return layer_launch<F, N, u64>(c, A, false);
+  });
+}
+
+spdz_status launch_linear_layer32(spdz_ctx *c, int64_t dout, int64_t din, int64_t tile_rows, const spdz_shares32 *W,
+                                  const spdz_shares32 *x, const spdz_shares32 *b, const spdz_triple32 *T,
+                                  spdz_shares32 *y, u32 *D_pub, u32 *E_pub) {
+  if (c->fid != FID_32) return SPDZ_E_UNSUPPORTED;
+  const int64_t n_tiles = (dout + tile_rows - 1) / tile_rows;
+  u32 *Ebuf = E_pub;
+  if (!Ebuf) {
+    SPDZ_RET(ensure_ws(c, (size_t)(n_tiles * din) * 4));
+    Ebuf = (u32 *)c->ws;
+  }
+  // four elements per lane where every row, party plane and base address is 16-byte aligned
+  auto al4 = [](const void *p) { return ((uintptr_t)p & 15) == 0; };
+  bool vec4 = din % 4 == 0 && al4(Ebuf) && (!D_pub || al4(D_pub));
+  for (const spdz_shares32 *s : {W, &T->a, &T->b})
+    vec4 = vec4 && al4(s->val) && al4(s->mac) && s->party_stride % 4 == 0;
+  return visit_n<F32>(c->n, [&](auto f, auto nn) -> spdz_status {
+    using F = decltype(f);
+    constexpr int N = decltype(nn)::value;
+    auto sv = [](const spdz_shares32 *s) { return svw<u32>(s->val, s->mac, s->party_stride); };
+    LayerArgs<F, N, u32> A;
+    A.W = sv(W);
+    A.x = sv(x);
+    A.b = sv(b);
+    A.A = sv(&T->a);
+    A.B = sv(&T->b);
+    A.C = sv(&T->c);
+    A.y = sv(y);
+    A.dout = dout;
+    A.din = din;
+    A.tile_rows = tile_rows;
+    A.n_tiles = n_tiles;
+    A.E = Ebuf;
+    A.D_pub = D_pub;
+    alpha_of<F, N>(c, A.alpha);
+    A.coef_state = coef_state(c);
+    A.j0 = c->log_count;
+    A.acc = c->d_acc;
+    return layer_launch<F, N, u32>(c, A, vec4);
   });
 }
 

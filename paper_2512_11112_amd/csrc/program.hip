@@ -883,7 +883,7 @@ spdz_status issue(spdz_prog *g, PNode &n) {
           st = node_triple(g, n, t);
           c->log_count = n.log_off;
           if (st == SPDZ_OK)
-            st = launch_beaver(c, &a.sh, &b.sh, t, &n.sh, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+            st = launch_beaver(c, &a.sh, &b.sh, t, &n.sh, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
           g->launches += 1;
         } else {
           const spdz_shares terms[2] = {a.sh, b.sh};

@@ -40,6 +40,15 @@ class Triple(ctypes.Structure):
     _fields_ = [("a", Shares), ("b", Shares), ("c", Shares)]
 
 
+class Shares32(ctypes.Structure):
+    _fields_ = [("val", ctypes.c_void_p), ("mac", ctypes.c_void_p), ("len", ctypes.c_int64),
+                ("party_stride", ctypes.c_int64)]
+
+
+class Triple32(ctypes.Structure):
+    _fields_ = [("a", Shares32), ("b", Shares32), ("c", Shares32)]
+
+
 u64p = ctypes.POINTER(ctypes.c_uint64)
 _lib = None
 
@@ -63,7 +72,7 @@ def lib() -> ctypes.CDLL:
                                      ctypes.POINTER(Triple), ctypes.POINTER(Shares), vp, vp]),
             "spdz_mul_fused": (i32, [vp, ctypes.POINTER(Shares), ctypes.POINTER(Shares),
                                      ctypes.POINTER(Triple), ctypes.POINTER(Shares), vp, vp, u64p,
-                                     ctypes.POINTER(Shares), vp, ctypes.POINTER(Shares)]),
+                                     ctypes.POINTER(Shares), vp, ctypes.POINTER(Shares), vp]),
             "spdz_linear": (i32, [vp, i32, ctypes.POINTER(Shares), u64p, u64p, ctypes.POINTER(Shares)]),
             "spdz_reduce_add": (i32, [vp, ctypes.POINTER(Shares), ctypes.POINTER(Shares)]),
             "spdz_mac_check": (i32, [vp, ctypes.POINTER(i32), u64p]),
@@ -76,6 +85,9 @@ def lib() -> ctypes.CDLL:
             "spdz_linear_layer": (i32, [vp, i64, i64, i64, ctypes.POINTER(Shares), ctypes.POINTER(Shares),
                                         ctypes.POINTER(Shares), ctypes.POINTER(Triple), ctypes.POINTER(Shares),
                                         vp, vp]),
+            "spdz_linear_layer32": (i32, [vp, i64, i64, i64, ctypes.POINTER(Shares32), ctypes.POINTER(Shares32),
+                                          ctypes.POINTER(Shares32), ctypes.POINTER(Triple32),
+                                          ctypes.POINTER(Shares32), vp, vp]),
             "spdz_linear_layer_noalloc": (i32, [vp, i64, i64, i64, ctypes.POINTER(Shares), ctypes.POINTER(Shares),
                                                 ctypes.POINTER(Shares), ctypes.POINTER(Triple),
                                                 ctypes.POINTER(Shares), vp, vp]),
@@ -203,6 +215,48 @@ class TripleTensor:
         return Triple(self.a.desc(), self.b.desc(), self.c.desc())
 
 
+@dataclass
+class ShareTensor32:
+    """Values and MAC shares of a batch over 2^32 - 5 packed one residue per 32-bit word:
+    device int32 tensors [n][W] holding the raw words (spdz_shares32)."""
+    val: torch.Tensor
+    mac: torch.Tensor
+
+    @staticmethod
+    def empty(n: int, W: int, device="cuda") -> "ShareTensor32":
+        return ShareTensor32(torch.empty((n, W), dtype=torch.int32, device=device),
+                             torch.empty((n, W), dtype=torch.int32, device=device))
+
+    @property
+    def width(self) -> int:
+        return self.val.shape[-1]
+
+    def desc(self) -> Shares32:
+        v, m = self.val, self.mac
+        assert v.is_cuda and m.is_cuda and v.dtype == torch.int32 and v.shape == m.shape and v.dim() == 2
+        if v.numel() == 0:
+            return Shares32(None, None, v.shape[1], 0)
+        assert v.stride() == m.stride() and v.stride(1) == 1
+        return Shares32(v.data_ptr(), m.data_ptr(), v.shape[1], v.stride(0))
+
+
+@dataclass
+class TripleTensor32:
+    a: ShareTensor32
+    b: ShareTensor32
+    c: ShareTensor32
+
+    @staticmethod
+    def empty_layer(n, dout, din, tile_rows, device="cuda") -> "TripleTensor32":
+        """Matrix-vector triples of a linear layer, packed: A [dout*din], B [n_tiles*din], C [dout]."""
+        n_tiles = -(-dout // tile_rows)
+        return TripleTensor32(ShareTensor32.empty(n, dout * din, device), ShareTensor32.empty(n, n_tiles * din, device),
+                              ShareTensor32.empty(n, dout, device))
+
+    def desc(self) -> Triple32:
+        return Triple32(self.a.desc(), self.b.desc(), self.c.desc())
+
+
 def spdz_copy_probe(dst: torch.Tensor, src: torch.Tensor, stream=None):
     """Plain device copy of src into dst (int64 tensors of equal size)."""
     assert dst.numel() == src.numel() and dst.is_contiguous() and src.is_contiguous()
@@ -282,9 +336,21 @@ class Context:
                                     ctypes.byref(dz), _ptr(d_pub), _ptr(e_pub)), "spdz_mul_batch")
         return z
 
-    def spdz_mul_fused(self, x, y, t, z, d_pub=None, e_pub=None, lin: Optional[Sequence[int]] = None,
-                       w: Optional[ShareTensor] = None, w_pub: Optional[torch.Tensor] = None,
-                       s: Optional[ShareTensor] = None):
+    def bind_mul_batch(self, x: ShareTensor, y: ShareTensor, t: TripleTensor, z: ShareTensor,
+                       d_pub: Optional[torch.Tensor] = None, e_pub: Optional[torch.Tensor] = None):
+        """spdz_mul_batch with its arguments marshalled once (see bind_mul_fused)."""
+        descs = (x.desc(), y.desc(), t.desc(), z.desc())
+        args = (self._h, *(ctypes.byref(d) for d in descs), _ptr(d_pub), _ptr(e_pub))
+        fn = lib().spdz_mul_batch
+
+        def call():
+            st = fn(*args)
+            if st != SPDZ_OK:
+                raise SpdzError(st, "spdz_mul_batch")
+        call._keep = (descs, (x, y, t, z, d_pub, e_pub))
+        return call
+
+    def _mul_fused_args(self, x, y, t, z, d_pub, e_pub, lin, w, w_pub, s, s_pub):
         dx, dy, dt, dz = x.desc(), y.desc(), t.desc(), z.desc()
         lin_arr = None
         if lin is not None:
@@ -294,10 +360,31 @@ class Context:
                     lin_arr[k * self.L + l] = (c >> (64 * l)) & ((1 << 64) - 1)
         dw = w.desc() if w is not None else None
         ds = s.desc() if s is not None else None
-        _check(lib().spdz_mul_fused(self._h, ctypes.byref(dx), ctypes.byref(dy), ctypes.byref(dt),
-                                    ctypes.byref(dz), _ptr(d_pub), _ptr(e_pub), lin_arr,
-                                    ctypes.byref(dw) if dw is not None else None, _ptr(w_pub),
-                                    ctypes.byref(ds) if ds is not None else None), "spdz_mul_fused")
+        return (self._h, ctypes.byref(dx), ctypes.byref(dy), ctypes.byref(dt), ctypes.byref(dz), _ptr(d_pub),
+                _ptr(e_pub), lin_arr, ctypes.byref(dw) if dw is not None else None, _ptr(w_pub),
+                ctypes.byref(ds) if ds is not None else None, _ptr(s_pub)), (dx, dy, dt, dz, dw, ds, lin_arr)
+
+    def spdz_mul_fused(self, x, y, t, z, d_pub=None, e_pub=None, lin: Optional[Sequence[int]] = None,
+                       w: Optional[ShareTensor] = None, w_pub: Optional[torch.Tensor] = None,
+                       s: Optional[ShareTensor] = None, s_pub: Optional[torch.Tensor] = None):
+        args, _keep = self._mul_fused_args(x, y, t, z, d_pub, e_pub, lin, w, w_pub, s, s_pub)
+        _check(lib().spdz_mul_fused(*args), "spdz_mul_fused")
+
+    def bind_mul_fused(self, x, y, t, z, d_pub=None, e_pub=None, lin: Optional[Sequence[int]] = None,
+                       w: Optional[ShareTensor] = None, w_pub: Optional[torch.Tensor] = None,
+                       s: Optional[ShareTensor] = None, s_pub: Optional[torch.Tensor] = None):
+        """spdz_mul_fused with its arguments marshalled once: returns a call without arguments
+        that enqueues the same operation (the tensors must stay alive and in place)."""
+        args, keep = self._mul_fused_args(x, y, t, z, d_pub, e_pub, lin, w, w_pub, s, s_pub)
+        fn = lib().spdz_mul_fused
+        tensors = (x, y, t, z, d_pub, e_pub, w, w_pub, s, s_pub)
+
+        def call():
+            st = fn(*args)
+            if st != SPDZ_OK:
+                raise SpdzError(st, "spdz_mul_fused")
+        call._keep = (keep, tensors)
+        return call
 
     def spdz_linear(self, terms: Sequence[ShareTensor], coeffs: Sequence[int], c0: int = 0,
                     out: Optional[ShareTensor] = None) -> ShareTensor:
@@ -341,6 +428,19 @@ class Context:
                                        _ptr(E_pub)), "spdz_linear_layer")
         return y
 
+    def spdz_linear_layer32(self, dout: int, din: int, tile_rows: int, W: ShareTensor32, x: ShareTensor32,
+                            b: ShareTensor32, T: TripleTensor32, y: Optional[ShareTensor32] = None,
+                            D_pub: Optional[torch.Tensor] = None,
+                            E_pub: Optional[torch.Tensor] = None) -> ShareTensor32:
+        """spdz_linear_layer on residues of 2^32 - 5 packed in 32-bit words (int32 tensors [n][len];
+        D_pub [dout*din] and E_pub [n_tiles*din] int32)."""
+        y = ShareTensor32.empty(self.n, dout) if y is None else y
+        dW, dx, db, dt, dy = W.desc(), x.desc(), b.desc(), T.desc(), y.desc()
+        _check(lib().spdz_linear_layer32(self._h, dout, din, tile_rows, ctypes.byref(dW), ctypes.byref(dx),
+                                         ctypes.byref(db), ctypes.byref(dt), ctypes.byref(dy), _ptr(D_pub),
+                                         _ptr(E_pub)), "spdz_linear_layer32")
+        return y
+
     def spdz_linear_layer_noalloc(self, dout: int, din: int, tile_rows: int, W: ShareTensor, x: ShareTensor,
                                   b: ShareTensor, T: TripleTensor, y: ShareTensor,
                                   D_pub: Optional[torch.Tensor] = None,
@@ -360,6 +460,21 @@ class Context:
         s = _check(lib().spdz_mac_check(self._h, ctypes.byref(acc), sig), "spdz_mac_check")
         sigma = [sum(int(sig[i * self.L + l]) << (64 * l) for l in range(self.L)) for i in range(self.n)]
         return bool(acc.value) and s == SPDZ_OK, sigma
+
+    def bind_mac_check(self):
+        """spdz_mac_check with its output buffers made once: returns a call without arguments that
+        returns the verdict (sigma stays in the bound buffer)."""
+        acc = ctypes.c_int(0)
+        sig = (ctypes.c_uint64 * (self.n * self.L))()
+        fn, h, pacc = lib().spdz_mac_check, self._h, ctypes.byref(acc)
+
+        def call() -> bool:
+            st = fn(h, pacc, sig)
+            if st not in (SPDZ_OK, SPDZ_MAC_REJECT):
+                raise SpdzError(st, "spdz_mac_check")
+            return st == SPDZ_OK and bool(acc.value)
+        call._keep = (acc, sig)
+        return call
 
     # -- measurement ------------------------------------------------------------
     def spdz_timing_enable(self, enable: bool = True):

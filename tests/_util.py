@@ -27,6 +27,32 @@ def triple_to_dev(t: F.TripleArr):
     return TripleTensor(share_to_dev(t.a), share_to_dev(t.b), share_to_dev(t.c))
 
 
+def share_to_dev32(s: F.Shares, pad: int = 0):
+    """Single-limb shares of residues below 2^32 -> packed 32-bit device shares [n][len]; with pad > 0
+    every party plane starts pad words into a larger buffer (a layout the 16-byte path cannot take)."""
+    from paper_2512_11112_amd.spdz import ShareTensor32
+
+    def pack(a):
+        assert a.shape[1] == 1 and int(a.max(initial=0)) < (1 << 32)
+        w = a[:, 0, :].astype(np.uint32).view(np.int32)
+        if pad:
+            buf = np.zeros((w.shape[0], w.shape[1] + pad), dtype=np.int32)
+            buf[:, pad:] = w
+            return torch.from_numpy(buf).cuda()[:, pad:]
+        return torch.from_numpy(np.ascontiguousarray(w)).cuda()
+    return ShareTensor32(pack(s.val), pack(s.mac))
+
+
+def triple_to_dev32(t: F.TripleArr, pad: int = 0):
+    from paper_2512_11112_amd.spdz import TripleTensor32
+    return TripleTensor32(share_to_dev32(t.a, pad), share_to_dev32(t.b, pad), share_to_dev32(t.c, pad))
+
+
+def host32(t: torch.Tensor) -> np.ndarray:
+    """int32 device words -> uint64 numpy holding the same residues."""
+    return t.detach().cpu().numpy().view(np.uint32).astype(np.uint64)
+
+
 def ints_of_sigma(sig: np.ndarray):
     """oracle sigma [n][L] -> list of ints"""
     return [sum(int(sig[i, l]) << (64 * l) for l in range(sig.shape[1])) for i in range(sig.shape[0])]

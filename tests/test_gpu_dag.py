@@ -126,6 +126,8 @@ class ArenaCheck:
                     np.array_equal(m[o:o + self.n * w].reshape(self.n, 1, w), z.mac)):
                 self.bad.append((name, node))
         self.seen += 1
+        if self.seen % 10000 == 0:
+            print(f"oracle: {self.seen} nodes compared", flush=True)
 
 
 def arena_host(g):

@@ -127,18 +127,21 @@ def test_linear_aliasing_output():
 
 
 # --------------------------------------------------------------------------
-def run_fused(D, check_seed, lin=None, with_pub=True):
+def run_fused(D, check_seed, lin=None, with_pub=True, open_s_in_kernel=True, ctx=None):
+    """The pipeline; s opened by the fused kernel's last block (s_pub) or by a separate spdz_open."""
     from paper_2512_11112_amd.spdz import ShareTensor
     n, L, W = D.n, D.f.L, D.x.width
-    ctx = make_ctx(D, check_seed)
+    ctx = make_ctx(D, check_seed) if ctx is None else ctx
     lin = lin if lin is not None else (1, 3, D.f.p - 1, 0)
     z, w, s = ShareTensor.empty(n, L, W), ShareTensor.empty(n, L, W), ShareTensor.empty(n, L, 1)
     dp = ctx.new_public(W) if with_pub else None
     ep = ctx.new_public(W) if with_pub else None
     wp = ctx.new_public(W)
+    sp = ctx.new_public(1) if open_s_in_kernel else None
     ctx.spdz_mul_fused(share_to_dev(D.x), share_to_dev(D.y), triple_to_dev(D.t), z, dp, ep,
-                       lin=lin, w=w, w_pub=wp, s=s)
-    sp = ctx.spdz_open(s)
+                       lin=lin, w=w, w_pub=wp, s=s, s_pub=sp)
+    if not open_s_in_kernel:
+        sp = ctx.spdz_open(s)
     assert ctx.opened_count() == 3 * W + 1
     ok, sigma = ctx.spdz_mac_check()
     return ctx, dict(z=z, w=w, s=s, d=dp, e=ep, wpub=wp, spub=sp, ok=ok, sigma=sigma)
@@ -158,14 +161,29 @@ def check_fused(got, ref):
 
 
 @pytest.mark.parametrize("p,n,W", [(P127, 3, (1 << 16) + 5), (P61, 2, 100001), (P127, 2, 3),
-                                   (P61, 4, 12345), (P_PAPER, 2, 100001), (P_PAPER, 3, 777)])
-def test_fused_pipeline(p, n, W):
-    print(f"case p-bits={p.bit_length()} n={n} W={W}", flush=True)
+                                   (P61, 4, 12345), (P_PAPER, 2, 100001), (P_PAPER, 3, 777), (P61, 8, 1)])
+@pytest.mark.parametrize("open_s_in_kernel", [True, False])
+def test_fused_pipeline(p, n, W, open_s_in_kernel):
+    print(f"case p-bits={p.bit_length()} n={n} W={W} open_s_in_kernel={open_s_in_kernel}", flush=True)
     D = deal_elementwise(p, n, W, 4)
     ref = pipeline_run(D, check_seed=4)
-    _, got = run_fused(D, 4)
+    _, got = run_fused(D, 4, open_s_in_kernel=open_s_in_kernel)
     check_fused(got, ref)
     assert got["ok"]
+
+
+def test_fused_pipeline_repeated_launches():
+    """The fused kernel's finished-block counter returns to zero after every launch: ten pipelines
+    in a row on one context (widths, hence grids, change between launches) each match the
+    oracle, MAC check number k against the oracle's check k."""
+    p, n, seed = P61, 3, 40
+    ctx = None
+    for rep, W in enumerate((300001, 65536, 4099, 1000, 257, 256, 3, 70000, 1, 99999)):
+        D = deal_elementwise(p, n, W, seed)   # same seed: the same alpha, prefixes of the same values
+        ref = pipeline_run(D, check_seed=seed, epoch=rep)
+        ctx = make_ctx(D, seed) if ctx is None else ctx
+        _, got = run_fused(D, seed, ctx=ctx, open_s_in_kernel=rep % 2 == 0)
+        check_fused(got, ref)
 
 
 @pytest.mark.parametrize("p", [P127, P61, P_PAPER])
