@@ -435,6 +435,19 @@ spdz_status spdz_timing_get(spdz_ctx *ctx, const char *kernel, double *total_ms,
  * must not overlap. */
 spdz_status spdz_copy_probe(uint64_t *dst, const uint64_t *src, int64_t words, void *hip_stream);
 
+/* Memory-pattern probe (measurement only): `reads` streams of `words` 64-bit
+ * words are read and `writes` streams written, stream k of the inputs at
+ * in + k * stride and of the outputs at out + k * stride (device memory,
+ * caller-owned, stride >= words); each element's words are all loaded before
+ * its stores.  Patterns built: (1,0) read-only, (0,1) write-only, (1,1) copy,
+ * (2,1) two-read-one-write triad, (20,4) and (60,30), the element-wise Beaver
+ * product's and the fused pipeline's stream counts at 2 parties / one limb and
+ * 3 parties / two limbs; others return SPDZ_E_UNSUPPORTED.  blocks_per_cu = 0
+ * fills the occupancy, else that many 256-thread blocks per compute unit (the
+ * Beaver kernels run 2).  Asynchronous on hip_stream. */
+spdz_status spdz_stream_probe(int reads, int writes, const uint64_t *in, uint64_t *out, int64_t stride,
+                              int64_t words, int blocks_per_cu, void *hip_stream);
+
 /* ---------------------------------------------------------------------- */
 /* Programs with control flow (Sec. III-B/C): a data-flow graph per basic   */
 /* block plus the control-flow graph, run by the non-blocking scheduler of  */

@@ -3,6 +3,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <chrono>
 #include <initializer_list>
 #include <new>
 #include <utility>
@@ -60,6 +61,19 @@ bool overlaps(const spdz_ctx *c, const spdz_shares *a, const spdz_shares *b) {
       if (alo < bhi && blo < ahi) return true;
     }
   return false;
+}
+
+// polls a word of pinned host memory that a kernel stores with system-scope release until it
+// reads seq (true), for at most POLL_US microseconds (false)
+constexpr double POLL_US = 2000.0;
+bool wait_flag(const u64 *flag, u64 seq) {
+  const auto t0 = std::chrono::steady_clock::now();
+  for (int k = 0;; k++) {
+    if (__atomic_load_n(flag, __ATOMIC_ACQUIRE) == seq) return true;
+    if ((k & 255) == 255 &&
+        std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count() > POLL_US)
+      return false;
+  }
 }
 
 #define SPDZ_CHECK(expr)                     \
@@ -147,7 +161,7 @@ spdz_status spdz_ctx_create(spdz_ctx **out, int n_parties, const uint64_t *p_lim
   const size_t red_words = (size_t)MAX_SLOTS * 2 * n_parties * n_limbs;
   if (hipMalloc((void **)&c->d_acc, acc_words * 8) != hipSuccess ||
       hipMalloc((void **)&c->d_red, red_words * 8) != hipSuccess ||
-      hipHostMalloc((void **)&c->h_sigma, (size_t)(n_parties + 1) * n_limbs * 8,
+      hipHostMalloc((void **)&c->h_sigma, (size_t)(2 * (MAX_PARTIES + 1) + 1) * 8,
                     hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
       hipHostGetDevicePointer((void **)&c->d_sigma, c->h_sigma, 0) != hipSuccess ||
       hipMalloc((void **)&c->d_count, 256) != hipSuccess ||
@@ -156,6 +170,7 @@ spdz_status spdz_ctx_create(spdz_ctx **out, int n_parties, const uint64_t *p_lim
     spdz_ctx_destroy(c);
     return SPDZ_E_NOMEM;
   }
+  memset(c->h_sigma, 0, (size_t)(2 * (MAX_PARTIES + 1) + 1) * 8);
   if (hipMemset(c->d_acc, 0, acc_words * 8) != hipSuccess || hipMemset(c->d_red, 0, red_words * 8) != hipSuccess ||
       hipMemset(c->d_count, 0, 256) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess) {
@@ -406,9 +421,11 @@ spdz_status spdz_mac_check(spdz_ctx *c, int *accepted, uint64_t *sigma_out) {
   SPDZ_LIVE(c);
   if (!accepted) return SPDZ_E_INVAL;
   *accepted = 0;
-  // the finalisation kernel writes the totals straight into pinned host memory: one wait, no copy
+  // the finalisation kernel writes the totals straight into pinned host memory, then its sequence
+  // number: the host polls that word (for at most POLL_US, then waits on the stream as usual)
   SPDZ_CHECK(launch_maccheck_finalize(c));
-  if (hipStreamSynchronize(c->stream) != hipSuccess) return SPDZ_E_HIP;
+  if (!wait_flag(c->h_sigma + (MAX_PARTIES + 1) * 2, c->fin_seq) && hipStreamSynchronize(c->stream) != hipSuccess)
+    return SPDZ_E_HIP;
   // a = sum_j r_j a_j and G_i = sum_j r_j gamma_i(a_j), device slots plus the CPU back end's sums;
   // sigma_i = G_i - alpha_i a, accept iff sum_i sigma_i = 0
   bool zero;
@@ -480,6 +497,14 @@ spdz_status spdz_copy_probe(uint64_t *dst, const uint64_t *src, int64_t words, v
   if (!dst || !src || words < 0) return SPDZ_E_INVAL;
   if (words == 0) return SPDZ_OK;
   return launch_copy(dst, src, words, (hipStream_t)hip_stream);
+}
+
+spdz_status spdz_stream_probe(int reads, int writes, const uint64_t *in, uint64_t *out, int64_t stride, int64_t words,
+                              int blocks_per_cu, void *hip_stream) {
+  if (reads < 0 || writes < 0 || words < 0 || stride < words || blocks_per_cu < 0 || (reads && !in) || !out)
+    return SPDZ_E_INVAL;
+  if (words == 0) return SPDZ_OK;
+  return launch_streams(reads, writes, in, out, stride, words, blocks_per_cu, (hipStream_t)hip_stream);
 }
 
 // ---------------------------------------------------------------------------

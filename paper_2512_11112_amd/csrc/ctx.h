@@ -51,8 +51,11 @@ struct spdz_ctx {
   int slots = 0;                // accumulator slots in use (= max grid of accumulating kernels)
   spdz::u64 *d_acc = nullptr;   // MAC-check partial sums [MAX_SLOTS][n + 1][L]
   spdz::u64 *d_red = nullptr;   // ReduceAdd partial sums [MAX_SLOTS][2 n][L]
-  spdz::u64 *h_sigma = nullptr; // [n + 1][L] MAC-check totals, pinned host memory the finalisation kernel writes
+  // [n + 1][L] MAC-check totals, then (at word 2 (MAX_PARTIES + 1)) the sequence number of the last
+  // finalisation: pinned, mapped host memory the finalisation kernel writes
+  spdz::u64 *h_sigma = nullptr;
   spdz::u64 *d_sigma = nullptr; // device address of h_sigma
+  spdz::u64 fin_seq = 0;        // finalisations launched
   unsigned *d_count = nullptr;  // blocks finished of the fused Beaver kernel (zero between launches)
   // MAC-check sums contributed by ops that ran on the CPU back end ([0] = A, [1 + i] = G_i), canonical
   spdz::u64 host_acc[spdz::MAX_PARTIES + 1][2] = {};
@@ -181,6 +184,8 @@ spdz_status launch_deal_secret(spdz_ctx *c, u64 seed, u64 array_id, const u64 *v
                                u64 *values_out);
 spdz_status launch_deal_triple(spdz_ctx *c, u64 seed, u64 array_id, spdz_triple *t);
 spdz_status launch_copy(u64 *dst, const u64 *src, int64_t words, hipStream_t stream);
+spdz_status launch_streams(int reads, int writes, const u64 *in, u64 *out, int64_t stride, int64_t words,
+                           int blocks_per_cu, hipStream_t stream);
 // input validation: clear the flag, check share arrays (values and MAC shares, every party and
 // limb) and public vectors [L][len] for words that are not canonical residues, then read the flag
 spdz_status launch_validate_clear(spdz_ctx *c);

@@ -197,6 +197,8 @@ struct FinArgs {
   u64 *acc;
   int nslots;
   u64 *sigma;  // receives the N + 1 totals (device address of pinned host memory)
+  u64 *flag;   // receives seq after the totals (pinned host memory)
+  u64 seq;
 };
 
 template <class F, int N>
@@ -214,12 +216,15 @@ __global__ __launch_bounds__(BLOCK) void k_mac_finalize(const FinArgs<F, N> A) {
       for (int l = 0; l < F::L; l++) p[k * F::L + l] = 0;
     }
   }
-  // totals of the device slots: [0] = sum r a, [1 + i] = sum r gamma_i, stored to pinned host memory
+  // totals of the device slots: [0] = sum r a, [1 + i] = sum r gamma_i, stored to pinned host
+  // memory, then the check's sequence number, which the host polls
   E t = block_sum<F, N + 1>(s);
   if (threadIdx.x <= N) {
     F::to_words(t, A.sigma + threadIdx.x * F::L);
     __threadfence_system();
   }
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(A.flag, A.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // --------------------------------------------------------------------------
@@ -343,6 +348,29 @@ __global__ __launch_bounds__(BLOCK) void k_copy(const u64 *__restrict__ src, u64
   if ((words & 1) && blockIdx.x == 0 && threadIdx.x == 0) dst[words - 1] = src[words - 1];
 }
 
+// --------------------------------------------------------------------------
+// stream-pattern bandwidth probe: R read streams and S write streams of words
+// 8-byte words each, stream k at base + k * stride; each element's R words are
+// loaded before its S words are stored (every word of a stream moves once)
+// --------------------------------------------------------------------------
+template <int R, int S>
+__global__ __launch_bounds__(BLOCK) void k_streams(const u64 *__restrict__ in, u64 *__restrict__ out, int64_t stride,
+                                                   int64_t words) {
+  u64 acc = 0;
+  for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < words; e += (int64_t)gridDim.x * BLOCK) {
+    u64 v[R > 0 ? R : 1];
+#pragma unroll
+    for (int k = 0; k < R; k++) v[k] = __builtin_nontemporal_load(in + k * stride + e);
+    u64 x = e;
+#pragma unroll
+    for (int k = 0; k < R; k++) x ^= v[k];
+#pragma unroll
+    for (int k = 0; k < S; k++) __builtin_nontemporal_store(x + k, out + k * stride + e);
+    acc += x;
+  }
+  if (S == 0 && acc == 1) out[0] = acc;  // keeps the loads of a read-only pattern
+}
+
 // ==========================================================================
 // host launchers
 // ==========================================================================
@@ -405,6 +433,28 @@ spdz_status launch_copy(u64 *dst, const u64 *src, int64_t words, hipStream_t str
   if (g < 1) g = 1;
   hipLaunchKernelGGL(k_copy, dim3((unsigned)g), dim3(BLOCK), 0, stream, src, dst, words);
   return hip_status(hipGetLastError());
+}
+
+spdz_status launch_streams(int reads, int writes, const u64 *in, u64 *out, int64_t stride, int64_t words,
+                           int blocks_per_cu, hipStream_t stream) {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return SPDZ_E_HIP;
+  auto go = [&](auto kern) -> spdz_status {
+    int64_t per_cu = blocks_per_cu > 0 ? blocks_per_cu : occupancy_blocks((const void *)kern);
+    int64_t g = (int64_t)cus * per_cu, need = (words + BLOCK - 1) / BLOCK;
+    if (g > need) g = need;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(kern, dim3((unsigned)g), dim3(BLOCK), 0, stream, in, out, stride, words);
+    return hip_status(hipGetLastError());
+  };
+  if (reads == 1 && writes == 0) return go(k_streams<1, 0>);
+  if (reads == 0 && writes == 1) return go(k_streams<0, 1>);
+  if (reads == 1 && writes == 1) return go(k_streams<1, 1>);
+  if (reads == 2 && writes == 1) return go(k_streams<2, 1>);
+  if (reads == 20 && writes == 4) return go(k_streams<20, 4>);
+  if (reads == 60 && writes == 30) return go(k_streams<60, 30>);
+  return SPDZ_E_UNSUPPORTED;
 }
 
 spdz_status launch_validate_clear(spdz_ctx *c) {
@@ -568,7 +618,8 @@ spdz_status launch_maccheck_finalize(spdz_ctx *c) {
     A.acc = c->d_acc;
     A.nslots = c->slots;
     A.sigma = c->d_sigma;
-    KTimer tm(c, "mac_finalize");
+    A.flag = c->d_sigma + (MAX_PARTIES + 1) * 2;
+    A.seq = ++c->fin_seq;
     hipLaunchKernelGGL((k_mac_finalize<F, N>), dim3(1), dim3(BLOCK), 0, c->stream, A);
     return hip_status(hipGetLastError());
   });

@@ -77,6 +77,7 @@ def lib() -> ctypes.CDLL:
             "spdz_reduce_add": (i32, [vp, ctypes.POINTER(Shares), ctypes.POINTER(Shares)]),
             "spdz_mac_check": (i32, [vp, ctypes.POINTER(i32), u64p]),
             "spdz_deal_alpha": (i32, [u64p, i32, i32, ctypes.c_uint64, u64p]),
+            "spdz_stream_probe": (i32, [i32, i32, vp, vp, i64, i64, i32, vp]),
             "spdz_deal_secret": (i32, [vp, ctypes.c_uint64, ctypes.c_uint64, vp,
                                        ctypes.POINTER(Shares), vp]),
             "spdz_deal_triple": (i32, [vp, ctypes.c_uint64, ctypes.c_uint64, ctypes.POINTER(Triple)]),
@@ -263,6 +264,18 @@ def spdz_copy_probe(dst: torch.Tensor, src: torch.Tensor, stream=None):
     st = (stream or torch.cuda.current_stream()).cuda_stream
     _check(lib().spdz_copy_probe(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
                                  src.numel(), ctypes.c_void_p(st)), "spdz_copy_probe")
+
+
+def spdz_stream_probe(reads: int, writes: int, inp: Optional[torch.Tensor], out: torch.Tensor, stride: int,
+                      words: int, blocks_per_cu: int = 0, stream=None):
+    """Memory-pattern probe: `reads` streams read from inp and `writes` written to out (int64 tensors,
+    stream k at word k * stride)."""
+    st = (stream or torch.cuda.current_stream()).cuda_stream
+    if inp is not None:
+        assert inp.numel() >= (max(reads, 1) - 1) * stride + words
+    assert out.numel() >= (max(writes, 1) - 1) * stride + words
+    _check(lib().spdz_stream_probe(reads, writes, _ptr(inp), ctypes.c_void_p(out.data_ptr()), stride, words,
+                                   blocks_per_cu, ctypes.c_void_p(st)), "spdz_stream_probe")
 
 
 def deal_alpha(p: int, n: int, seed: int) -> list:

@@ -447,3 +447,25 @@ def test_overlapping_party_and_limb_planes_rejected():
     d_ok = spdz.Shares(buf_v.data_ptr(), buf_m.data_ptr(), 64, 128, 64)
     assert spdz.lib().spdz_open(ctx._h, ctypes.byref(d_ok), ctypes.c_void_p(out.data_ptr())) == 0
     ctx.close()
+
+
+def test_stream_probe_patterns():
+    """The bandwidth probe moves what it claims: out stream k, element e = e ^ (xor of the read
+    streams at e) + k; unbuilt patterns are refused."""
+    from paper_2512_11112_amd.spdz import SpdzError, spdz_stream_probe
+    words, stride = 10007, 10240
+    g = torch.Generator().manual_seed(3)
+    for r, s in ((1, 1), (2, 1), (20, 4), (0, 1)):
+        inp = torch.randint(-(1 << 62), 1 << 62, (max(r, 1) * stride,), generator=g, dtype=torch.int64).cuda()
+        out = torch.zeros(s * stride, dtype=torch.int64, device="cuda")
+        spdz_stream_probe(r, s, inp if r else None, out, stride, words, 2)
+        torch.cuda.synchronize()
+        x = torch.arange(words, dtype=torch.int64)
+        h = inp.cpu()
+        for k in range(r):
+            x ^= h[k * stride:k * stride + words]
+        for k in range(s):
+            assert torch.equal(out.cpu()[k * stride:k * stride + words], x + k), (r, s, k)
+    big = torch.zeros(3 * stride, dtype=torch.int64, device="cuda")
+    with pytest.raises(SpdzError):   # (3, 3) is not a built pattern
+        spdz_stream_probe(3, 3, big, big, stride, words, 2)
