@@ -337,9 +337,13 @@ int64_t spdz_dag_opened_count(const spdz_dag *dag);
 spdz_status spdz_dag_deal(spdz_dag *dag, uint64_t seed, uint64_t input_array0, uint64_t triple_array0);
 
 /* Run every op once.  mode: SPDZ_MODE_PER_OP (one launch per op),
- * SPDZ_MODE_PER_LEVEL (one persistent fused launch per level), SPDZ_MODE_GRAPH
- * (the per-level launches captured once into a hipGraph and replayed; when a
- * policy sends ops to the CPU the run falls back to per-level launches).
+ * SPDZ_MODE_PER_LEVEL (one persistent fused launch per batch; see
+ * spdz_dag_set_flush), SPDZ_MODE_GRAPH (the per-batch launches captured once
+ * into a hipGraph and replayed; when a policy sends ops to the CPU the run
+ * falls back to per-batch launches, the CPU back end working on a level while
+ * the GPU runs it, and each level's transfers batched into one kernel per
+ * direction through pinned staging; the triples of CPU-run products are moved
+ * to the host once, before their first run).
  * policy: SPDZ_POLICY_STATIC (width < threshold runs on the CPU back end),
  * SPDZ_POLICY_LEARNED (the cost model of spdz_dag_set_cost_model decides),
  * SPDZ_POLICY_ALL_GPU, SPDZ_POLICY_ALL_CPU.  Results do not depend on mode or
@@ -363,10 +367,32 @@ spdz_status spdz_dag_autotune(spdz_dag *dag, int max_levels, int *tile, int *blo
 /* MIN_KERNEL_SIZE of the static policy (default 65535 = slice 262140 / 4). */
 spdz_status spdz_dag_set_threshold(spdz_dag *dag, int64_t min_kernel_size);
 
-/* Statistics of the last run: ops on each side, host/device copies, and the
- * time spent in cost-model inference (ms). */
+/* Batch flush of the non-blocking scheduler (Sec. III-C, Algorithm 1: ready
+ * queues, heavy ops first).  Within a level the scheduler takes first the GPU
+ * ops whose outputs a later CPU-run op reads, then the rest, Beaver products
+ * before the others in each group, and accumulates them into a pending batch;
+ * the batch is launched as one fused kernel when it holds flush_elems elements
+ * or when the level's ready queue is empty (flush_elems = 0, the default: one
+ * launch per level).  Right after the batch that completes the first group,
+ * those outputs start their transfer to the host, so the CPU back end can take
+ * up the next level while the rest of this one runs on the GPU.  Under
+ * SPDZ_POLICY_LEARNED the flush point of each level is the cost model's: an
+ * early flush after the first group when the model's GPU time for the rest of
+ * the level exceeds the fixed cost of one more launch (ns_per_copy of
+ * spdz_dag_set_cost_model), else none.  Results do not depend on it. */
+spdz_status spdz_dag_set_flush(spdz_dag *dag, int64_t flush_elems);
+
+/* Statistics of the last run: ops on each side, host/device transfers (one
+ * kernel per level and direction that moves anything), and the time spent in
+ * cost-model inference (ms). */
 spdz_status spdz_dag_last_stats(const spdz_dag *dag, int64_t *gpu_ops, int64_t *cpu_ops, int64_t *copies,
                                 double *predict_ms);
+
+/* More statistics of the last run: level-kernel launches, batches flushed
+ * before their level's queue was empty, transfer launches and bytes moved
+ * between host and device (all nullable). */
+spdz_status spdz_dag_run_info(const spdz_dag *dag, int64_t *launches, int64_t *early_flushes, int64_t *transfers,
+                              int64_t *transfer_bytes);
 
 /* ---------------------------------------------------------------------- */
 /* FP32 MLP cost model of the learned dispatcher                            */
@@ -408,6 +434,12 @@ spdz_status spdz_mlp_train(void *hip_stream, float *W, const float *X, const flo
  * learned run evaluates the model for every op in one batched GPU launch; the
  * decisions are kept until the model changes. */
 spdz_status spdz_dag_set_cost_model(spdz_dag *dag, const float *W, double ns_per_byte, double ns_per_copy);
+
+/* Time one host <-> device transfer of `words` 64-bit words as a hybrid DAG run
+ * makes it (the transfer kernel between device memory and pinned, mapped
+ * staging, the wait for it, and the host copy to or from ordinary memory):
+ * median ns over reps, device to host and host to device.  Synchronous. */
+spdz_status spdz_dag_time_transfer(spdz_ctx *ctx, int64_t words, int reps, double *d2h_ns, double *h2d_ns);
 
 /* Measure one level of q ops of `kind` and `width` (q clipped so the level
  * holds at most 2^26 elements): per-op GPU time inside a fused launch and

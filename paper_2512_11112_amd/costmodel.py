@@ -12,7 +12,6 @@ op on each side from (kind, log2 width, parties, limbs, log2(1 + q)).
 from __future__ import annotations
 
 import math
-import time
 from dataclasses import dataclass
 
 import numpy as np
@@ -41,7 +40,7 @@ class Sweep:
     rows: list           # (kind, width, n, q) per sample
 
 
-def sweep(parties=(2, 3), log2_widths=range(4, 25, 2), qs=(1, 16, 256), reps: int = 3, progress=None) -> Sweep:
+def sweep(parties=(2, 3), log2_widths=range(4, 25, 2), qs=(1, 16, 256, 512), reps: int = 3, progress=None) -> Sweep:
     X, T, rows = [], [], []
     for n in parties:
         ctx = S.Context(n, P61, [1] * n, 0)
@@ -60,25 +59,16 @@ def sweep(parties=(2, 3), log2_widths=range(4, 25, 2), qs=(1, 16, 256), reps: in
     return Sweep(np.array(X, dtype=np.float32), np.array(T, dtype=np.float32), rows)
 
 
-def transfer_costs(sizes=(1 << 12, 1 << 16, 1 << 20, 1 << 24), reps: int = 5):
-    """Least-squares (ns per byte, ns per copy) of pageable host <-> device copies."""
+def transfer_costs(words=(1 << 9, 1 << 13, 1 << 17, 1 << 21, 1 << 24), reps: int = 5):
+    """Least-squares (ns per byte, ns per transfer) of the hybrid run's host <-> device transfers
+    (one kernel through pinned, mapped staging plus the host copy), both directions."""
+    ctx = S.Context(2, P61, [1, 1], 0)
     xs, ys = [], []
-    for nbytes in sizes:
-        h = torch.empty(nbytes // 8, dtype=torch.int64)
-        d = torch.empty(nbytes // 8, dtype=torch.int64, device="cuda")
-        for direction in (0, 1):
-            ts = []
-            for _ in range(reps):
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                if direction == 0:
-                    d.copy_(h)
-                else:
-                    h.copy_(d)
-                torch.cuda.synchronize()
-                ts.append((time.perf_counter() - t0) * 1e9)
-            xs.append(nbytes)
-            ys.append(sorted(ts)[len(ts) // 2])
+    for w in words:
+        d2h, h2d = S.dag_time_transfer(ctx, w, reps)
+        xs += [8 * w, 8 * w]
+        ys += [d2h, h2d]
+    ctx.close()
     A = np.stack([np.array(xs, dtype=np.float64), np.ones(len(xs))], axis=1)
     (per_byte, fixed), *_ = np.linalg.lstsq(A, np.array(ys), rcond=None)
     return max(float(per_byte), 0.0), max(float(fixed), 0.0)

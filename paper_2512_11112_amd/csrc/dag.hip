@@ -222,6 +222,7 @@ struct spdz_dag {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   int graph_tile = 0, graph_bpc = 0;
+  int64_t graph_flush = -1, graph_launches = 0, graph_early = 0;
   // dispatch
   int64_t threshold = 65535;
   std::vector<float> cost_model;  // MLP weights (learned policy)
@@ -235,6 +236,21 @@ struct spdz_dag {
   std::vector<uint8_t> tri_on_host;
   // statistics of the last run
   int64_t last_gpu_ops = 0, last_cpu_ops = 0, last_copies = 0;
+  int64_t last_launches = 0, last_xfer_bytes = 0, last_early_flushes = 0;
+  // batch flush of the scheduler: a level's pending GPU batch is launched once it holds
+  // flush_elems elements (0: only when the level's ready queue is empty)
+  int64_t flush_elems = 0;
+  std::vector<float> learned_gpu_ns;  // the cost model's GPU time per op (learned flush decisions)
+  double flush_min_ns = 0.0;          // learned flush: the least predicted GPU work worth an early cut
+  // host <-> device transfers of a hybrid run: transfer tables on the device, two pinned mapped
+  // staging buffers per direction (levels alternate between them), their device addresses
+  void *d_xfer = nullptr;
+  int64_t xfer_cap = 0;
+  u64 *h_stage[4] = {nullptr, nullptr, nullptr, nullptr};  // [0], [1]: device to host; [2], [3]: host to device
+  u64 *d_stage[4] = {nullptr, nullptr, nullptr, nullptr};
+  int64_t stage_cap[4] = {0, 0, 0, 0};
+  hipEvent_t ev_stage[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool ev_stage_live[4] = {false, false, false, false};
   // the DAG's own stream (captured in graph mode), ordered after / before the context stream
   hipStream_t stream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_copy = nullptr;
@@ -381,6 +397,11 @@ spdz_status spdz_dag_destroy(spdz_dag *g) {
   if (g->ev_copy) (void)hipEventDestroy(g->ev_copy);
   if (g->stream) (void)hipStreamDestroy(g->stream);
   for (u64 *p : {g->h_nval, g->h_nmac, g->h_tval, g->h_tmac}) free(p);
+  if (g->d_xfer) (void)hipFree(g->d_xfer);
+  for (int b = 0; b < 4; b++) {
+    if (g->h_stage[b]) (void)hipHostFree(g->h_stage[b]);
+    if (g->ev_stage[b]) (void)hipEventDestroy(g->ev_stage[b]);
+  }
   delete g;
   return SPDZ_OK;
 }
@@ -486,37 +507,62 @@ static spdz_status launch_level(spdz_dag *g, const DagOpDev *d_ops, const int32_
   return SPDZ_E_UNSUPPORTED;
 }
 
-// Plan of the GPU part of a run: per level the GPU ops in launch order (Beaver
-// products first, the heavy queue of the scheduler), each with its first work
-// item, and the level's work-item count.
+// Plan of the GPU part of a run.  Per level the GPU ops in launch order: ops whose outputs a
+// later CPU op reads first (the "urgent" ops, so that their transfer to the host can start
+// before the rest of the level has run), then within each group Beaver products first (the
+// heavy queue of the scheduler).  The scheduler accumulates these ops into a batch and
+// flushes it (one fused launch) when its elements reach the level's flush point or the
+// level's ready queue is empty; every batch has its own work-item numbering.
 struct GpuPlan {
   std::vector<int32_t> list;
-  std::vector<int64_t> level_begin;
-  std::vector<int64_t> level_tiles;
-  std::vector<int64_t> tile0;  // per list entry
+  std::vector<int64_t> tile0;        // per list entry: first work item within its batch
+  std::vector<int64_t> batch_begin;  // list index of each batch's first op (+ end sentinel)
+  std::vector<int64_t> batch_tiles;  // work items per batch
+  std::vector<int64_t> level_batch;  // first batch of each level (+ end sentinel)
+  std::vector<int64_t> urgent_batch; // per level: the batch after which the level's urgent outputs are complete, -1 if none
+  int64_t early_flushes = 0;         // batches cut before a level's queue emptied
 };
 
-static void make_plan(spdz_dag *g, const std::vector<uint8_t> &on_gpu, int tile, GpuPlan &plan) {
-  plan.list.clear();
-  plan.level_begin.clear();
-  plan.level_tiles.clear();
-  plan.tile0.clear();
+// flush_at[l]: elements after which the pending batch of level l is flushed (0: only when the
+// level's queue is empty); urgent: ops whose outputs the host needs (null: none)
+static void make_plan(spdz_dag *g, const std::vector<uint8_t> &on_gpu, int tile, GpuPlan &plan,
+                      const std::vector<uint8_t> *urgent = nullptr, const std::vector<int64_t> *flush_at = nullptr) {
+  plan = GpuPlan();
   for (size_t l = 0; l < g->levels.size(); l++) {
-    plan.level_begin.push_back((int64_t)plan.list.size());
-    int64_t tiles = 0;
-    for (int pass = 0; pass < 2; pass++) {
+    plan.level_batch.push_back((int64_t)plan.batch_begin.size());
+    plan.urgent_batch.push_back(-1);
+    const int64_t cut = flush_at ? (*flush_at)[l] : 0;
+    int64_t tiles = 0, elems = 0;
+    bool open = false;
+    for (int pass = 0; pass < 4; pass++) {  // urgent heavy, urgent light, heavy, light
+      const bool want_urgent = pass < 2, want_heavy = (pass & 1) == 0;
       for (int32_t k : g->levels[l]) {
         const bool heavy = g->ops[k].kind == SPDZ_OP_MUL;
-        if (!on_gpu[k] || heavy != (pass == 0)) continue;
+        const bool urg = urgent && (*urgent)[k];
+        if (!on_gpu[k] || heavy != want_heavy || urg != want_urgent) continue;
+        if (!open) {
+          plan.batch_begin.push_back((int64_t)plan.list.size());
+          tiles = elems = 0;
+          open = true;
+        }
         g->h_ops[k].tile0 = tiles;
         plan.tile0.push_back(tiles);
         tiles += tiles_of(g->ops[k].width, tile);
+        elems += g->ops[k].width;
         plan.list.push_back(k);
+        if (urg) plan.urgent_batch[l] = (int64_t)plan.batch_begin.size() - 1;
+        if (cut > 0 && elems >= cut) {  // flush: the batch is launched now
+          plan.batch_tiles.push_back(tiles);
+          open = false;
+        }
       }
     }
-    plan.level_tiles.push_back(tiles);
+    if (open) plan.batch_tiles.push_back(tiles);
+    const int64_t nb = (int64_t)plan.batch_begin.size() - plan.level_batch.back();
+    if (nb > 1) plan.early_flushes += nb - 1;
   }
-  plan.level_begin.push_back((int64_t)plan.list.size());
+  plan.level_batch.push_back((int64_t)plan.batch_begin.size());
+  plan.batch_begin.push_back((int64_t)plan.list.size());
 }
 
 static spdz_status upload_plan(spdz_dag *g, const GpuPlan &plan, DagOpDev *d_ops, int32_t *d_list, hipStream_t st) {
@@ -528,18 +574,32 @@ static spdz_status upload_plan(spdz_dag *g, const GpuPlan &plan, DagOpDev *d_ops
   return hip_status(hipStreamSynchronize(st));  // host vectors may change after this
 }
 
-static spdz_status enqueue_level(spdz_dag *g, const GpuPlan &plan, const DagOpDev *d_ops, const int32_t *d_list,
-                                 size_t l, int mode, int tile, int bpc, const LaunchTarget &T) {
-  const int64_t b = plan.level_begin[l], e = plan.level_begin[l + 1];
-  if (e == b) return SPDZ_OK;
-  if (mode == 0) {
-    for (int64_t q = b; q < e; q++) {
-      const int64_t t0 = plan.tile0[q], nt = tiles_of(g->ops[plan.list[q]].width, tile);
-      SPDZ_RET(launch_level(g, d_ops, d_list + q, 1, t0, t0 + nt, tile, bpc, T));
+// batches [b0, b1) of a plan: one fused launch per batch (mode 1) or one launch per op (mode 0)
+static spdz_status enqueue_batches(spdz_dag *g, const GpuPlan &plan, const DagOpDev *d_ops, const int32_t *d_list,
+                                   int64_t b0, int64_t b1, int mode, int tile, int bpc, const LaunchTarget &T,
+                                   int64_t *launches = nullptr) {
+  for (int64_t b = b0; b < b1; b++) {
+    const int64_t lb = plan.batch_begin[b], le = plan.batch_begin[b + 1];
+    if (le == lb) continue;
+    if (mode == 0) {
+      for (int64_t q = lb; q < le; q++) {
+        const int64_t t0 = plan.tile0[q], nt = tiles_of(g->ops[plan.list[q]].width, tile);
+        SPDZ_RET(launch_level(g, d_ops, d_list + q, 1, t0, t0 + nt, tile, bpc, T));
+        if (launches) *launches += 1;
+      }
+    } else {
+      SPDZ_RET(launch_level(g, d_ops, d_list + lb, (int32_t)(le - lb), 0, plan.batch_tiles[b], tile, bpc, T));
+      if (launches) *launches += 1;
     }
-    return SPDZ_OK;
   }
-  return launch_level(g, d_ops, d_list + b, (int32_t)(e - b), 0, plan.level_tiles[l], tile, bpc, T);
+  return SPDZ_OK;
+}
+
+// every batch of level l
+static spdz_status enqueue_level(spdz_dag *g, const GpuPlan &plan, const DagOpDev *d_ops, const int32_t *d_list,
+                                 size_t l, int mode, int tile, int bpc, const LaunchTarget &T, int64_t *launches = nullptr) {
+  return enqueue_batches(g, plan, d_ops, d_list, plan.level_batch[l], plan.level_batch[l + 1], mode, tile, bpc, T,
+                         launches);
 }
 
 // --------------------------------------------------------------------------
@@ -745,6 +805,190 @@ static spdz_status copy_triple_to_host(spdz_dag *g, int64_t k, hipStream_t st) {
   return SPDZ_OK;
 }
 
+// --------------------------------------------------------------------------
+// host <-> device transfers of a hybrid run.  Everything one level moves in one
+// direction is one kernel launch: the kernel copies the level's segments
+// between the device arenas and a pinned, mapped staging buffer (reads or
+// writes over the host link), and the host copies between the staging buffer
+// and its mirrors of the arenas.
+// --------------------------------------------------------------------------
+struct XferSeg {
+  int32_t arena;  // 0 node values, 1 node MACs, 2 triple values, 3 triple MACs
+  int32_t pad;
+  int64_t off;    // word offset in the arena (and in its host mirror)
+  int64_t pos;    // word offset in the staging buffer
+  int64_t words;
+};
+constexpr int64_t XFER_CHUNK = 1 << 16;  // longest segment (words), so that blocks share long nodes
+
+__global__ __launch_bounds__(BLOCK) void k_xfer(const XferSeg *segs, int64_t nseg, u64 *nval, u64 *nmac, u64 *tval,
+                                                u64 *tmac, u64 *stage, int to_host) {
+  for (int64_t s = blockIdx.x; s < nseg; s += gridDim.x) {
+    const XferSeg q = segs[s];
+    u64 *a = q.arena == 0 ? nval : q.arena == 1 ? nmac : q.arena == 2 ? tval : tmac;
+    if (to_host) {
+      for (int64_t k = threadIdx.x; k < q.words; k += BLOCK) stage[q.pos + k] = a[q.off + k];
+    } else {
+      for (int64_t k = threadIdx.x; k < q.words; k += BLOCK) a[q.off + k] = stage[q.pos + k];
+    }
+  }
+}
+
+// appends the segments of `words` words from arena word `off`, staged from `pos`; returns the new pos
+static int64_t add_segs(std::vector<XferSeg> &v, int arena, int64_t off, int64_t words, int64_t pos) {
+  for (int64_t k = 0; k < words; k += XFER_CHUNK) {
+    const int64_t w = std::min(XFER_CHUNK, words - k);
+    v.push_back(XferSeg{arena, 0, off + k, pos, w});
+    pos += w;
+  }
+  return pos;
+}
+
+static u64 *host_arena(spdz_dag *g, int arena) {
+  return arena == 0 ? g->h_nval : arena == 1 ? g->h_nmac : arena == 2 ? g->h_tval : g->h_tmac;
+}
+
+// staging buffer b (pinned, mapped) of at least `words` words; waits for its last user first
+static spdz_status ensure_stage(spdz_dag *g, int b, int64_t words) {
+  if (!g->ev_stage[b] && hipEventCreateWithFlags(&g->ev_stage[b], hipEventDisableTiming) != hipSuccess) return SPDZ_E_HIP;
+  if (g->stage_cap[b] >= words) return SPDZ_OK;
+  if (g->ev_stage_live[b]) SPDZ_RET(hip_status(hipEventSynchronize(g->ev_stage[b])));
+  if (g->h_stage[b]) (void)hipHostFree(g->h_stage[b]);
+  g->h_stage[b] = g->d_stage[b] = nullptr;
+  g->stage_cap[b] = 0;
+  const int64_t cap = std::max<int64_t>(words, 1 << 16);
+  if (hipHostMalloc((void **)&g->h_stage[b], (size_t)cap * 8, hipHostMallocMapped) != hipSuccess) return SPDZ_E_NOMEM;
+  if (hipHostGetDevicePointer((void **)&g->d_stage[b], g->h_stage[b], 0) != hipSuccess) return SPDZ_E_HIP;
+  g->stage_cap[b] = cap;
+  return SPDZ_OK;
+}
+
+static spdz_status launch_xfer(spdz_dag *g, const XferSeg *d_segs, int64_t nseg, int b, bool to_host) {
+  if (nseg == 0) return SPDZ_OK;
+  const int64_t grid = std::min<int64_t>(nseg, (int64_t)g->c->num_cus * 4);
+  hipLaunchKernelGGL(k_xfer, dim3((unsigned)grid), dim3(BLOCK), 0, g->stream, d_segs, nseg, g->nval, g->nmac, g->tval,
+                     g->tmac, g->d_stage[b], to_host ? 1 : 0);
+  SPDZ_RET(hip_status(hipGetLastError()));
+  SPDZ_RET(hip_status(hipEventRecord(g->ev_stage[b], g->stream)));
+  g->ev_stage_live[b] = true;
+  g->last_copies += 1;
+  return SPDZ_OK;
+}
+
+// host side of a transfer: staging buffer b <-> host mirrors, segments [s0, s1) of segs (the
+// pool copies long lists in parallel)
+static void host_copy(spdz_dag *g, const std::vector<XferSeg> &segs, int64_t s0, int64_t s1, int b, bool from_stage) {
+  u64 *st = g->h_stage[b];
+  auto one = [&](int64_t i) {
+    const XferSeg &q = segs[i];
+    u64 *h = host_arena(g, q.arena) + q.off;
+    if (from_stage) memcpy(h, st + q.pos, (size_t)q.words * 8);
+    else memcpy(st + q.pos, h, (size_t)q.words * 8);
+  };
+  int64_t words = 0;
+  for (int64_t i = s0; i < s1; i++) words += segs[i].words;
+  if (words < (1 << 17)) {
+    for (int64_t i = s0; i < s1; i++) one(i);
+  } else {
+    CpuPool::get().parallel_for(s1 - s0, [&](int64_t i) { one(s0 + i); });
+  }
+  g->last_xfer_bytes += words * 8;
+}
+
+// The transfer schedule of a hybrid run.  Stage 0 is before the first level; stage l follows
+// level l's urgent batch (device to host: the outputs of level l that later CPU ops read, and
+// at stage 0 the inputs they read) or precedes level l's GPU batches (host to device: the
+// CPU-produced operands of level l's GPU ops).  Segments of all stages are kept in one table.
+struct XferPlan {
+  std::vector<XferSeg> segs;
+  std::vector<int64_t> d2h_b, d2h_e, h2d_b, h2d_e;  // per stage, ranges in segs
+  std::vector<int64_t> d2h_words, h2d_words;
+  std::vector<uint8_t> urgent;                      // per op: a later CPU op reads its output
+  std::vector<uint8_t> resid_after;                 // node residency at the end of the run
+};
+
+static void plan_transfers(spdz_dag *g, const std::vector<uint8_t> &on_gpu, XferPlan &xp) {
+  const int64_t nl = (int64_t)g->levels.size(), n = g->c->n;
+  xp = XferPlan();
+  xp.urgent.assign(g->n_ops, 0);
+  std::vector<uint8_t> r(g->n_nodes, 0);
+  for (int i = 0; i < g->n_inputs; i++) r[i] = g->resid[i];
+  std::vector<std::vector<int64_t>> d2h(nl + 1), h2d(nl + 1);  // node ids per stage
+  auto stage_of = [&](int64_t nd) -> int64_t { return nd < g->n_inputs ? 0 : g->ops[nd - g->n_inputs].level; };
+  for (int64_t l = 0; l < nl; l++) {
+    for (int32_t k : g->levels[l]) {
+      const spdz_dag_op &op = g->ops[k];
+      const int64_t srcs[2] = {op.src1, op.kind == SPDZ_OP_SMUL ? -1 : op.src2};
+      for (int64_t sn : srcs) {
+        if (sn < 0) continue;
+        if (on_gpu[k] && !(r[sn] & 1)) {
+          h2d[l + 1].push_back(sn);
+          r[sn] |= 1;
+        } else if (!on_gpu[k] && !(r[sn] & 2)) {
+          d2h[stage_of(sn)].push_back(sn);
+          r[sn] |= 2;
+          if (sn >= g->n_inputs) xp.urgent[sn - g->n_inputs] = 1;
+        }
+      }
+    }
+    for (int32_t k : g->levels[l]) r[g->n_inputs + k] |= on_gpu[k] ? 1 : 2;
+  }
+  for (int64_t st = 0; st <= nl; st++) {
+    for (int dir = 0; dir < 2; dir++) {
+      const std::vector<int64_t> &nodes = dir == 0 ? d2h[st] : h2d[st];
+      (dir == 0 ? xp.d2h_b : xp.h2d_b).push_back((int64_t)xp.segs.size());
+      int64_t pos = 0;
+      for (int64_t nd : nodes) {
+        const int64_t w = n * g->node_width[nd];
+        pos = add_segs(xp.segs, 0, g->node_off[nd], w, pos);
+        pos = add_segs(xp.segs, 1, g->node_off[nd], w, pos);
+      }
+      (dir == 0 ? xp.d2h_e : xp.h2d_e).push_back((int64_t)xp.segs.size());
+      (dir == 0 ? xp.d2h_words : xp.h2d_words).push_back(pos);
+    }
+  }
+  xp.resid_after = r;
+}
+
+// The Beaver triples of CPU-run products are preprocessing material of the CPU back end:
+// brought to the host mirrors once (through staging buffer 0), before the online run
+static spdz_status stage_triples(spdz_dag *g, const std::vector<uint8_t> &on_gpu) {
+  const int64_t n = g->c->n, cap = int64_t(1) << 25;
+  std::vector<XferSeg> segs;
+  std::vector<int64_t> ops;
+  int64_t pos = 0;
+  auto flush = [&]() -> spdz_status {
+    if (segs.empty()) return SPDZ_OK;
+    SPDZ_RET(ensure_stage(g, 0, pos));
+    const size_t bytes = segs.size() * sizeof(XferSeg);
+    if ((int64_t)bytes > g->xfer_cap) {
+      if (g->d_xfer) (void)hipFree(g->d_xfer);
+      g->d_xfer = nullptr;
+      g->xfer_cap = 0;
+      if (hipMalloc(&g->d_xfer, bytes) != hipSuccess) return SPDZ_E_NOMEM;
+      g->xfer_cap = (int64_t)bytes;
+    }
+    SPDZ_RET(hip_status(hipMemcpyAsync(g->d_xfer, segs.data(), bytes, hipMemcpyHostToDevice, g->stream)));
+    SPDZ_RET(launch_xfer(g, (const XferSeg *)g->d_xfer, (int64_t)segs.size(), 0, true));
+    SPDZ_RET(hip_status(hipEventSynchronize(g->ev_stage[0])));
+    host_copy(g, segs, 0, (int64_t)segs.size(), 0, true);
+    for (int64_t k : ops) g->tri_on_host[k] = 1;
+    segs.clear();
+    ops.clear();
+    pos = 0;
+    return SPDZ_OK;
+  };
+  for (int64_t k = 0; k < g->n_ops; k++) {
+    if (on_gpu[k] || g->ops[k].kind != SPDZ_OP_MUL || g->tri_on_host[k]) continue;
+    const int64_t w = 3 * n * g->ops[k].width;
+    if (pos + 2 * w > cap) SPDZ_RET(flush());
+    pos = add_segs(segs, 2, g->tri_off[k], w, pos);
+    pos = add_segs(segs, 3, g->tri_off[k], w, pos);
+    ops.push_back(k);
+  }
+  return flush();
+}
+
 }  // namespace spdz
 
 namespace spdz {
@@ -773,7 +1017,7 @@ spdz_status dag_decide_learned(spdz_dag *g, std::vector<uint8_t> &on_gpu);
 
 static spdz_status run_graph(spdz_dag *g) {
   spdz_ctx *c = g->c;
-  if (!g->gexec || g->graph_tile != g->tile || g->graph_bpc != g->blocks_per_cu) {
+  if (!g->gexec || g->graph_tile != g->tile || g->graph_bpc != g->blocks_per_cu || g->graph_flush != g->flush_elems) {
     if (g->gexec) (void)hipGraphExecDestroy(g->gexec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
     g->gexec = nullptr;
@@ -785,8 +1029,11 @@ static spdz_status run_graph(spdz_dag *g) {
     }
     GpuPlan plan;
     std::vector<uint8_t> all(g->n_ops, 1);
-    make_plan(g, all, g->tile, plan);
+    std::vector<int64_t> flush_at(g->levels.size(), g->flush_elems);
+    make_plan(g, all, g->tile, plan, nullptr, &flush_at);
     SPDZ_RET(upload_plan(g, plan, g->d_ops_graph, g->d_list_graph, g->stream));
+    g->graph_launches = (int64_t)plan.batch_tiles.size();
+    g->graph_early = plan.early_flushes;
     g->graph_slots = 0;
     LaunchTarget T{g->stream, c->d_acc, &g->graph_slots};
     SPDZ_RET(hip_status(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal)));
@@ -801,7 +1048,10 @@ static spdz_status run_graph(spdz_dag *g) {
     if (hipGraphInstantiate(&g->gexec, g->graph, nullptr, nullptr, 0) != hipSuccess) return SPDZ_E_HIP;
     g->graph_tile = g->tile;
     g->graph_bpc = g->blocks_per_cu;
+    g->graph_flush = g->flush_elems;
   }
+  g->last_launches = g->graph_launches;
+  g->last_early_flushes = g->graph_early;
   SPDZ_RET(set_params(g));
   SPDZ_RET(hip_status(hipGraphLaunch(g->gexec, g->stream)));
   if (g->graph_slots > c->slots) c->slots = g->graph_slots;
@@ -833,58 +1083,105 @@ spdz_status spdz_dag_run(spdz_dag *g, int mode, int policy, double *wall_ms) {
   for (uint8_t v : on_gpu) ngpu += v;
   g->last_gpu_ops = ngpu;
   g->last_cpu_ops = g->n_ops - ngpu;
-  g->last_copies = 0;
+  g->last_copies = g->last_launches = g->last_xfer_bytes = g->last_early_flushes = 0;
   const bool all_gpu = ngpu == g->n_ops;
 
   if (all_gpu && mode == 2) {
     SPDZ_RET(run_graph(g));
     for (int64_t k = 0; k < g->n_ops; k++) g->resid[g->n_inputs + k] = 1;
   } else {
-    if (!all_gpu) SPDZ_RET(ensure_host_mirrors(g));
+    // the schedule: which outputs go to the host (urgent ops, launched first in their level),
+    // which operands come to the device, and where each level's pending GPU batch is flushed
+    const size_t nl = g->levels.size();
+    XferPlan xp;
+    plan_transfers(g, on_gpu, xp);
+    std::vector<int64_t> flush_at(nl, g->flush_elems);
+    if (policy == SPDZ_POLICY_LEARNED && !g->learned_gpu_ns.empty()) {
+      // early flush after the urgent ops when the model predicts the rest of the level's GPU work
+      // to take longer than an extra launch costs: their transfer and the next CPU level then
+      // overlap that work
+      for (size_t l = 0; l < nl; l++) {
+        int64_t urgent_elems = 0;
+        double rest_ns = 0.0;
+        for (int32_t k : g->levels[l]) {
+          if (!on_gpu[k]) continue;
+          if (xp.urgent[k]) urgent_elems += g->ops[k].width;
+          else rest_ns += g->learned_gpu_ns[k];
+        }
+        flush_at[l] = urgent_elems > 0 && rest_ns > g->flush_min_ns ? urgent_elems : 0;
+      }
+    }
     GpuPlan plan;
-    make_plan(g, on_gpu, g->tile, plan);
+    make_plan(g, on_gpu, g->tile, plan, &xp.urgent, &flush_at);
+    g->last_early_flushes = plan.early_flushes;
+    if (!all_gpu) {
+      SPDZ_RET(ensure_host_mirrors(g));
+      SPDZ_RET(stage_triples(g, on_gpu));
+    }
     SPDZ_RET(upload_plan(g, plan, g->d_ops, g->d_list, g->stream));
     SPDZ_RET(set_params(g));
+    int64_t dmax = 0, hmax = 0;
+    for (size_t st = 0; st <= nl; st++) {
+      dmax = std::max(dmax, xp.d2h_words[st]);
+      hmax = std::max(hmax, xp.h2d_words[st]);
+    }
+    const XferSeg *dsegs = nullptr;
+    if (!xp.segs.empty()) {
+      for (int b = 0; b < 4; b++) SPDZ_RET(ensure_stage(g, b, b < 2 ? dmax : hmax));
+      const size_t bytes = xp.segs.size() * sizeof(XferSeg);
+      if ((int64_t)bytes > g->xfer_cap) {
+        SPDZ_RET(hip_status(hipStreamSynchronize(g->stream)));
+        if (g->d_xfer) (void)hipFree(g->d_xfer);
+        g->d_xfer = nullptr;
+        g->xfer_cap = 0;
+        if (hipMalloc(&g->d_xfer, bytes) != hipSuccess) return SPDZ_E_NOMEM;
+        g->xfer_cap = (int64_t)bytes;
+      }
+      SPDZ_RET(hip_status(hipMemcpyAsync(g->d_xfer, xp.segs.data(), bytes, hipMemcpyHostToDevice, g->stream)));
+      SPDZ_RET(hip_status(hipStreamSynchronize(g->stream)));  // xp.segs is read by the copy
+      dsegs = (const XferSeg *)g->d_xfer;
+    }
     const u64 cst = coef_state(c);
     const int64_t jb = c->log_count;
     LaunchTarget T{g->stream, c->d_acc, &c->slots};
     const int gmode = mode == 2 ? 1 : mode;
+    // stage 0: inputs that CPU ops read
+    if (xp.d2h_e[0] > xp.d2h_b[0]) SPDZ_RET(launch_xfer(g, dsegs + xp.d2h_b[0], xp.d2h_e[0] - xp.d2h_b[0], 0, true));
     std::vector<int32_t> cpu_ops;
-    for (size_t l = 0; l < g->levels.size(); l++) {
+    for (size_t l = 0; l < nl; l++) {
+      const size_t st = l + 1;
+      // operands of this level's GPU ops that CPU ops produced: host -> staging -> device
+      if (xp.h2d_e[st] > xp.h2d_b[st]) {
+        const int b = 2 + (int)(st & 1);
+        if (g->ev_stage_live[b]) SPDZ_RET(hip_status(hipEventSynchronize(g->ev_stage[b])));
+        host_copy(g, xp.segs, xp.h2d_b[st], xp.h2d_e[st], b, false);
+        SPDZ_RET(launch_xfer(g, dsegs + xp.h2d_b[st], xp.h2d_e[st] - xp.h2d_b[st], b, false));
+      }
+      // the level's GPU batches; after the batch that completes its urgent ops, their outputs
+      // go to the host
+      const int64_t b0 = plan.level_batch[l], b1 = plan.level_batch[l + 1], ub = plan.urgent_batch[l];
+      const bool d2h = xp.d2h_e[st] > xp.d2h_b[st];
+      const int64_t bsplit = d2h ? (ub >= 0 ? ub + 1 : b1) : b1;
+      SPDZ_RET(enqueue_batches(g, plan, g->d_ops, g->d_list, b0, bsplit, gmode, g->tile, g->blocks_per_cu, T,
+                               &g->last_launches));
+      if (d2h) SPDZ_RET(launch_xfer(g, dsegs + xp.d2h_b[st], xp.d2h_e[st] - xp.d2h_b[st], (int)(st & 1), true));
+      SPDZ_RET(enqueue_batches(g, plan, g->d_ops, g->d_list, bsplit, b1, gmode, g->tile, g->blocks_per_cu, T,
+                               &g->last_launches));
+      // the CPU part of the level runs while the GPU works: it needs what earlier stages sent
+      // to the host, the latest of which is stage l (its staging buffer is read now, before
+      // stage l + 2 reuses it)
       cpu_ops.clear();
-      for (int32_t k : g->levels[l]) {
-        const spdz_dag_op &op = g->ops[k];
-        const int64_t srcs[2] = {op.src1, op.kind == SPDZ_OP_SMUL ? -1 : op.src2};
-        if (on_gpu[k]) {
-          for (int64_t sn : srcs)
-            if (sn >= 0 && !(g->resid[sn] & 1)) SPDZ_RET(copy_node(g, sn, false, g->stream));
-        } else {
-          cpu_ops.push_back(k);
-        }
+      for (int32_t k : g->levels[l])
+        if (!on_gpu[k]) cpu_ops.push_back(k);
+      const size_t prev = st - 1;
+      if (xp.d2h_e[prev] > xp.d2h_b[prev]) {
+        const int b = (int)(prev & 1);
+        SPDZ_RET(hip_status(hipEventSynchronize(g->ev_stage[b])));
+        host_copy(g, xp.segs, xp.d2h_b[prev], xp.d2h_e[prev], b, true);
       }
-      bool wait_copies = false;
-      for (int32_t k : cpu_ops) {
-        const spdz_dag_op &op = g->ops[k];
-        const int64_t srcs[2] = {op.src1, op.kind == SPDZ_OP_SMUL ? -1 : op.src2};
-        for (int64_t sn : srcs)
-          if (sn >= 0 && !(g->resid[sn] & 2)) {
-            SPDZ_RET(copy_node(g, sn, true, g->stream));
-            wait_copies = true;
-          }
-        if (op.kind == SPDZ_OP_MUL && !g->tri_on_host[k]) {
-          SPDZ_RET(copy_triple_to_host(g, k, g->stream));
-          wait_copies = true;
-        }
-      }
-      if (wait_copies) SPDZ_RET(hip_status(hipEventRecord(g->ev_copy, g->stream)));
-      // GPU part of the level (runs while the host works on the CPU part)
-      SPDZ_RET(enqueue_level(g, plan, g->d_ops, g->d_list, l, gmode, g->tile, g->blocks_per_cu, T));
-      if (!cpu_ops.empty()) {
-        if (wait_copies) SPDZ_RET(hip_status(hipEventSynchronize(g->ev_copy)));
-        cpu_level(g, cpu_ops, cst, jb, true);
-      }
-      for (int32_t k : g->levels[l]) g->resid[g->n_inputs + k] = on_gpu[k] ? 1 : 2;
+      if (!cpu_ops.empty()) cpu_level(g, cpu_ops, cst, jb, true);
     }
+    g->resid = xp.resid_after;
   }
   SPDZ_RET(hip_status(hipEventRecord(g->ev_out, g->stream)));
   SPDZ_RET(hip_status(hipStreamWaitEvent(c->stream, g->ev_out, 0)));
@@ -916,6 +1213,22 @@ spdz_status spdz_dag_set_launch(spdz_dag *g, int tile, int blocks_per_cu) {
 spdz_status spdz_dag_set_threshold(spdz_dag *g, int64_t min_kernel_size) {
   if (!g || min_kernel_size < 0) return SPDZ_E_INVAL;
   g->threshold = min_kernel_size;
+  return SPDZ_OK;
+}
+
+spdz_status spdz_dag_set_flush(spdz_dag *g, int64_t flush_elems) {
+  if (!g || flush_elems < 0) return SPDZ_E_INVAL;
+  g->flush_elems = flush_elems;
+  return SPDZ_OK;
+}
+
+spdz_status spdz_dag_run_info(const spdz_dag *g, int64_t *launches, int64_t *early_flushes, int64_t *transfers,
+                              int64_t *transfer_bytes) {
+  if (!g) return SPDZ_E_INVAL;
+  if (launches) *launches = g->last_launches;
+  if (early_flushes) *early_flushes = g->last_early_flushes;
+  if (transfers) *transfers = g->last_copies;
+  if (transfer_bytes) *transfer_bytes = g->last_xfer_bytes;
   return SPDZ_OK;
 }
 
@@ -1025,9 +1338,11 @@ spdz_status dag_decide_learned(spdz_dag *g, std::vector<uint8_t> &on_gpu) {
   SPDZ_RET(hip_status(hipMemcpyAsync(Y.data(), g->d_pred, Y.size() * sizeof(float), hipMemcpyDeviceToHost, g->stream)));
   SPDZ_RET(hip_status(hipStreamSynchronize(g->stream)));
   const int n = g->c->n;
+  g->learned_gpu_ns.assign(B, 0.f);
   for (int64_t k = 0; k < B; k++) {
     const spdz_dag_op &op = g->ops[k];
     const double cpu = std::exp2((double)Y[2 * k]), gpu = std::exp2((double)Y[2 * k + 1]);
+    g->learned_gpu_ns[k] = (float)gpu;
     // moving the op to the host: its inputs down, its triple down, its output back up
     double words = (double)n * 2 * (g->node_width[op.src1] + (op.kind == SPDZ_OP_SMUL ? 0 : g->node_width[op.src2]));
     double copies = op.kind == SPDZ_OP_SMUL ? 2 : 3;
@@ -1054,11 +1369,63 @@ spdz_status spdz_dag_set_cost_model(spdz_dag *g, const float *W, double ns_per_b
   if (!g->d_model && hipMalloc((void **)&g->d_model, SPDZ_MLP_NPARAM * sizeof(float)) != hipSuccess) return SPDZ_E_NOMEM;
   g->cost_model.assign(W, W + SPDZ_MLP_NPARAM);
   g->learned_on_gpu.clear();
+  g->learned_gpu_ns.clear();
   g->ns_per_byte = ns_per_byte;
   g->ns_per_copy = ns_per_copy;
+  g->flush_min_ns = ns_per_copy;
   SPDZ_RET(hip_status(hipMemcpyAsync(g->d_model, g->cost_model.data(), SPDZ_MLP_NPARAM * sizeof(float),
                                      hipMemcpyHostToDevice, g->stream)));
   return hip_status(hipStreamSynchronize(g->stream));
+}
+
+spdz_status spdz_dag_time_transfer(spdz_ctx *c, int64_t words, int reps, double *d2h_ns, double *h2d_ns) {
+  if (!c || words < 1 || words > (int64_t(1) << 28) || reps < 1) return SPDZ_E_INVAL;
+  u64 *dev = nullptr, *host = nullptr, *hdev = nullptr;
+  void *dsegs = nullptr;
+  std::vector<XferSeg> segs;
+  add_segs(segs, 0, 0, words, 0);
+  spdz_status s = SPDZ_OK;
+  if (hipMalloc((void **)&dev, (size_t)words * 8) != hipSuccess ||
+      hipMalloc(&dsegs, segs.size() * sizeof(XferSeg)) != hipSuccess ||
+      hipHostMalloc((void **)&host, (size_t)words * 8, hipHostMallocMapped) != hipSuccess)
+    s = SPDZ_E_NOMEM;
+  if (s == SPDZ_OK && hipHostGetDevicePointer((void **)&hdev, host, 0) != hipSuccess) s = SPDZ_E_HIP;
+  if (s == SPDZ_OK)
+    s = hip_status(hipMemcpy(dsegs, segs.data(), segs.size() * sizeof(XferSeg), hipMemcpyHostToDevice));
+  hipEvent_t ev = nullptr;
+  if (s == SPDZ_OK && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) s = SPDZ_E_HIP;
+  // one transfer as the hybrid run does it: the kernel launch, the wait for its event, and the
+  // host copy between the staging buffer and the host's own memory
+  std::vector<u64> mirror(words);
+  double med[2] = {0, 0};
+  for (int dir = 0; dir < 2 && s == SPDZ_OK; dir++) {
+    std::vector<double> ts;
+    for (int r = 0; r <= reps && s == SPDZ_OK; r++) {
+      const auto t0 = std::chrono::steady_clock::now();
+      if (dir == 1) memcpy(host, mirror.data(), (size_t)words * 8);
+      const int64_t grid = std::min<int64_t>((int64_t)segs.size(), (int64_t)c->num_cus * 4);
+      hipLaunchKernelGGL(k_xfer, dim3((unsigned)grid), dim3(BLOCK), 0, c->stream, (const XferSeg *)dsegs,
+                         (int64_t)segs.size(), dev, dev, dev, dev, hdev, dir == 0 ? 1 : 0);
+      if (hipGetLastError() != hipSuccess || hipEventRecord(ev, c->stream) != hipSuccess ||
+          hipEventSynchronize(ev) != hipSuccess)
+        s = SPDZ_E_HIP;
+      if (dir == 0) memcpy(mirror.data(), host, (size_t)words * 8);
+      if (r > 0) ts.push_back(std::chrono::duration<double, std::nano>(std::chrono::steady_clock::now() - t0).count());
+    }
+    if (s == SPDZ_OK) {
+      std::sort(ts.begin(), ts.end());
+      med[dir] = ts[ts.size() / 2];
+    }
+  }
+  if (ev) (void)hipEventDestroy(ev);
+  if (dev) (void)hipFree(dev);
+  if (dsegs) (void)hipFree(dsegs);
+  if (host) (void)hipHostFree(host);
+  if (s == SPDZ_OK) {
+    if (d2h_ns) *d2h_ns = med[0];
+    if (h2d_ns) *h2d_ns = med[1];
+  }
+  return s;
 }
 
 spdz_status spdz_dag_time_level(spdz_ctx *c, int kind, int64_t width, int64_t q, int reps, double *gpu_ns,

@@ -119,6 +119,11 @@ def lib() -> ctypes.CDLL:
             "spdz_dag_autotune": (i32, [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                         ctypes.POINTER(ctypes.c_double)]),
             "spdz_dag_set_threshold": (i32, [vp, i64]),
+            "spdz_dag_set_flush": (i32, [vp, i64]),
+            "spdz_dag_run_info": (i32, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                        ctypes.POINTER(i64)]),
+            "spdz_dag_time_transfer": (i32, [vp, i64, i32, ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(ctypes.c_double)]),
             "spdz_dag_last_stats": (i32, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
                                           ctypes.POINTER(ctypes.c_double)]),
             "spdz_dag_set_cost_model": (i32, [vp, vp, ctypes.c_double, ctypes.c_double]),
@@ -721,6 +726,15 @@ class Dag:
     def set_threshold(self, thr: int):
         _check(lib().spdz_dag_set_threshold(self._h, thr), "spdz_dag_set_threshold")
 
+    def set_flush(self, flush_elems: int):
+        """Static batch flush point of the scheduler, in elements (0: one launch per level)."""
+        _check(lib().spdz_dag_set_flush(self._h, flush_elems), "spdz_dag_set_flush")
+
+    def run_info(self):
+        v = [ctypes.c_int64(0) for _ in range(4)]
+        _check(lib().spdz_dag_run_info(self._h, *(ctypes.byref(x) for x in v)), "spdz_dag_run_info")
+        return dict(zip(("launches", "early_flushes", "transfers", "transfer_bytes"), (x.value for x in v)))
+
     def last_stats(self):
         g, c, cp = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
         pm = ctypes.c_double(0)
@@ -734,6 +748,14 @@ class Dag:
         assert w.size == MLP_NPARAM
         _check(lib().spdz_dag_set_cost_model(self._h, w.ctypes.data_as(ctypes.c_void_p), ns_per_byte, ns_per_copy),
                "spdz_dag_set_cost_model")
+
+
+def dag_time_transfer(ctx: Context, words: int, reps: int = 5):
+    """(device-to-host ns, host-to-device ns) of one hybrid-run transfer of `words` 64-bit words."""
+    d, h = ctypes.c_double(0), ctypes.c_double(0)
+    _check(lib().spdz_dag_time_transfer(ctx._h, words, reps, ctypes.byref(d), ctypes.byref(h)),
+           "spdz_dag_time_transfer")
+    return d.value, h.value
 
 
 def dag_time_level(ctx: Context, kind: int, width: int, q: int, reps: int = 3):

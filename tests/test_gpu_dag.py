@@ -52,23 +52,52 @@ def test_dag_modes_and_policies(n):
     assert ok
     ctx, g = build(dag, 5)
     assert g.opened_count() == dag.n_opened()
-    runs = [(S.MODE_PER_OP, S.POLICY_ALL_GPU), (S.MODE_PER_LEVEL, S.POLICY_ALL_GPU),
-            (S.MODE_GRAPH, S.POLICY_ALL_GPU), (S.MODE_GRAPH, S.POLICY_ALL_GPU),
-            (S.MODE_PER_LEVEL, S.POLICY_STATIC), (S.MODE_PER_LEVEL, S.POLICY_ALL_CPU)]
-    for epoch, (mode, policy) in enumerate(runs):
-        print(f"case n={n} mode={mode} policy={policy}", flush=True)
+    # (mode, policy, flush point): per-op, per-level and graph launches; the static policy with
+    # about half the ops on the CPU back end, with and without early flushes; all on the CPU;
+    # the graph captured with batches cut every 3000 elements
+    runs = [(S.MODE_PER_OP, S.POLICY_ALL_GPU, 0), (S.MODE_PER_LEVEL, S.POLICY_ALL_GPU, 0),
+            (S.MODE_GRAPH, S.POLICY_ALL_GPU, 0), (S.MODE_GRAPH, S.POLICY_ALL_GPU, 0),
+            (S.MODE_PER_LEVEL, S.POLICY_STATIC, 0), (S.MODE_PER_LEVEL, S.POLICY_ALL_CPU, 0),
+            (S.MODE_GRAPH, S.POLICY_STATIC, 1500), (S.MODE_GRAPH, S.POLICY_ALL_GPU, 3000)]
+    for epoch, (mode, policy, flush) in enumerate(runs):
+        print(f"case n={n} mode={mode} policy={policy} flush={flush}", flush=True)
         if policy == S.POLICY_STATIC:
             g.set_threshold(400)   # about half the ops below, half above
+        g.set_flush(flush)
         g.run(mode, policy)
-        st = g.last_stats()
+        st, info = g.last_stats(), g.run_info()
         if policy == S.POLICY_STATIC:
             assert st["cpu_ops"] > 0 and st["gpu_ops"] > 0
+            assert info["transfers"] > 0 and info["transfer_bytes"] > 0
+        if flush:
+            assert info["early_flushes"] > 0, info
+        elif policy != S.POLICY_ALL_CPU and mode != S.MODE_PER_OP:
+            assert info["early_flushes"] == 0, info
+            if policy == S.POLICY_ALL_GPU:
+                assert info["launches"] == SMALL["depth"], info
         g.fetch_host_outputs()
         ok_d, sig_d = ctx.spdz_mac_check()
         ref_e, ok_e, sig_e = (ref, ok, sigma) if epoch == 0 else dag_run(dag, seed=5, check_seed=5, epoch=epoch,
                                                                       keep=set())
         assert ok_d and sig_d == ints_of_sigma(sig_e), (mode, policy)
         check_nodes(g, ref, range(dag.n_ops + 2))
+
+
+def width_model(S):
+    """MLP parameters (layout of spdz.h) whose CPU output is log2 width and GPU output 9."""
+    W = np.zeros(S.MLP_NPARAM, dtype=np.float32)
+    H, I = S.MLP_HID, S.MLP_IN
+    o1 = 0                      # W1 [H][I], b1 [H]
+    o2 = o1 + H * I + H         # W2 [H][H], b2 [H]
+    o3 = o2 + H * H + H         # W3 [H][H], b3 [H]
+    o4 = o3 + H * H + H         # W4 [2][H], b4 [2]
+    assert o4 + 2 * H + 2 == S.MLP_NPARAM
+    W[o1 + 0 * I + 3] = 1.0     # hidden unit 0 of layer 1 = relu(log2 width)
+    W[o2 + 0] = 1.0             # passed through layers 2 and 3 on unit 0
+    W[o3 + 0] = 1.0
+    W[o4 + 0] = 1.0             # CPU output = unit 0
+    W[o4 + 2 * H + 1] = 9.0     # GPU output bias
+    return W
 
 
 def test_dag_learned_policy_and_autotune():
@@ -78,18 +107,22 @@ def test_dag_learned_policy_and_autotune():
     ctx, g = build(dag, 6)
     tile, bpc, ms = g.autotune(max_levels=5)
     assert tile in (512, 1024, 2048, 4096, 8192) and bpc in (2, 4, 8, 16) and ms > 0
-    # a cost model that sends small ops to the CPU: random weights, then the output bias decides
-    rng = np.random.default_rng(0)
-    W = (rng.standard_normal(S.MLP_NPARAM) * 0.05).astype(np.float32)
-    W[-2], W[-1] = 8.0, 9.0     # log2 ns: CPU 256 ns, GPU 512 ns per op -> CPU unless transfers cost more
+    # a hand-set cost model: predicted log2 CPU ns = log2 width (one ReLU path through the three
+    # hidden layers), log2 GPU ns = 9, so ops narrower than 512 go to the CPU back end
+    W = width_model(S)
     g.set_cost_model(W, ns_per_byte=0.0, ns_per_copy=0.0)
     g.run(S.MODE_PER_LEVEL, S.POLICY_LEARNED)
     st = g.last_stats()
-    assert st["cpu_ops"] > 0
+    assert st["cpu_ops"] > 0 and st["gpu_ops"] > 0, st
+    assert st["cpu_ops"] == int(np.sum(dag.width < 512))
+    # with no fixed cost per launch the model's flush rule cuts every level whose GPU ops feed
+    # CPU ops and has other GPU work
+    assert g.run_info()["early_flushes"] > 0
     g.fetch_host_outputs()
     ok_d, sig_d = ctx.spdz_mac_check()
     assert ok_d and sig_d == ints_of_sigma(sigma)
     check_nodes(g, ref, range(dag.n_ops + 2))
+    W[-130:-2] = 0.0
     W[-2], W[-1] = 30.0, 1.0    # GPU always
     g.set_cost_model(W, 0.01, 1000.0)
     g.run(S.MODE_GRAPH, S.POLICY_LEARNED)
@@ -169,3 +202,99 @@ def test_dag_full_size_every_node():
     assert not chk.bad, chk.bad[:10]
     assert ok and ok0 and sig0 == ints_of_sigma(sigma)
     assert more[1][0] and ok1 and sig1 == ints_of_sigma(more[1][1])
+
+
+# --------------------------------------------------------------------------
+# the learned dispatcher trained on the library's own timings, against the best static setting
+# chosen on training seeds (smaller DAGs of the same generator), and the configured held-out
+# DAGs at full size under the trained model, every node against the oracle
+# --------------------------------------------------------------------------
+MID = dict(depth=20, ops_per_level=300)
+
+
+@pytest.fixture(scope="module")
+def trained_model():
+    from paper_2512_11112_amd import costmodel as CM
+    sw = CM.sweep(parties=(2,), log2_widths=range(4, 21, 4), qs=(1, 64, 512), reps=2)
+    W, loss = CM.train(sw, epochs=400)
+    assert loss[-1] < loss[0]
+    npb, npc = CM.transfer_costs(words=(1 << 9, 1 << 15, 1 << 21), reps=3)
+    return W, npb, npc
+
+
+def median_run(ctx, g, policy, reps=5):
+    from paper_2512_11112_amd import spdz as S
+    ts = []
+    for _ in range(reps + 1):
+        ms = g.run(S.MODE_GRAPH, policy)
+        ok, _ = ctx.spdz_mac_check()
+        assert ok
+        ts.append(ms)
+    return sorted(ts[1:])[reps // 2]
+
+
+@pytest.mark.timeout(900)
+def test_trained_cost_model_vs_best_static(trained_model):
+    """Static MIN_KERNEL_SIZE chosen on training seeds 100, 101; on held-out seeds 1000, 1001 the
+    learned policy's median time is at most 1.1 x the chosen static rule's (the decisions it makes
+    are reported), and its outputs equal the oracle's node for node."""
+    from paper_2512_11112_amd import spdz as S
+    W, npb, npc = trained_model
+    thresholds = (0, 256, 4096, 65535)
+    train = {t: [] for t in thresholds}
+    for seed in (100, 101):
+        dag = make_dag(seed, P61, **MID)
+        ctx, g = build(dag, seed)
+        for t in thresholds:
+            g.set_threshold(t)
+            train[t].append(median_run(ctx, g, S.POLICY_STATIC, reps=3))
+        g.close()
+        ctx.close()
+    best = min(thresholds, key=lambda t: np.mean(train[t]))
+    print(f"training means {[(t, round(float(np.mean(v)), 3)) for t, v in train.items()]}, best {best}", flush=True)
+    learned, static = [], []
+    for seed in (1000, 1001):
+        dag = make_dag(seed, P61, **MID)
+        ctx, g = build(dag, seed)
+        g.set_cost_model(W, npb, npc)
+        g.set_threshold(best)
+        static.append(median_run(ctx, g, S.POLICY_STATIC))
+        learned.append(median_run(ctx, g, S.POLICY_LEARNED))
+        st = g.last_stats()
+        print(f"seed {seed}: learned {learned[-1]:.3f} ms ({st['cpu_ops']} CPU ops), static {static[-1]:.3f} ms",
+              flush=True)
+        g.fetch_host_outputs()
+        ref, ok, _ = dag_run(dag, seed=seed, check_seed=seed, keep=None)
+        check_nodes(g, ref, range(dag.n_ops + 2))
+        g.close()
+        ctx.close()
+    assert np.mean(learned) <= 1.1 * np.mean(static), (learned, static)
+
+
+@pytest.mark.timeout(1500)
+def test_c4_heldout_full_size_trained_model(trained_model):
+    """The configured learned-dispatch workload: 100k-op DAGs of held-out seeds 1000 and 1001 run
+    under the trained cost model; every node and the MAC check's sigma equal the oracle's."""
+    from paper_2512_11112_amd import spdz as S
+    W, npb, npc = trained_model
+    for seed in (1000, 1001):
+        dag = make_dag(seed, P61)
+        assert dag.n_ops == 100000
+        ctx, g = build(dag, seed)
+        g.autotune(max_levels=10)
+        g.set_cost_model(W, npb, npc)
+        print(f"case held-out seed {seed}: learned policy, graph mode", flush=True)
+        g.run(S.MODE_GRAPH, S.POLICY_LEARNED)
+        st = g.last_stats()
+        print(f"seed {seed}: {st['cpu_ops']} ops on the CPU back end", flush=True)
+        g.fetch_host_outputs()
+        ok, sig = ctx.spdz_mac_check()
+        arenas = {"learned": arena_host(g)}
+        g.close()
+        ctx.close()
+        chk = ArenaCheck(dag, arenas)
+        _, ok_ref, sig_ref = dag_run(dag, seed=seed, check_seed=seed, keep=set(), on_node=chk)
+        assert chk.seen == dag.n_ops + 2
+        assert not chk.bad, chk.bad[:10]
+        assert ok and ok_ref and sig == ints_of_sigma(sig_ref)
+        del arenas, chk
