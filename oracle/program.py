@@ -168,8 +168,8 @@ def infer(prog: Program):
             din, dout, tr = n.imm
             if (x.width, W.width, b.width) != (din, din * dout, dout) or tr < 1:
                 raise ProgramError(f"node {nid}: layer shapes")
-            if not (x.secret and W.secret and b.secret):
-                raise ProgramError(f"node {nid}: layer operands must be secret")
+            if not (x.secret and W.secret):
+                raise ProgramError(f"node {nid}: layer x and W must be secret")
     for b in prog.blocks.values():
         if b.term[0] == "cbr":
             c = nodes[b.term[1]]
@@ -298,6 +298,8 @@ class Exec:
             self.count[nd.id] = k + 1
             T = deal_matvec_triple(f, self.n, self.seed, triple_array(nd.id, k), dout, din, tr, self.al)
             x, W, b = (self.val[i] for i in nd.args)
+            if not nodes[nd.args[2]].secret:   # a public bias is a public constant of the sum
+                b = self.share_pub(self.pub(nd.args[2], dout))
             D = DealtLayer(f, self.n, self.seed, dout, din, tr, self.al, None, W, None, x, None, b, T)
             yv, ym = [], []
             for t in range(D.n_tiles):

@@ -67,6 +67,7 @@ struct PNode {
   spdz_triple tri{};     // product / layer triples dealt during the run
   std::vector<spdz_triple> pool;  // triples dealt ahead (spdz_prog_predeal), by execution number
   u64 *ltmp = nullptr;   // layer dealer: public A, B, C
+  spdz_shares bsh{};     // layer with a public bias: its sharing (party 0 holds it, MACs alpha_i b)
   // run state
   int64_t inst = 0;
   bool pending = false, queued = false, dev_ready = false, host_ready = false, await_host = false;
@@ -354,7 +355,7 @@ spdz_status infer(spdz_prog *g) {
     if (n.op == OP_LAYER) {
       const PNode &x = N[n.args[0]], &W = N[n.args[1]], &b = N[n.args[2]];
       if (x.width != n.imm[0] || W.width != n.imm[0] * n.imm[1] || b.width != n.imm[1]) return fail(g, nm + "layer shapes");
-      if (!x.secret || !W.secret || !b.secret) return fail(g, nm + "layer operands must be secret");
+      if (!x.secret || !W.secret) return fail(g, nm + "layer x and W must be secret");
       if (g->c->L != 1) return fail(g, nm + "layers need a single-limb field");
     }
   }
@@ -397,6 +398,8 @@ spdz_status infer(spdz_prog *g) {
         } else if (n.op == OP_PHI) {
           for (auto &pv : n.phi)
             if (!N[pv.first].secret) N[pv.first].dev_use = true;
+        } else if (n.op == OP_LAYER && !N[n.args[2]].secret) {
+          N[n.args[2]].dev_use = true;  // a public bias is shared on the device
         }
       }
     }
@@ -618,6 +621,7 @@ spdz_status alloc_buffers(spdz_prog *g) {
       SPDZ_RET(alloc_shares(g, n.tri.b, tiles * din));
       SPDZ_RET(alloc_shares(g, n.tri.c, dout));
       if (hipMalloc((void **)&n.ltmp, (size_t)(dout * din + tiles * din + dout) * 8) != hipSuccess) return SPDZ_E_NOMEM;
+      if (!g->nodes[n.args[2]].secret) SPDZ_RET(alloc_shares(g, n.bsh, dout));
     }
   }
   return SPDZ_OK;
@@ -973,7 +977,13 @@ spdz_status issue(spdz_prog *g, PNode &n) {
       spdz_triple *t = nullptr;
       st = node_triple(g, n, t);
       c->log_count = n.log_off;
-      if (st == SPDZ_OK) st = launch_linear_layer(c, dout, din, tr, &W.sh, &x.sh, &b.sh, t, &n.sh, nullptr, nullptr, nullptr);
+      const spdz_shares *bs = &b.sh;
+      if (st == SPDZ_OK && !b.secret) {  // a public bias enters as a constant: share(b) then the layer
+        st = launch_pubop(c, SPDZ_PUB_SHARE, nullptr, b.dpub, b.width, &n.bsh);
+        bs = &n.bsh;
+        g->launches++;
+      }
+      if (st == SPDZ_OK) st = launch_linear_layer(c, dout, din, tr, &W.sh, &x.sh, bs, t, &n.sh, nullptr, nullptr, nullptr);
       g->launches += 2;
       break;
     }
@@ -1092,6 +1102,7 @@ void destroy(spdz_prog *g) {
     free_shares(n.tri.a);
     free_shares(n.tri.b);
     free_shares(n.tri.c);
+    free_shares(n.bsh);
     for (auto &t : n.pool) {
       free_shares(t.a);
       free_shares(t.b);

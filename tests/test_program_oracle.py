@@ -76,7 +76,7 @@ def plain_run(text: str, p: int, seed: int):
 PROGRAMS = [("pipeline", P.pipeline(37)), ("branch", P.branch(21)), ("loop", P.loop(13, 4)),
             ("nested", P.nested(9, 3)), ("select_shl_load", P.select_shl_load(40, 10, 7)),
             ("revealed_branch", P.revealed_branch(11)), ("opened_operand", P.opened_operand(10)),
-            ("layer", P.layer(9, 7, 3)),
+            ("layer", P.layer(9, 7, 3)), ("layer_public_bias", P.layer_public_bias(9, 7, 3)),
             ("loop_program", P.loop_program(16, 3))]
 
 

@@ -21,7 +21,10 @@ Text format (one statement per line, '#' starts a comment, ids are integers):
     <id> = load <base> <start> <count>  elements start .. start+count-1 of base; <start> is a
                                         public scalar node
     <id> = phi <v1> <b1> [<v2> <b2> ...]  value vk when the block was entered from block bk
-    <id> = layer <x> <W> <b> <din> <dout> <tile_rows>   private linear layer W x + b
+    <id> = layer <x> <W> <b> <din> <dout> <tile_rows>   linear layer W x + b, x and W
+                                        secret; b secret or public (a public b enters as
+                                        a public constant: party 0 adds it, every MAC
+                                        share alpha_i b)
     br <bid>                            terminators: one per block, last line of the block
     cbr <cond> <bid_true> <bid_false>   cond a public scalar; nonzero selects bid_true
     ret
@@ -259,6 +262,21 @@ block 0
 4 = layer 1 2 3 {din} {dout} {tile_rows}
 5 = mul 4 4
 6 = open 5
+ret
+"""
+
+
+def layer_public_bias(din: int, dout: int, tile_rows: int) -> str:
+    """y = W x + b with a public bias b (the paper's Fig. 2 annotations), y opened."""
+    return f"""
+input 1 private {din} 0
+input 2 private {din * dout} 1
+input 3 public {dout} 2
+output 4
+output 5
+block 0
+4 = layer 1 2 3 {din} {dout} {tile_rows}
+5 = open 4
 ret
 """
 
