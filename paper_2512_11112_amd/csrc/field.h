@@ -247,13 +247,12 @@ struct F32 {
   struct E {
     u32 v;
   };
-  // exact sum hi 2^64 + lo of products (each < 2^64) and residues: one carry per term at most,
-  // so hi counts at most 2^32 - 1 of them
+  // exact sum of products and residues in two 64-bit halves: a b = a (b mod 2^16) + 2^16 a (b >> 16),
+  // each part below 2^48, so 2^16 terms fit either half with no carry to track
   struct Wide {
-    u64 lo;
-    u32 hi;
+    u64 lo, hi;
   };
-  static constexpr int WIDE_TERMS = 1 << 28;
+  static constexpr int WIDE_TERMS = 1 << 15;
 
   SPDZ_HD static E zero() { return {0}; }
   SPDZ_HD static u64 fold(u64 x) { return 5 * (x >> 32) + (x & 0xffffffffull); }  // < 6 * 2^32
@@ -283,20 +282,14 @@ struct F32 {
   }
   SPDZ_HD static E norm(E a) { return a; }
   SPDZ_HD static Wide wzero() { return {0, 0}; }
-  // a 32 x 32 -> 64-bit product added with its carry: one multiply-add and one add-with-carry
+  // two multiply-adds; the halves of b are shared by every product with the same b
   SPDZ_HD static void wmac(Wide &w, E a, E b) {
-    const u64 p = (u64)a.v * b.v;
-    const u64 s = w.lo + p;
-    w.hi += s < p;
-    w.lo = s;
+    w.lo += (u64)a.v * (b.v & 0xffffu);
+    w.hi += (u64)a.v * (b.v >> 16);
   }
-  SPDZ_HD static void wadd(Wide &w, E a) {
-    const u64 s = w.lo + a.v;
-    w.hi += s < a.v;
-    w.lo = s;
-  }
-  // 2^64 = 25 (mod p): hi 2^64 + lo = 25 hi + (lo mod p), below 2^37
-  SPDZ_HD static E wreduce(Wide w) { return reduce((u64)reduce(w.lo).v + 25ull * w.hi); }
+  SPDZ_HD static void wadd(Wide &w, E a) { w.lo += a.v; }
+  // lo + 2^16 hi, each half reduced first: below 2^32 + 2^48
+  SPDZ_HD static E wreduce(Wide w) { return reduce((u64)reduce(w.lo).v + ((u64)reduce(w.hi).v << 16)); }
 
   __device__ __forceinline__ static E load(const u64 *base, int64_t /*limb_stride*/, int64_t idx) {
     return {(u32)__builtin_nontemporal_load(base + idx)};
