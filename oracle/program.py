@@ -224,7 +224,7 @@ class Exec:
             src = [v for v, b in nd.phi if b == pred]
             if not src:
                 raise ProgramError(f"phi {nd.id}: no value for predecessor {pred}")
-            v = self.val[src[0]]
+            v = self.at_entry[src[0]]   # the value held when the block was entered
             if nd.secret and not isinstance(v, F.Shares):
                 v = self.share_pub(v)
             self.val[nd.id] = v
@@ -327,6 +327,7 @@ class Exec:
             if self.entries > MAX_BLOCK_ENTRIES:
                 raise ProgramError("too many block entries")
             b = prog.blocks[blk]
+            self.at_entry = dict(self.val)   # phis read these, all at once
             for nid in b.lines:
                 self.run_node(prog.nodes[nid], pred)
             if b.term[0] == "ret":

@@ -46,6 +46,10 @@ constexpr int64_t MAX_ENTRIES = 1000000;
 
 enum Op { OP_INPUT, OP_CONST, OP_ADD, OP_SUB, OP_MUL, OP_LT, OP_EQ, OP_REDUCE, OP_OPEN, OP_LOAD, OP_PHI, OP_LAYER };
 
+// a phi that another phi of its block reads keeps its previous value here while the
+// phis of a new entry are copied (phis reading each other in a cycle)
+int hold_id(int phi) { return phi + 3 * AUX; }
+
 u64 triple_array(int node, int64_t instance) { return PROG_TRIPLE0 + 3 * ((u64)node + NODE_STRIDE * (u64)instance); }
 
 struct PNode {
@@ -406,6 +410,20 @@ spdz_status infer(spdz_prog *g) {
   }
   for (int o : g->outputs)
     if (!N[o].secret) N[o].dev_use = true;
+  // a hold for each phi that another phi of its block reads
+  std::vector<int> held;
+  for (int b : g->block_order)
+    for (int id : g->blocks[b].lines)
+      if (N[id].op == OP_PHI)
+        for (auto &pv : N[id].phi)
+          if (N[pv.first].op == OP_PHI && N[pv.first].block == b && pv.first != id) held.push_back(pv.first);
+  for (int c : held) {
+    PNode h;
+    h.id = hold_id(c), h.op = OP_PHI, h.width = N[c].width;
+    h.secret = h.device = N[c].secret;
+    h.dev_use = !h.secret;
+    N[h.id] = h;
+  }
   return SPDZ_OK;
 }
 
@@ -713,26 +731,82 @@ void enqueue(spdz_prog *g, PNode &n) {
   (n.heavy ? g->heavy : g->light).push_back(n.id);
 }
 
+spdz_status copy_phi(spdz_prog *g, PNode &n);
+spdz_status settle_opens(spdz_prog *g);
+spdz_status upload(spdz_prog *g, PNode &n);
+spdz_status copy_shares(spdz_prog *g, const spdz_shares &src, int64_t first, spdz_shares &dst);
+
+// The phis of a block take the values their sources held when the block was entered (all
+// at once).  A source that is a node of the entered block itself (the back edge of a loop
+// whose body is one block, or another phi of the block) is about to be recomputed, so those
+// phis are copied here, before any node of the new entry runs; the rest wait for their
+// sources in the queues like any node.
 spdz_status enter_block(spdz_prog *g, int dst, int pred) {
   if (++g->entries > MAX_ENTRIES) return fail(g, "too many block entries");
   PBlock &B = g->blocks[dst];
   auto &N = g->nodes;
+  std::vector<int> now;  // phis copied at entry
   for (int id : B.lines) {
     PNode &n = N[id];
     if (n.pending) return fail(g, "block " + std::to_string(dst) + " re-entered before node " + std::to_string(id) + " ran");
-    n.inst++;
-    n.pending = true;
-    n.queued = n.dev_ready = n.host_ready = n.await_host = false;
-    n.log_off = g->log_cur + n.log_static;
-    if (n.op == OP_PHI) {
-      n.phi_src = -1;
-      for (auto &pv : n.phi)
-        if (pv.second == pred) {
-          n.phi_src = pv.first;
-          break;
+    if (n.op != OP_PHI) continue;
+    n.phi_src = -1;
+    for (auto &pv : n.phi)
+      if (pv.second == pred) {
+        n.phi_src = pv.first;
+        break;
+      }
+    if (n.phi_src < 0) return fail(g, "phi " + std::to_string(id) + ": no value for predecessor block " + std::to_string(pred));
+    if (N[n.phi_src].block == dst) now.push_back(id);
+  }
+  if (!now.empty()) {
+    bool wait = false;  // a public phi of an opened value needs its host words
+    for (int id : now) wait = wait || (!N[id].secret && !N[N[id].phi_src].host_ready);
+    if (wait) SPDZ_RET(settle_opens(g));
+    // copied in an order where no copy overwrites a phi that a later copy still reads
+    std::vector<int> left = now;
+    while (!left.empty()) {
+      size_t k = 0;
+      for (; k < left.size(); k++) {
+        bool read = false;
+        for (int o : left) read = read || (o != left[k] && N[o].phi_src == left[k]);
+        if (!read) break;
+      }
+      if (k == left.size()) {  // phis that read each other in a cycle: one value is held aside first
+        PNode &c = N[left[0]];
+        PNode &h = N[hold_id(c.id)];
+        if (c.secret) {
+          SPDZ_RET(copy_shares(g, c.sh, 0, h.sh));
+        } else {
+          std::memcpy(h.hpub, c.hpub, (size_t)g->c->L * c.width * 8);
+          SPDZ_RET(upload(g, h));
         }
-      if (n.phi_src < 0) return fail(g, "phi " + std::to_string(id) + ": no value for predecessor block " + std::to_string(pred));
+        h.dev_ready = true;
+        h.host_ready = !c.secret;
+        for (int o : left)
+          if (N[o].phi_src == c.id) N[o].phi_src = h.id;
+        continue;
+      }
+      PNode &n = N[left[k]];
+      const PNode &s = N[n.phi_src];
+      if (n.secret ? !s.dev_ready : !s.host_ready) return fail(g, "phi " + std::to_string(n.id) + ": source not computed");
+      if (n.phi_src != n.id) SPDZ_RET(copy_phi(g, n));  // a phi of itself keeps its value
+      left.erase(left.begin() + k);
     }
+  }
+  for (int id : B.lines) {
+    PNode &n = N[id];
+    n.inst++;
+    n.queued = n.await_host = false;
+    n.log_off = g->log_cur + n.log_static;
+    if (std::find(now.begin(), now.end(), id) != now.end()) {  // copied above
+      n.pending = false;
+      n.dev_ready = true;
+      n.host_ready = !n.device;
+      continue;
+    }
+    n.pending = true;
+    n.dev_ready = n.host_ready = false;
     g->pending_total++;
     for (int l : B.loops) g->loops[l].outstanding++;
   }
@@ -857,6 +931,32 @@ spdz_status issue_group(spdz_prog *g, FGroup &G) {
   return SPDZ_OK;
 }
 
+// a phi's value: the source's words (public), its shares (secret), or a public source shared
+spdz_status copy_phi(spdz_prog *g, PNode &n) {
+  spdz_ctx *c = g->c;
+  PNode &s = g->nodes[n.phi_src];
+  if (!n.secret) {
+    std::memcpy(n.hpub, s.hpub, (size_t)c->L * n.width * 8);
+    return n.dev_use ? upload(g, n) : SPDZ_OK;
+  }
+  if (s.secret) return copy_shares(g, s.sh, 0, n.sh);
+  g->launches++;
+  return launch_pubop(c, SPDZ_PUB_SHARE, nullptr, s.dpub, s.width, &n.sh);
+}
+
+// waits for the stream; the host words of every open issued so far are then valid
+spdz_status settle_opens(spdz_prog *g) {
+  auto &N = g->nodes;
+  SPDZ_RET(stream_sync(g));
+  for (auto &kv : N)
+    if (kv.second.await_host) {
+      kv.second.await_host = false;
+      kv.second.host_ready = true;
+      for (int u : kv.second.users) enqueue(g, N[u]);
+    }
+  return SPDZ_OK;
+}
+
 spdz_status issue(spdz_prog *g, PNode &n) {
   spdz_ctx *c = g->c;
   auto &N = g->nodes;
@@ -958,19 +1058,7 @@ spdz_status issue(spdz_prog *g, PNode &n) {
       }
       break;
     }
-    case OP_PHI: {
-      PNode &s = N[n.phi_src];
-      if (!n.secret) {
-        std::memcpy(n.hpub, s.hpub, (size_t)L * n.width * 8);
-        if (n.dev_use) st = upload(g, n);
-      } else if (s.secret) {
-        st = copy_shares(g, s.sh, 0, n.sh);
-      } else {
-        st = launch_pubop(c, SPDZ_PUB_SHARE, nullptr, s.dpub, s.width, &n.sh);
-        g->launches++;
-      }
-      break;
-    }
+    case OP_PHI: st = copy_phi(g, n); break;
     case OP_LAYER: {
       PNode &x = N[n.args[0]], &W = N[n.args[1]], &b = N[n.args[2]];
       const int64_t din = n.imm[0], dout = n.imm[1], tr = n.imm[2];
@@ -1012,6 +1100,8 @@ spdz_status try_branch(spdz_prog *g, bool &taken, bool &done) {
     const bool nz = cnd.hpub[0] != 0 || (g->c->L == 2 && cnd.hpub[1] != 0);
     dst = nz ? B.t : B.f;
   }
+  for (int id : g->blocks[dst].lines)
+    if (g->nodes[id].pending) return SPDZ_OK;  // its previous entry is still being issued
   taken = true;
   return enter_block(g, dst, B.id);
 }
@@ -1052,13 +1142,7 @@ spdz_status run(spdz_prog *g) {
       bool waiting = false;
       for (auto &kv : N) waiting = waiting || kv.second.await_host;
       if (!waiting) return fail(g, "no node can proceed");
-      SPDZ_RET(stream_sync(g));
-      for (auto &kv : N)
-        if (kv.second.await_host) {
-          kv.second.await_host = false;
-          kv.second.host_ready = true;
-          for (int u : kv.second.users) enqueue(g, N[u]);
-        }
+      SPDZ_RET(settle_opens(g));
     }
   }
   c->log_count = g->log_cur;

@@ -31,7 +31,8 @@ PROGRAMS = [("pipeline", P.pipeline(3001)), ("branch", P.branch(777)), ("loop", 
             ("nested", P.nested(257, 3)), ("select_shl_load", P.select_shl_load(4099, 1000, 77)),
             ("revealed_branch", P.revealed_branch(513)), ("opened_operand", P.opened_operand(3001)),
             ("layer", P.layer(300, 70, 16)), ("layer_public_bias", P.layer_public_bias(300, 70, 16)),
-            ("loop_program", P.loop_program(2048, 4))]
+            ("loop_program", P.loop_program(2048, 4)), ("one_block_loop", P.one_block_loop(1000, 5)),
+            ("phi_swap", P.phi_swap(777, 4))]
 
 
 @pytest.mark.parametrize("fuse", [True, False])

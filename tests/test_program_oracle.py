@@ -34,11 +34,12 @@ def plain_run(text: str, p: int, seed: int):
     while True:
         entries += 1
         b = prog.blocks[blk]
+        at_entry = dict(val)
         for nid in b.lines:
             nd = prog.nodes[nid]
             w = nd.width
             if nd.op == "phi":
-                val[nid] = val[[v for v, bb in nd.phi if bb == pred][0]]
+                val[nid] = at_entry[[v for v, bb in nd.phi if bb == pred][0]]
             elif nd.op in ("add", "sub", "mul"):
                 x, y = get(nd.args[0], w), get(nd.args[1], w)
                 op = {"add": lambda a, c: (a + c) % p, "sub": lambda a, c: (a - c) % p,
@@ -77,7 +78,8 @@ PROGRAMS = [("pipeline", P.pipeline(37)), ("branch", P.branch(21)), ("loop", P.l
             ("nested", P.nested(9, 3)), ("select_shl_load", P.select_shl_load(40, 10, 7)),
             ("revealed_branch", P.revealed_branch(11)), ("opened_operand", P.opened_operand(10)),
             ("layer", P.layer(9, 7, 3)), ("layer_public_bias", P.layer_public_bias(9, 7, 3)),
-            ("loop_program", P.loop_program(16, 3))]
+            ("loop_program", P.loop_program(16, 3)), ("one_block_loop", P.one_block_loop(12, 4)),
+            ("phi_swap", P.phi_swap(6, 5))]
 
 
 @pytest.mark.parametrize("p,n", [(P_PAPER, 2), (P61, 3), (P_TINY, 2)])
@@ -116,6 +118,41 @@ def test_loop_closed_form():
     want = [(x[e] * pow(y[e], T, p) + sum(i * pow(y[e], T - 1 - i, p) for i in range(T))) % p for e in range(W)]
     assert [int(v) for v in F.from_limbs(res["outputs"][12])] == want
     assert res["entries"] == 1 + (T + 1) + T + 1
+
+
+@pytest.mark.parametrize("T", [1, 2, 5])
+def test_one_block_loop_recurrence(T):
+    """The one-block loop against its recurrence in Python integers: phis read the values
+    held at the block's entry, so b gets a's previous value (reading a's new value instead,
+    or s's before the open, changes the result)."""
+    p, W = P_PAPER, 6
+    res = run_program(P.one_block_loop(W, T), p, 2, 7, 7)
+    f = F.Field(p)
+    a = [int(v) for v in F.from_limbs(f.deal_values(7, 0, W))]
+    b = [int(v) for v in F.from_limbs(f.deal_values(7, 1, W))]
+    s = 0
+    for _ in range(T):
+        b_entry = b                      # phi 12 at this entry
+        a_next = [(a[e] * b[e] + s) % p for e in range(W)]
+        a, b, s = a_next, a, sum(a_next) % p
+    assert [int(v) for v in F.from_limbs(res["outputs"][20])] == a
+    got_b = res["outputs"][12]
+    assert [sum(int(got_b.val[i, 0, e]) for i in range(2)) % p for e in range(W)] == b_entry
+    assert res["entries"] == 1 + T + 1 and res["ok"]
+
+
+@pytest.mark.parametrize("T", [1, 2, 3, 6])
+def test_phi_swap_exchanges(T):
+    """Two phis reading each other exchange their values on every back edge."""
+    p, W = P61, 5
+    res = run_program(P.phi_swap(W, T), p, 2, 2, 2)
+    f = F.Field(p)
+    x = [int(v) for v in F.from_limbs(f.deal_values(2, 0, W))]
+    y = [int(v) for v in F.from_limbs(f.deal_values(2, 1, W))]
+    a = x if (T - 1) % 2 == 0 else y
+    got = res["outputs"][11]
+    assert [sum(int(got.val[i, 0, e]) for i in range(2)) % p for e in range(W)] == a
+    assert [int(v) for v in F.from_limbs(res["outputs"][15])] == [x[e] * y[e] % p for e in range(W)]
 
 
 def test_nested_entries_follow_the_inner_trip_counts():

@@ -20,7 +20,11 @@ Text format (one statement per line, '#' starts a comment, ids are integers):
     <id> = open <a>                     reveal a secret value (public result)
     <id> = load <base> <start> <count>  elements start .. start+count-1 of base; <start> is a
                                         public scalar node
-    <id> = phi <v1> <b1> [<v2> <b2> ...]  value vk when the block was entered from block bk
+    <id> = phi <v1> <b1> [<v2> <b2> ...]  value vk when the block was entered from block bk:
+                                        vk as it was at that entry, also where vk is a node
+                                        of the block itself (a loop of one block) or another
+                                        phi of it (the phis of a block read their values
+                                        all at once, as LLVM's do)
     <id> = layer <x> <W> <b> <din> <dout> <tile_rows>   linear layer W x + b, x and W
                                         secret; b secret or public (a public b enters as
                                         a public constant: party 0 adds it, every MAC
@@ -128,6 +132,66 @@ block 2
 br 1
 block 3
 12 = open 6
+ret
+"""
+
+
+def one_block_loop(W: int, trips: int) -> str:
+    """A loop whose body is one block branching back to itself (the shape clang -O2 gives a
+    counted loop): a, b, s = x, y, 0, then trips times a, b, s = a b + s, a, sum(a b + s),
+    the sum opened each trip.  b's phi reads a's phi (its value at the entry), s's phi the
+    open of the previous trip; the final a is opened."""
+    return f"""
+input 1 private {W} 0
+input 2 private {W} 1
+const 3 1 {trips}
+const 4 1 0
+const 5 1 1
+output 12
+output 20
+block 0
+br 1
+block 1
+10 = phi 4 0 17 1
+11 = phi 1 0 14 1
+12 = phi 2 0 11 1
+13 = phi 4 0 16 1
+18 = mul 11 12
+14 = add 18 13
+15 = reduce 14
+16 = open 15
+17 = add 10 5
+19 = lt 17 3
+cbr 19 1 2
+block 2
+20 = open 14
+ret
+"""
+
+
+def phi_swap(W: int, trips: int) -> str:
+    """a, b = x, y, then trips - 1 times a, b = b, a in a one-block loop: two phis that read
+    each other; a b opened at the end."""
+    return f"""
+input 1 private {W} 0
+input 2 private {W} 1
+const 3 1 {trips}
+const 4 1 0
+const 5 1 1
+output 11
+output 15
+block 0
+br 1
+block 1
+10 = phi 4 0 13 1
+11 = phi 1 0 12 1
+12 = phi 2 0 11 1
+13 = add 10 5
+14 = lt 13 3
+cbr 14 1 2
+block 2
+16 = mul 11 12
+15 = open 16
 ret
 """
 
