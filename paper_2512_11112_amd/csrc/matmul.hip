@@ -176,9 +176,9 @@ __global__ __launch_bounds__(256) void k_digits(const u64 *__restrict__ src, int
 // One operand stage of a tile (SK = 64 inner indices, 8 digits, 64 rows) is one
 // contiguous 32 KB block of the tile-major digit planes, ordered [digit][16-deep
 // chunk][row][16 bytes]; the 256 threads move it 16 bytes each per round (fully
-// coalesced, sequential addresses) and store it to LDS in the same order, which makes
-// the 16-byte LDS writes and the MFMA operand reads (32 consecutive rows per half
-// wave) conflict-free without padding.
+// coalesced, sequential addresses) straight from global memory into LDS in the same
+// order (no registers, no LDS store instructions), which makes the MFMA operand reads
+// (32 consecutive rows per half wave) conflict-free without padding.
 // --------------------------------------------------------------------------
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
@@ -190,9 +190,38 @@ __device__ __forceinline__ u64 rot61(u64 x, int t) {
   return t == 0 ? x : (((x << t) | (x >> (61 - t))) & F61::P);
 }
 
+// Output tile of linear block b: jobs outermost; within a job, when both tile counts are
+// multiples of 16, each run of 256 consecutive blocks covers a 16 x 16 square of tiles and
+// the 32 of them that land on one XCD (blocks are dealt to the 8 XCDs in turn) a 4 x 8
+// patch, so an XCD's L2 holds 4 left and 8 right operand stages for 32 blocks; otherwise
+// row-major.
+__device__ __forceinline__ void tile_of(int b, int tx, int ty, int &bx, int &by, int &bz) {
+  const int per_z = tx * ty;
+  bz = b / per_z;
+  b -= bz * per_z;
+  if (tx % 16 == 0 && ty % 16 == 0) {
+    const int xcd = b % 8, slot = b / 8, g = slot / 32, r = slot % 32;
+    by = (g / (tx / 16)) * 16 + (xcd / 2) * 4 + r / 8;
+    bx = (g % (tx / 16)) * 16 + (xcd % 2) * 8 + r % 8;
+  } else {
+    bx = b % tx;
+    by = b / tx;
+  }
+}
+
+typedef __attribute__((address_space(3))) void *lds_ptr;
+
+// 16 bytes per lane from global memory straight into LDS: a wave's 64 lanes fill the 1 KB
+// at `wave_dst` (wave-uniform), lane l at wave_dst + 16 l
+__device__ __forceinline__ void to_lds(const int8_t *src, int8_t *wave_dst) {
+  __builtin_amdgcn_global_load_lds(src, (lds_ptr)wave_dst, 16, 0, 0);
+}
+
 __global__ __launch_bounds__(256, 1) void k_gemm_mfma(const GemmArgs A) {
-  const GemmJob &J = A.job[blockIdx.z];
-  const int64_t r0 = (int64_t)blockIdx.y * TILE, c0 = (int64_t)blockIdx.x * TILE;
+  int bx, by, bz;
+  tile_of(blockIdx.x, (int)(A.Np / TILE), (int)(A.Mp / TILE), bx, by, bz);
+  const GemmJob &J = A.job[bz];
+  const int64_t r0 = (int64_t)by * TILE, c0 = (int64_t)bx * TILE;
   // two stage buffers: stage s is read from buffer s & 1 while stage s + 1 is in flight
   __shared__ __attribute__((aligned(16))) int8_t S[2][2][STAGE];  // [buffer][left | right]
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -202,20 +231,19 @@ __global__ __launch_bounds__(256, 1) void k_gemm_mfma(const GemmArgs A) {
   for (int s = 0; s < 2 * NDIG - 1; s++) acc[s] = (v16i){0};
   const int ks = (int)(A.Kp / SK), nst = J.npairs * ks;
   // the stage s of tile row (column) block b is STAGE contiguous bytes at (b ks + s) STAGE;
-  // round q of a fetch moves run 4 q + wave of it, 16 bytes per lane
+  // a fetch moves run q of it in eight rounds, 16 bytes per lane, into the same offsets of LDS
   const int64_t toff = (int64_t)t * 16;
-  const int8_t *gl = (const int8_t *)J.L[0] + (int64_t)blockIdx.y * ks * STAGE + toff;
-  const int8_t *gr = (const int8_t *)J.R[0] + (int64_t)blockIdx.x * ks * STAGE + toff;
-  const int8_t *l1 = (const int8_t *)J.L[1] + (int64_t)blockIdx.y * ks * STAGE + toff;
-  const int8_t *r1 = (const int8_t *)J.R[1] + (int64_t)blockIdx.x * ks * STAGE + toff;
-  v4i ra[NDIG], rb[NDIG];  // the next stage, on its way from global memory to LDS
+  const int woff = wave * 1024;
+  const int8_t *gl = (const int8_t *)J.L[0] + (int64_t)by * ks * STAGE + toff;
+  const int8_t *gr = (const int8_t *)J.R[0] + (int64_t)bx * ks * STAGE + toff;
+  const int8_t *l1 = (const int8_t *)J.L[1] + (int64_t)by * ks * STAGE + toff;
+  const int8_t *r1 = (const int8_t *)J.R[1] + (int64_t)bx * ks * STAGE + toff;
 #pragma unroll
   for (int q = 0; q < NDIG; q++) {
-    ra[q] = *reinterpret_cast<const v4i *>(gl + q * SCH * RUN);
-    rb[q] = *reinterpret_cast<const v4i *>(gr + q * SCH * RUN);
-    *reinterpret_cast<v4i *>(&S[0][0][q * SCH * RUN + t * 16]) = ra[q];
-    *reinterpret_cast<v4i *>(&S[0][1][q * SCH * RUN + t * 16]) = rb[q];
+    to_lds(gl + q * SCH * RUN, &S[0][0][q * SCH * RUN + woff]);
+    to_lds(gr + q * SCH * RUN, &S[0][1][q * SCH * RUN + woff]);
   }
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   // MFMA operands: lane supplies row (lane & 31) of its wave's 32 rows (columns) at chunk
   // 2 kk + (lane >> 5); left and right use the same chunk, so the k pairing is consistent
@@ -238,14 +266,15 @@ __global__ __launch_bounds__(256, 1) void k_gemm_mfma(const GemmArgs A) {
     for (int d = 0; d < NDIG; d++) b0[d] = *reinterpret_cast<const v4i *>(sr + (d * SCH) * RUN + boff);
     a0[0] = *reinterpret_cast<const v4i *>(sl + aoff);
     a0[1] = *reinterpret_cast<const v4i *>(sl + SCH * RUN + aoff);
-    // first half: each group of 8 MFMAs also issues two global loads of the next stage,
-    // reads a first-half operand two groups ahead and two second-half operands, so no
-    // burst of memory instructions holds up the matrix pipe
+    // first half: each group of 8 MFMAs also starts two loads of the next stage into the
+    // other buffer (last read in stage st - 1, before every wave passed the previous
+    // barrier), reads a first-half operand two groups ahead and two second-half operands,
+    // so no burst of memory instructions holds up the matrix pipe
 #pragma unroll
     for (int dk = 0; dk < NDIG; dk++) {
       __builtin_amdgcn_sched_barrier(0);
-      ra[dk] = *reinterpret_cast<const v4i *>(gl + dk * SCH * RUN);
-      rb[dk] = *reinterpret_cast<const v4i *>(gr + dk * SCH * RUN);
+      to_lds(gl + dk * SCH * RUN, wl + dk * SCH * RUN + woff);
+      to_lds(gr + dk * SCH * RUN, wrr + dk * SCH * RUN + woff);
       if (dk + 2 < NDIG) a0[dk + 2] = *reinterpret_cast<const v4i *>(sl + ((dk + 2) * SCH) * RUN + aoff);
       b1[dk] = *reinterpret_cast<const v4i *>(sr + (dk * SCH + 2) * RUN + boff);
       a1[dk] = *reinterpret_cast<const v4i *>(sl + (dk * SCH + 2) * RUN + aoff);
@@ -253,18 +282,16 @@ __global__ __launch_bounds__(256, 1) void k_gemm_mfma(const GemmArgs A) {
       for (int dl = 0; dl < NDIG; dl++)
         acc[dk + dl] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0[dk], b0[dl], acc[dk + dl], 0, 0, 0);
     }
-    // second half: the next stage goes to the other buffer (last read in stage st - 1,
-    // before every wave passed the previous barrier), two 16-byte stores per group
+    // second half
 #pragma unroll
     for (int dk = 0; dk < NDIG; dk++) {
       __builtin_amdgcn_sched_barrier(0);
-      *reinterpret_cast<v4i *>(wl + dk * SCH * RUN + t * 16) = ra[dk];
-      *reinterpret_cast<v4i *>(wrr + dk * SCH * RUN + t * 16) = rb[dk];
 #pragma unroll
       for (int dl = 0; dl < NDIG; dl++)
         acc[dk + dl] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1[dk], b1[dl], acc[dk + dl], 0, 0, 0);
     }
     __builtin_amdgcn_sched_barrier(0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the next stage has landed in LDS
     __syncthreads();
   }
   // recombine the shift classes mod p, one output element at a time, and apply the epilogue
@@ -383,7 +410,7 @@ spdz_status launch_matmul_triple(spdz_ctx *c, int64_t M, int64_t K, int64_t N, c
     dim3 grid((unsigned)(Np / TILE), (unsigned)(Mp / TILE), (unsigned)nout);
     KTimer tm(c, name);
     if (variant == 1)
-      hipLaunchKernelGGL(k_gemm_mfma, grid, dim3(256), 0, c->stream, G);
+      hipLaunchKernelGGL(k_gemm_mfma, dim3(grid.x * grid.y * grid.z), dim3(256), 0, c->stream, G);
     else
       hipLaunchKernelGGL(k_gemm_valu, grid, dim3(256), 0, c->stream, G);
     return hip_status(hipGetLastError());
@@ -418,8 +445,7 @@ spdz_status launch_public_matmul(spdz_ctx *c, int64_t M, int64_t K, int64_t N, c
   G.Np = Np;
   G.Kp = Kp;
   G.job[0] = GemmJob{1, {lp, nullptr}, {rp, nullptr}, nullptr, nullptr, 0, Cm};
-  dim3 grid((unsigned)(Np / TILE), (unsigned)(Mp / TILE), 1);
-  hipLaunchKernelGGL(k_gemm_mfma, grid, dim3(256), 0, c->stream, G);
+  hipLaunchKernelGGL(k_gemm_mfma, dim3((unsigned)((Np / TILE) * (Mp / TILE))), dim3(256), 0, c->stream, G);
   return hip_status(hipGetLastError());
 }
 
