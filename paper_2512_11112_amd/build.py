@@ -6,8 +6,8 @@ Every .hip file under csrc/ is compiled to an object in _build/ (in
 parallel), then linked into paper_2512_11112_amd/libspdz.so.  The calibration
 program calib/mfma_rate.hip (the int8 MFMA rate this GPU sustains, reported
 beside the GEMM's measurements) is a measurement probe, not part of the
-library: build_calib() compiles it next to its source, and a failure there
-never fails the library build.
+library: the matrix-triple benchmark compiles it on first use (build_calib()),
+and build() leaves it alone.
 """
 from __future__ import annotations
 
@@ -57,9 +57,6 @@ def build(verbose: bool = True) -> str:
     os.replace(tmp, OUT)
     if verbose:
         print(f"built {OUT} from {len(srcs)} sources", file=sys.stderr)
-    calib = build_calib()
-    if calib is None and verbose:
-        print("calib/mfma_rate not built (measurement probe only)", file=sys.stderr)
     return OUT
 
 

@@ -78,6 +78,123 @@ struct LevelArgs {
   u64 *acc;                  // MAC-check slots
 };
 
+// an element's input words: operand 1 (and 2), and for a product the triple's a, b, c
+template <int N>
+struct OpIn {
+  F61::E v1[N], m1[N], v2[N], m2[N], av[N], bv[N], am[N], bm[N], cv[N], cm[N];
+};
+
+// word idx of an array at a uniform base, as a 32-bit byte offset (idx < 2^29)
+__device__ __forceinline__ u64 ldw(const u64 *base, uint32_t idx) {
+  return *reinterpret_cast<const u64 *>(reinterpret_cast<const char *>(base) + (idx << 3));
+}
+__device__ __forceinline__ void stw(u64 *base, uint32_t idx, u64 v) {
+  *reinterpret_cast<u64 *>(reinterpret_cast<char *>(base) + (idx << 3)) = v;
+}
+
+template <int N, int KIND>
+__device__ __forceinline__ void load_in(const LevelArgs<N> &A, const DagOpDev &op, int64_t e, OpIn<N> &in) {
+  using E = F61::E;
+  // offsets below 2^32 words: a node holds n * width <= 8 * 2^20 words, a triple 3 n width
+  const uint32_t w = (uint32_t)op.width, ue = (uint32_t)e;
+  const uint32_t i1 = view_index(op.off1, e, op.w1), w1 = (uint32_t)op.w1;
+  const u64 *v1 = A.nval + op.in1, *m1 = A.nmac + op.in1;
+#pragma unroll
+  for (int i = 0; i < N; i++) {
+    in.v1[i] = E{ldw(v1, i * w1 + i1)};
+    in.m1[i] = E{ldw(m1, i * w1 + i1)};
+  }
+  if (KIND == 2) return;
+  const uint32_t i2 = view_index(op.off2, e, op.w2), w2 = (uint32_t)op.w2;
+  const u64 *v2 = A.nval + op.in2, *m2 = A.nmac + op.in2;
+#pragma unroll
+  for (int i = 0; i < N; i++) {
+    in.v2[i] = E{ldw(v2, i * w2 + i2)};
+    in.m2[i] = E{ldw(m2, i * w2 + i2)};
+  }
+  if (KIND == 1) return;
+  const u64 *tv = A.tval + op.tri, *tm = A.tmac + op.tri;
+#pragma unroll
+  for (int i = 0; i < N; i++) {
+    in.av[i] = E{ldw(tv, i * w + ue)};
+    in.bv[i] = E{ldw(tv, (N + i) * w + ue)};
+    in.cv[i] = E{ldw(tv, (2 * N + i) * w + ue)};
+    in.am[i] = E{ldw(tm, i * w + ue)};
+    in.bm[i] = E{ldw(tm, (N + i) * w + ue)};
+    in.cm[i] = E{ldw(tm, (2 * N + i) * w + ue)};
+  }
+}
+
+// public-constant multiple
+template <int N>
+__device__ __forceinline__ void smul_out(const LevelArgs<N> &A, const DagOpDev &op, int64_t e, const OpIn<N> &in) {
+  using F = F61;
+  const F::E c{op.konst};
+  const uint32_t w = (uint32_t)op.width, ue = (uint32_t)e;
+  u64 *ov = A.nval + op.out, *om = A.nmac + op.out;
+#pragma unroll
+  for (int i = 0; i < N; i++) {
+    stw(ov, i * w + ue, F::canon(F::mul(c, in.v1[i])).v);
+    stw(om, i * w + ue, F::canon(F::mul(c, in.m1[i])).v);
+  }
+}
+
+// addition
+template <int N>
+__device__ __forceinline__ void add_out(const LevelArgs<N> &A, const DagOpDev &op, int64_t e, const OpIn<N> &in) {
+  using F = F61;
+  const uint32_t w = (uint32_t)op.width, ue = (uint32_t)e;
+  u64 *ov = A.nval + op.out, *om = A.nmac + op.out;
+#pragma unroll
+  for (int i = 0; i < N; i++) {
+    stw(ov, i * w + ue, F::canon(F::add(in.v1[i], in.v2[i])).v);
+    stw(om, i * w + ue, F::canon(F::add(in.m1[i], in.m2[i])).v);
+  }
+}
+
+// Beaver product with the op's triple; its MAC-check terms go to mc
+template <int N>
+__device__ __forceinline__ void beaver_out(const LevelArgs<N> &A, const DagOpDev &op, int64_t e, const OpIn<N> &in,
+                                           u64 cstate, int64_t jb, F61::E (&mc)[N + 1]) {
+  using F = F61;
+  using E = F61::E;
+  const int64_t w = op.width;
+  E d = F::zero(), ee = F::zero();
+#pragma unroll
+  for (int i = 0; i < N; i++) {
+    d = F::add(d, F::sub(in.v1[i], in.av[i]));
+    ee = F::add(ee, F::sub(in.v2[i], in.bv[i]));
+  }
+  const E de = F::mul(d, ee);
+  const E rd = uniform_elem<F>(cstate, (u64)(jb + op.jlog + e));
+  const E re = uniform_elem<F>(cstate, (u64)(jb + op.jlog + w + e));
+#pragma unroll
+  for (int i = 0; i < N; i++) {
+    F::Wide t = F::wzero();
+    F::wadd(t, in.cv[i]);
+    F::wmac(t, d, in.bv[i]);
+    F::wmac(t, ee, in.av[i]);
+    if (i == 0) F::wadd(t, de);
+    stw(A.nval + op.out, (uint32_t)(i * w + e), F::canon(F::wreduce(t)).v);
+    t = F::wzero();
+    F::wadd(t, in.cm[i]);
+    F::wmac(t, d, in.bm[i]);
+    F::wmac(t, ee, in.am[i]);
+    F::wmac(t, A.alpha[i], de);
+    stw(A.nmac + op.out, (uint32_t)(i * w + e), F::canon(F::wreduce(t)).v);
+    t = F::wzero();
+    F::wmac(t, rd, F::sub(in.m1[i], in.am[i]));
+    F::wmac(t, re, F::sub(in.m2[i], in.bm[i]));
+    mc[1 + i] = F::add(mc[1 + i], F::wreduce(t));
+  }
+  F::Wide t = F::wzero();
+  F::wmac(t, rd, d);
+  F::wmac(t, re, ee);
+  mc[0] = F::add(mc[0], F::wreduce(t));
+}
+
+constexpr int LTAB = 1024;  // launches of up to this many ops keep their op table in LDS
+
 template <int N>
 __global__ __launch_bounds__(BLOCK) void k_dag_level(const LevelArgs<N> A) {
   using F = F61;
@@ -87,105 +204,53 @@ __global__ __launch_bounds__(BLOCK) void k_dag_level(const LevelArgs<N> A) {
   for (int k = 0; k <= N; k++) mc[k] = F::zero();
   const u64 cstate = A.params->coef_state;
   const int64_t jb = A.params->j_base;
+  // the launch's op ids and first work items, read once per block into LDS: the search for
+  // an item's op then costs LDS reads instead of a chain of dependent global loads
+  __shared__ int64_t s_t0[LTAB];
+  __shared__ int32_t s_op[LTAB];
+  const bool tab = A.nlist > 1 && A.nlist <= LTAB;
+  if (tab) {
+    for (int i = threadIdx.x; i < A.nlist; i += BLOCK) {
+      const int32_t k = A.list[i];
+      s_op[i] = k;
+      s_t0[i] = A.ops[k].tile0;
+    }
+    __syncthreads();
+  }
   for (int64_t item = A.item0 + blockIdx.x; item < A.total_tiles; item += gridDim.x) {
     // op owning this work item: last list entry with tile0 <= item
     int lo = 0, hi = A.nlist - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (A.ops[A.list[mid]].tile0 <= item) lo = mid;
+      if ((tab ? s_t0[mid] : A.ops[A.list[mid]].tile0) <= item) lo = mid;
       else hi = mid - 1;
     }
-    const DagOpDev op = A.ops[A.list[lo]];
+    // the op is the same for the whole block: its descriptor goes to scalar registers, and the
+    // arrays are addressed as a uniform base plus a 32-bit lane offset
+    const DagOpDev op = A.ops[__builtin_amdgcn_readfirstlane(tab ? s_op[lo] : A.list[lo])];
     const int64_t w = op.width;
     const int64_t e0 = (item - op.tile0) * A.tile;
     const int64_t e1 = min(e0 + (int64_t)A.tile, w);
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += BLOCK) {
-      const uint32_t i1 = view_index(op.off1, e, op.w1);
-      // every op reads all of an element's input words before it writes any (an op's output
-      // node never overlaps its inputs), so each element costs one memory round trip
-      if (op.kind == 2) {  // public-constant multiple
-        const E c{op.konst};
-        E xv[N], xm[N];
-#pragma unroll
-        for (int i = 0; i < N; i++) {
-          xv[i] = E{A.nval[op.in1 + i * op.w1 + i1]};
-          xm[i] = E{A.nmac[op.in1 + i * op.w1 + i1]};
-        }
-#pragma unroll
-        for (int i = 0; i < N; i++) {
-          A.nval[op.out + i * w + e] = F::canon(F::mul(c, xv[i])).v;
-          A.nmac[op.out + i * w + e] = F::canon(F::mul(c, xm[i])).v;
-        }
-        continue;
+    // every op reads all of an element's input words before it writes any (an op's output
+    // node never overlaps its inputs), so each element costs one memory round trip
+    if (op.kind == 2) {
+      for (int64_t e = e0 + threadIdx.x; e < e1; e += BLOCK) {
+        OpIn<N> in;
+        load_in<N, 2>(A, op, e, in);
+        smul_out<N>(A, op, e, in);
       }
-      const uint32_t i2 = view_index(op.off2, e, op.w2);
-      if (op.kind == 1) {  // addition
-        E xv[N], yv[N], xm[N], ym[N];
-#pragma unroll
-        for (int i = 0; i < N; i++) {
-          xv[i] = E{A.nval[op.in1 + i * op.w1 + i1]};
-          yv[i] = E{A.nval[op.in2 + i * op.w2 + i2]};
-          xm[i] = E{A.nmac[op.in1 + i * op.w1 + i1]};
-          ym[i] = E{A.nmac[op.in2 + i * op.w2 + i2]};
-        }
-#pragma unroll
-        for (int i = 0; i < N; i++) {
-          A.nval[op.out + i * w + e] = F::canon(F::add(xv[i], yv[i])).v;
-          A.nmac[op.out + i * w + e] = F::canon(F::add(xm[i], ym[i])).v;
-        }
-        continue;
+    } else if (op.kind == 1) {
+      for (int64_t e = e0 + threadIdx.x; e < e1; e += BLOCK) {
+        OpIn<N> in;
+        load_in<N, 1>(A, op, e, in);
+        add_out<N>(A, op, e, in);
       }
-      // Beaver product with the op's triple
-      E xv[N], yv[N], av[N], bv[N], xmv[N], ymv[N], amv[N], bmv[N], cvv[N], cmv[N];
-      E d = F::zero(), ee = F::zero();
-#pragma unroll
-      for (int i = 0; i < N; i++) {
-        xv[i] = E{A.nval[op.in1 + i * op.w1 + i1]};
-        yv[i] = E{A.nval[op.in2 + i * op.w2 + i2]};
-        av[i] = E{A.tval[op.tri + i * w + e]};
-        bv[i] = E{A.tval[op.tri + (N + i) * w + e]};
+    } else {
+      for (int64_t e = e0 + threadIdx.x; e < e1; e += BLOCK) {
+        OpIn<N> in;
+        load_in<N, 0>(A, op, e, in);
+        beaver_out<N>(A, op, e, in, cstate, jb, mc);
       }
-#pragma unroll
-      for (int i = 0; i < N; i++) {
-        xmv[i] = E{A.nmac[op.in1 + i * op.w1 + i1]};
-        ymv[i] = E{A.nmac[op.in2 + i * op.w2 + i2]};
-        amv[i] = E{A.tmac[op.tri + i * w + e]};
-        bmv[i] = E{A.tmac[op.tri + (N + i) * w + e]};
-        cvv[i] = E{A.tval[op.tri + (2 * N + i) * w + e]};
-        cmv[i] = E{A.tmac[op.tri + (2 * N + i) * w + e]};
-      }
-#pragma unroll
-      for (int i = 0; i < N; i++) {
-        d = F::add(d, F::sub(xv[i], av[i]));
-        ee = F::add(ee, F::sub(yv[i], bv[i]));
-      }
-      const E de = F::mul(d, ee);
-      const E rd = uniform_elem<F>(cstate, (u64)(jb + op.jlog + e));
-      const E re = uniform_elem<F>(cstate, (u64)(jb + op.jlog + w + e));
-#pragma unroll
-      for (int i = 0; i < N; i++) {
-        const E xm = xmv[i], ym = ymv[i], am = amv[i], bm = bmv[i], cv = cvv[i], cm = cmv[i];
-        F::Wide t = F::wzero();
-        F::wadd(t, cv);
-        F::wmac(t, d, bv[i]);
-        F::wmac(t, ee, av[i]);
-        if (i == 0) F::wadd(t, de);
-        A.nval[op.out + i * w + e] = F::canon(F::wreduce(t)).v;
-        t = F::wzero();
-        F::wadd(t, cm);
-        F::wmac(t, d, bm);
-        F::wmac(t, ee, am);
-        F::wmac(t, A.alpha[i], de);
-        A.nmac[op.out + i * w + e] = F::canon(F::wreduce(t)).v;
-        t = F::wzero();
-        F::wmac(t, rd, F::sub(xm, am));
-        F::wmac(t, re, F::sub(ym, bm));
-        mc[1 + i] = F::add(mc[1 + i], F::wreduce(t));
-      }
-      F::Wide t = F::wzero();
-      F::wmac(t, rd, d);
-      F::wmac(t, re, ee);
-      mc[0] = F::add(mc[0], F::wreduce(t));
     }
   }
   block_add_to_slot<F, N + 1>(mc, A.acc + (size_t)blockIdx.x * (N + 1));
@@ -1252,7 +1317,7 @@ spdz_status spdz_dag_autotune(spdz_dag *g, int max_levels, int *tile_out, int *b
       hipMalloc((void **)&g->tune_acc, (size_t)MAX_SLOTS * (MAX_PARTIES + 1) * sizeof(u64)) != hipSuccess)
     return SPDZ_E_NOMEM;
   SPDZ_RET(set_params(g));
-  const int tiles[] = {512, 1024, 2048, 4096, 8192};
+  const int tiles[] = {256, 512, 1024, 2048, 4096, 8192};
   const int bpcs[] = {2, 4, 8, 16};
   const size_t nl = std::min<size_t>((size_t)max_levels, g->levels.size());
   hipEvent_t e0, e1;

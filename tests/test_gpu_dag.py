@@ -106,7 +106,7 @@ def test_dag_learned_policy_and_autotune():
     ref, ok, sigma = dag_run(dag, seed=6, check_seed=6)
     ctx, g = build(dag, 6)
     tile, bpc, ms = g.autotune(max_levels=5)
-    assert tile in (512, 1024, 2048, 4096, 8192) and bpc in (2, 4, 8, 16) and ms > 0
+    assert tile in (256, 512, 1024, 2048, 4096, 8192) and bpc in (2, 4, 8, 16) and ms > 0
     # a hand-set cost model: predicted log2 CPU ns = log2 width (one ReLU path through the three
     # hidden layers), log2 GPU ns = 9, so ops narrower than 512 go to the CPU back end
     W = width_model(S)
