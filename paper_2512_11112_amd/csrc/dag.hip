@@ -294,6 +294,8 @@ struct spdz_dag {
   float *d_model = nullptr, *d_feat = nullptr, *d_pred = nullptr;
   double ns_per_byte = 0.0, ns_per_copy = 0.0;
   std::vector<uint8_t> learned_on_gpu;  // decisions of the current model (they depend only on the ops and the model)
+  std::vector<uint8_t> static_on_gpu;   // decisions of the static rule at static_thr, kept like the model's
+  int64_t static_thr = -1;
   double last_predict_ms = 0.0;
   // host mirrors for the CPU back end (pinned), residency per node: bit 0 device, bit 1 host
   u64 *h_nval = nullptr, *h_nmac = nullptr, *h_tval = nullptr, *h_tmac = nullptr;
@@ -1138,7 +1140,12 @@ spdz_status spdz_dag_run(spdz_dag *g, int mode, int policy, double *wall_ms) {
 
   std::vector<uint8_t> on_gpu(g->n_ops, 1);
   if (policy == SPDZ_POLICY_STATIC) {
-    for (int64_t k = 0; k < g->n_ops; k++) on_gpu[k] = g->ops[k].width >= g->threshold;
+    if (g->static_thr != g->threshold || (int64_t)g->static_on_gpu.size() != g->n_ops) {
+      g->static_on_gpu.resize(g->n_ops);
+      for (int64_t k = 0; k < g->n_ops; k++) g->static_on_gpu[k] = g->ops[k].width >= g->threshold;
+      g->static_thr = g->threshold;
+    }
+    on_gpu = g->static_on_gpu;
   } else if (policy == SPDZ_POLICY_ALL_CPU) {
     std::fill(on_gpu.begin(), on_gpu.end(), 0);
   } else if (policy == SPDZ_POLICY_LEARNED) {

@@ -44,7 +44,7 @@ constexpr u64 NODE_STRIDE = 1 << 16;
 constexpr u64 PROG_TRIPLE0 = 1ull << 20;
 constexpr int64_t MAX_ENTRIES = 1000000;
 
-enum Op { OP_INPUT, OP_CONST, OP_ADD, OP_SUB, OP_MUL, OP_LT, OP_EQ, OP_REDUCE, OP_OPEN, OP_LOAD, OP_PHI, OP_LAYER };
+enum Op { OP_INPUT, OP_CONST, OP_ADD, OP_SUB, OP_MUL, OP_LT, OP_EQ, OP_REDUCE, OP_OPEN, OP_LOAD, OP_PHI, OP_LAYER, OP_DIV, OP_MOD };
 
 // a phi that another phi of its block reads keeps its previous value here while the
 // phis of a new entry are copied (phis reading each other in a cycle)
@@ -271,6 +271,10 @@ spdz_status parse(spdz_prog *g, const char *text) {
         n.op = op == "add" ? OP_ADD : op == "sub" ? OP_SUB : op == "mul" ? OP_MUL : op == "lt" ? OP_LT : OP_EQ;
         n.args = {(int)v[0], (int)v[1]};
         add_line(n);
+      } else if (op == "div" || op == "mod") {
+        if (!need(2) || v[1] < 1) return fail(g, where + op + " a k (k >= 1)");
+        n.op = op == "div" ? OP_DIV : OP_MOD, n.args = {(int)v[0]}, n.imm = {v[1]};
+        add_line(n);
       } else if (op == "reduce" || op == "open") {
         if (!need(1)) return fail(g, where + op + " a");
         n.op = op == "reduce" ? OP_REDUCE : OP_OPEN, n.args = {(int)v[0]};
@@ -334,6 +338,8 @@ spdz_status infer(spdz_prog *g) {
           n.width = std::max(N[n.args[0]].width, N[n.args[1]].width);
           n.secret = false;
           break;
+        case OP_DIV:
+        case OP_MOD: n.width = N[n.args[0]].width, n.secret = false; break;
         case OP_REDUCE: n.width = 1, n.secret = N[n.args[0]].secret; break;
         case OP_OPEN: n.width = N[n.args[0]].width, n.secret = false; break;
         case OP_LOAD: n.width = n.imm[0], n.secret = N[n.args[0]].secret; break;
@@ -351,6 +357,7 @@ spdz_status infer(spdz_prog *g) {
     }
     if ((n.op == OP_LT || n.op == OP_EQ) && (N[n.args[0]].secret || N[n.args[1]].secret))
       return fail(g, nm + "comparison of a secret value");
+    if ((n.op == OP_DIV || n.op == OP_MOD) && N[n.args[0]].secret) return fail(g, nm + "integer division of a secret value");
     if (n.op == OP_OPEN && !N[n.args[0]].secret) return fail(g, nm + "open of a public value");
     if (n.op == OP_LOAD && (N[n.args[1]].secret || N[n.args[1]].width != 1)) return fail(g, nm + "load start must be a public scalar");
     if (n.op == OP_PHI)
@@ -1020,6 +1027,20 @@ spdz_status issue(spdz_prog *g, PNode &n) {
     case OP_EQ: {
       PNode &a = N[n.args[0]], &b = N[n.args[1]];
       host_visit([&](auto f) { host_binop<decltype(f)>(n.op, a.hpub, a.width, b.hpub, b.width, n.hpub, n.width); });
+      if (n.dev_use) st = upload(g, n);
+      break;
+    }
+    case OP_DIV:
+    case OP_MOD: {  // each element of a public value, an integer in [0, p), by a literal
+      const PNode &a = N[n.args[0]];
+      const unsigned __int128 k = (unsigned __int128)n.imm[0];
+      for (int64_t e = 0; e < n.width; e++) {
+        unsigned __int128 x = a.hpub[e];
+        if (L == 2) x |= (unsigned __int128)a.hpub[a.width + e] << 64;
+        const unsigned __int128 r = n.op == OP_DIV ? x / k : x % k;
+        n.hpub[e] = (u64)r;
+        if (L == 2) n.hpub[n.width + e] = (u64)(r >> 64);
+      }
       if (n.dev_use) st = upload(g, n);
       break;
     }

@@ -374,11 +374,43 @@ class _Lower:
             nx = self.node_of(x)
             self.emit(lines, "shl", [nx], x.width, x.secret, name, extra=f" {y.const}")
             return
+        if op in ("and", "lshr", "udiv", "urem"):
+            self.integer_op(lines, name, op, x, y, mask)
+            return
         if op not in ("add", "sub", "mul"):
             raise FrontendError(f"{op} on a value not known at translation time")
         nx, ny = self.node_of(x), self.node_of(y)
         w = max(x.width if x.kind != "const" else 1, y.width if y.kind != "const" else 1)
         self.emit(lines, op, [nx, ny], w, x.secret or y.secret, name)
+
+    def integer_op(self, lines, name, op, x: Val, y: Val, mask: int):
+        """Loop-count arithmetic on a public integer by a constant, as the program's div and mod
+        (exact on integers in [0, p)): x & C for C a run of one bits [k, h) is
+        (x mod 2^h) - (x mod 2^k); x >> k is div 2^k; udiv and urem by a constant."""
+        if x.secret:
+            raise FrontendError(f"{op} of a secret value (the gate set is arithmetic)")
+        if y.kind != "const" or y.const & mask == 0:
+            raise FrontendError(f"{op} by a value not known at translation time")
+        nx, c = self.public_scalar(lines, x) if x.width == 1 else self.node_of(x), y.const & mask
+        if op == "lshr":
+            self.emit(lines, "div", [nx], x.width, False, name, extra=f" {1 << c}")
+        elif op == "udiv":
+            self.emit(lines, "div", [nx], x.width, False, name, extra=f" {c}")
+        elif op == "urem":
+            self.emit(lines, "mod", [nx], x.width, False, name, extra=f" {c}")
+        else:
+            k, h = (c & -c).bit_length() - 1, c.bit_length()
+            if c != (1 << h) - (1 << k):
+                raise FrontendError(f"and with the mask {c} (only a run of one bits)")
+            hi = nx if (1 << h) >= self.p else self.emit(lines, "mod", [nx], x.width, False, "", extra=f" {1 << h}").node
+            if k == 0:
+                if hi == nx:   # the mask keeps every bit a value below p can have
+                    self.vals[name] = x
+                else:
+                    self.vals[name] = Val("node", node=hi, width=x.width, secret=False)
+                return
+            lo = self.emit(lines, "mod", [nx], x.width, False, "", extra=f" {1 << k}").node
+            self.emit(lines, "sub", [hi, lo], x.width, False, name)
 
     def icmp(self, lines, name, pred, a, b):
         x, y = self.operand(a), self.operand(b)
@@ -511,7 +543,9 @@ class _Lower:
                     kind = "or_disjoint" if op == "or" and "disjoint" in mm.group(1) else op
                     self.binop(lines, name, kind, mm.group(2), a, b)
                 elif op == "icmp":
-                    mm = re.match(r"icmp\s+(\w+)\s+(?:<\d+ x i\d+>|i\d+)\s+(.+)$", rest)
+                    mm = re.match(r"icmp\s+(?:samesign\s+)?(\w+)\s+(?:<\d+ x i\d+>|i\d+)\s+(.+)$", rest)
+                    if not mm:
+                        raise FrontendError(f"cannot read {s!r}")
                     a, b = _split_top(mm.group(2))
                     self.icmp(lines, name, mm.group(1), a, b)
                 elif op == "select":

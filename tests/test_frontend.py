@@ -112,6 +112,28 @@ def test_public_bound_loop(n, width, vw, il):
     assert want == sum(x[i] * y[i] + 3 * x[i] for i in range(n)) % P_PAPER
 
 
+@pytest.mark.parametrize("vw,il", [(16, 2), (4, 4), (None, None)])
+@pytest.mark.parametrize("seed", [8, 11])
+def test_runtime_bound_loop(vw, il, seed):
+    """The bound is a public input known only at run time: the vectorizer's trip-count
+    arithmetic (the bound rounded down to a multiple of the vector length, an and with a mask)
+    becomes the program's public div/mod, and the remainder loop takes what is left."""
+    t = FE.translate(source("dot_runtime.c"), "dot_rt", sizes={0: 4096, 1: 4096}, vector_width=vw, interleave=il)
+    assert t.privacy == {0: "private", 1: "private", 2: "public"} and 2 in t.inputs
+    assert re.search(r"= mod \d+ \d+$", t.text, flags=re.M)
+    res = run_program(t.text, P_PAPER, 2, seed, seed)
+    assert res["ok"]
+    vals = input_values(t, {}, seed)
+    n = vals[2][0]
+    fn = cleartext_function("dot_runtime.c", "dot_rt")
+    fn.restype = ctypes.c_uint64
+    fn.argtypes = [ctypes.POINTER(ctypes.c_uint64)] * 2 + [ctypes.c_uint32]
+    want = fn(u64_array(vals[0]), u64_array(vals[1]), n)
+    assert opened(t, res) == [want]
+    x, y = vals[0], vals[1]
+    assert want == sum(x[i] * y[i] + 3 * x[i] for i in range(n % 4001)) % P_PAPER
+
+
 @pytest.mark.parametrize("tval", [2, 9])
 def test_public_branch(tval):
     """Both sides are loops, so the branch stays a conditional br on a public comparison, the

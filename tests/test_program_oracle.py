@@ -12,7 +12,7 @@ import pytest
 
 import oracle.fast as F
 from oracle.program import ProgramError, parse, run_program
-from workloads import P61, P_PAPER, P_TINY, programs as P
+from workloads import P61, P127, P_PAPER, P_TINY, programs as P
 
 
 def plain_run(text: str, p: int, seed: int):
@@ -51,6 +51,9 @@ def plain_run(text: str, p: int, seed: int):
                 val[nid] = [int(a < c) for a, c in zip(get(nd.args[0], w), get(nd.args[1], w))]
             elif nd.op == "eq":
                 val[nid] = [int(a == c) for a, c in zip(get(nd.args[0], w), get(nd.args[1], w))]
+            elif nd.op in ("div", "mod"):
+                k = nd.imm[0]
+                val[nid] = [a // k if nd.op == "div" else a % k for a in val[nd.args[0]]]
             elif nd.op == "reduce":
                 val[nid] = [sum(val[nd.args[0]]) % p]
             elif nd.op == "open":
@@ -79,7 +82,7 @@ PROGRAMS = [("pipeline", P.pipeline(37)), ("branch", P.branch(21)), ("loop", P.l
             ("revealed_branch", P.revealed_branch(11)), ("opened_operand", P.opened_operand(10)),
             ("layer", P.layer(9, 7, 3)), ("layer_public_bias", P.layer_public_bias(9, 7, 3)),
             ("loop_program", P.loop_program(16, 3)), ("one_block_loop", P.one_block_loop(12, 4)),
-            ("phi_swap", P.phi_swap(6, 5))]
+            ("phi_swap", P.phi_swap(6, 5)), ("public_div_mod", P.public_div_mod(11))]
 
 
 @pytest.mark.parametrize("p,n", [(P_PAPER, 2), (P61, 3), (P_TINY, 2)])
@@ -153,6 +156,36 @@ def test_phi_swap_exchanges(T):
     got = res["outputs"][11]
     assert [sum(int(got.val[i, 0, e]) for i in range(2)) % p for e in range(W)] == a
     assert [int(v) for v in F.from_limbs(res["outputs"][15])] == [x[e] * y[e] % p for e in range(W)]
+
+
+@pytest.mark.parametrize("p", [P_PAPER, P61, P127])
+def test_div_mod_of_public_values(p):
+    """div and mod take a public value as an integer in [0, p): checked on constants whose
+    quotients and remainders are known, and on a dealt public vector against Python's // and %."""
+    text = """
+input 1 public 9 0
+const 2 1 4001
+const 3 1 100
+output 4
+output 5
+output 6
+output 7
+block 0
+4 = mod 1 4001
+5 = div 1 32
+6 = mod 2 32
+7 = div 3 7
+ret
+"""
+    res = run_program(text, p, 2, 3, 3)
+    v = [int(a) for a in F.from_limbs(F.Field(p).deal_values(3, 0, 9))]
+    out = {o: [int(a) for a in F.from_limbs(res["outputs"][o])] for o in (4, 5, 6, 7)}
+    assert out[4] == [a % 4001 for a in v] and out[5] == [a // 32 for a in v]
+    assert out[6] == [4001 % 32] == [1] and out[7] == [14]
+    with pytest.raises(ProgramError, match="secret"):
+        parse("input 1 private 4 0\nblock 0\n2 = div 1 4\nret\n", p)
+    with pytest.raises(ProgramError):
+        parse("input 1 public 4 0\nblock 0\n2 = mod 1 0\nret\n", p)
 
 
 def test_nested_entries_follow_the_inner_trip_counts():

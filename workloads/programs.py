@@ -16,6 +16,10 @@ Text format (one statement per line, '#' starts a comment, ids are integers):
     <id> = shl <a> <k>                  a * 2^k, k a literal (lowered, see below)
     <id> = select <c> <t> <f>           f + c (t - f) (lowered, see below)
     <id> = lt|eq <a> <b>                public operands only: 1 if a < b (a = b) as integers
+    <id> = div|mod <a> <k>              public a only, k a literal >= 1: each element of a,
+                                        an integer in [0, p), divided by k (quotient or
+                                        remainder; loop-count arithmetic such as a bound
+                                        rounded down to a multiple of the vector length)
     <id> = reduce <a>                   sum of the elements (width 1)
     <id> = open <a>                     reveal a secret value (public result)
     <id> = load <base> <start> <count>  elements start .. start+count-1 of base; <start> is a
@@ -192,6 +196,24 @@ cbr 14 1 2
 block 2
 16 = mul 11 12
 15 = open 16
+ret
+"""
+
+
+def public_div_mod(W: int) -> str:
+    """Integer quotient and remainder of a public vector by literals, one of them scaling a
+    secret vector that is then opened."""
+    return f"""
+input 1 public {W} 0
+input 2 private {W} 1
+output 3
+output 4
+output 6
+block 0
+3 = mod 1 4001
+4 = div 1 32
+5 = mul 2 3
+6 = open 5
 ret
 """
 
