@@ -615,6 +615,36 @@ def suite_program(args):
         prog.close()
         ctx.close()
         torch.cuda.empty_cache()
+    # the paper's workload through its pipeline (Fig. 2 compiled by the front end, run by the
+    # runtime): front end, setup (program load, fake preprocessing) and online time per size
+    from paper_2512_11112_amd import frontend as FE
+    fig2 = open(os.path.join(ROOT, "tests", "frontend", "fig2_layer.c")).read()
+    for d in (2048, 4096, 8192):
+        t0 = time.perf_counter()
+        tr = FE.translate(fig2, "linear_layer", sizes={0: d, 1: d * d, 2: d}, defines={"DIN": d, "DOUT": d},
+                          p=p, slice_size=524280)
+        fe_ms = (time.perf_counter() - t0) * 1e3
+        ctx = S.Context(n, p, S.deal_alpha(p, n, seed), seed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prog = S.Program(ctx, tr.text)
+        prog.predeal(seed, 1)
+        torch.cuda.synchronize()
+        setup_ms = (time.perf_counter() - t0) * 1e3
+        ok, _, _ = prog.run(seed)
+        assert ok
+        walls = []
+        for _ in range(5):
+            ok, _, ms = prog.run(seed)
+            assert ok
+            walls.append(ms)
+        res[f"fig2_layer_d{d}"] = {"frontend_ms": fe_ms, "setup_ms": setup_ms, "online_ms": _median(walls),
+                                   "tile_rows": 524280 // d}
+        log(f"Fig. 2 layer d={d} through the front end: front end {fe_ms:.1f} ms, setup {setup_ms:.1f} ms, "
+            f"online {_median(walls):.3f} ms")
+        prog.close()
+        ctx.close()
+        torch.cuda.empty_cache()
     big = res["W4194304_trips16"]
     out = {"metric": "control-flow runtime: MAC'd Beaver mults/s of a 16-iteration loop program "
                      "(2 parties, p = 2^32-5, width 2^22, public loop control, MAC check included)",
