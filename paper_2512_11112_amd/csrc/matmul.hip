@@ -266,21 +266,23 @@ __global__ __launch_bounds__(256, 1) void k_gemm_mfma(const GemmArgs A) {
     for (int d = 0; d < NDIG; d++) b0[d] = *reinterpret_cast<const v4i *>(sr + (d * SCH) * RUN + boff);
     a0[0] = *reinterpret_cast<const v4i *>(sl + aoff);
     a0[1] = *reinterpret_cast<const v4i *>(sl + SCH * RUN + aoff);
-    // first half: each group of 8 MFMAs also starts two loads of the next stage into the
+    // first half: each group of 8 MFMAs reads a first-half operand two groups ahead and two
+    // second-half operands, and after its MFMAs starts two loads of the next stage into the
     // other buffer (last read in stage st - 1, before every wave passed the previous
-    // barrier), reads a first-half operand two groups ahead and two second-half operands,
-    // so no burst of memory instructions holds up the matrix pipe
+    // barrier); the compiler waits for the group's LDS reads before such a load (it cannot
+    // tell the buffers apart), which by then have landed, so no wait holds up the matrix pipe
 #pragma unroll
     for (int dk = 0; dk < NDIG; dk++) {
       __builtin_amdgcn_sched_barrier(0);
-      to_lds(gl + dk * SCH * RUN, wl + dk * SCH * RUN + woff);
-      to_lds(gr + dk * SCH * RUN, wrr + dk * SCH * RUN + woff);
       if (dk + 2 < NDIG) a0[dk + 2] = *reinterpret_cast<const v4i *>(sl + ((dk + 2) * SCH) * RUN + aoff);
       b1[dk] = *reinterpret_cast<const v4i *>(sr + (dk * SCH + 2) * RUN + boff);
       a1[dk] = *reinterpret_cast<const v4i *>(sl + (dk * SCH + 2) * RUN + aoff);
 #pragma unroll
       for (int dl = 0; dl < NDIG; dl++)
         acc[dk + dl] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0[dk], b0[dl], acc[dk + dl], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+      to_lds(gl + dk * SCH * RUN, wl + dk * SCH * RUN + woff);
+      to_lds(gr + dk * SCH * RUN, wrr + dk * SCH * RUN + woff);
     }
     // second half
 #pragma unroll

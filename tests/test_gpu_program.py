@@ -32,7 +32,8 @@ PROGRAMS = [("pipeline", P.pipeline(3001)), ("branch", P.branch(777)), ("loop", 
             ("revealed_branch", P.revealed_branch(513)), ("opened_operand", P.opened_operand(3001)),
             ("layer", P.layer(300, 70, 16)), ("layer_public_bias", P.layer_public_bias(300, 70, 16)),
             ("loop_program", P.loop_program(2048, 4)), ("one_block_loop", P.one_block_loop(1000, 5)),
-            ("phi_swap", P.phi_swap(777, 4)), ("public_div_mod", P.public_div_mod(1001))]
+            ("phi_swap", P.phi_swap(777, 4)), ("public_div_mod", P.public_div_mod(1001)),
+            ("public_phi_swap", P.public_phi_swap(999, 6))]
 
 
 @pytest.mark.parametrize("fuse", [True, False])

@@ -82,7 +82,8 @@ PROGRAMS = [("pipeline", P.pipeline(37)), ("branch", P.branch(21)), ("loop", P.l
             ("revealed_branch", P.revealed_branch(11)), ("opened_operand", P.opened_operand(10)),
             ("layer", P.layer(9, 7, 3)), ("layer_public_bias", P.layer_public_bias(9, 7, 3)),
             ("loop_program", P.loop_program(16, 3)), ("one_block_loop", P.one_block_loop(12, 4)),
-            ("phi_swap", P.phi_swap(6, 5)), ("public_div_mod", P.public_div_mod(11))]
+            ("phi_swap", P.phi_swap(6, 5)), ("public_div_mod", P.public_div_mod(11)),
+            ("public_phi_swap", P.public_phi_swap(5, 6))]
 
 
 @pytest.mark.parametrize("p,n", [(P_PAPER, 2), (P61, 3), (P_TINY, 2)])
@@ -142,6 +143,29 @@ def test_one_block_loop_recurrence(T):
     got_b = res["outputs"][12]
     assert [sum(int(got_b.val[i, 0, e]) for i in range(2)) % p for e in range(W)] == b_entry
     assert res["entries"] == 1 + T + 1 and res["ok"]
+
+
+@pytest.mark.parametrize("T", [1, 2, 7])
+def test_public_phi_pair_is_fibonacci(T):
+    """u, v = v, u + v through two public phis of one block: at the last entry u = F(T), v = F(T+1);
+    s, t = t, s alternate between 0 and T; the secret accumulator follows acc = acc (u + s) + y."""
+    p, W = P_PAPER, 4
+    res = run_program(P.public_phi_swap(W, T), p, 2, 5, 5)
+    fib = [1, 1]
+    while len(fib) < T + 3:
+        fib.append(fib[-1] + fib[-2])
+    u = [int(v) for v in F.from_limbs(res["outputs"][11])]
+    v = [int(v) for v in F.from_limbs(res["outputs"][12])]
+    assert u == [fib[T - 1]] and v == [fib[T]]
+    f = F.Field(p)
+    x = [int(a) for a in F.from_limbs(f.deal_values(5, 0, W))]
+    y = [int(a) for a in F.from_limbs(f.deal_values(5, 1, W))]
+    acc = x
+    for k in range(T):
+        sk = 0 if k % 2 == 0 else T
+        acc = [(a * (fib[k] + sk) + b) % p for a, b in zip(acc, y)]
+    assert [int(a) for a in F.from_limbs(res["outputs"][16])] == acc
+    assert [int(a) for a in F.from_limbs(res["outputs"][20])] == [0 if (T - 1) % 2 == 0 else T]
 
 
 @pytest.mark.parametrize("T", [1, 2, 3, 6])

@@ -218,6 +218,43 @@ ret
 """
 
 
+def public_phi_swap(W: int, trips: int) -> str:
+    """Public phis of one block that read each other: u, v = v, u + v (a Fibonacci pair) and a
+    swapped pair s, t = t, s starting at 0, trips; a secret accumulator scaled by u + s on every
+    trip: acc = x, then acc = acc (u + s) + y."""
+    return f"""
+input 1 private {W} 0
+input 2 private {W} 1
+const 3 1 {trips}
+const 4 1 0
+const 5 1 1
+output 11
+output 12
+output 13
+output 16
+output 20
+block 0
+br 1
+block 1
+10 = phi 4 0 14 1
+11 = phi 5 0 12 1
+12 = phi 5 0 15 1
+13 = phi 1 0 18 1
+20 = phi 4 0 21 1
+21 = phi 3 0 20 1
+22 = add 11 20
+17 = mul 13 22
+18 = add 17 2
+15 = add 11 12
+14 = add 10 5
+19 = lt 14 3
+cbr 19 1 2
+block 2
+16 = open 18
+ret
+"""
+
+
 def nested(W: int, outer: int) -> str:
     """for i < outer: for j < i + 1: acc = acc * y + x; acc opened after every outer
     iteration (its reduction); the inner trip count depends on the outer counter."""
