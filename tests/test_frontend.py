@@ -196,6 +196,14 @@ def test_rejections():
         FE.translate(src, "stores", sizes={0: 16})
     with pytest.raises(FE.FrontendError, match="annotation"):
         FE.translate("word_t f(const word_t *x) { return x[0] * x[1]; }", "f", sizes={0: 2})
+    # integer operations exist only for public values: bits of a secret have no arithmetic form
+    with pytest.raises(FE.FrontendError, match="secret"):
+        FE.translate(src, "secret_shift", sizes={0: 2})
+    with pytest.raises(FE.FrontendError, match="secret"):
+        FE.translate(src, "secret_mask", sizes={0: 2})
+    # a public and with a mask that is not one run of one bits
+    with pytest.raises(FE.FrontendError, match="mask"):
+        FE.translate(src, "public_odd_mask", sizes={0: 128})
 
 
 def test_ir_reader_on_the_papers_listing_shape():
