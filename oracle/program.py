@@ -114,6 +114,10 @@ def lower(nodes, blk: Block, nid: int, op: str, a: List[int], p: int):
         add(Node(nid, "phi", phi=[(a[i], a[i + 1]) for i in range(0, len(a), 2)]))
     elif op == "layer":
         add(Node(nid, "layer", a[:3], imm=a[3:6]))
+    elif op == "bcast":
+        if len(a) != 2 or a[1] < 1:
+            raise ProgramError("bcast a w with a literal w >= 1")
+        add(Node(nid, op, a[:1], imm=[a[1]]))
     elif op in ("div", "mod"):
         if len(a) != 2 or a[1] < 1:
             raise ProgramError(f"{op} a k with a literal k >= 1")
@@ -147,6 +151,8 @@ def infer(prog: Program):
                 n.secret = False
             elif n.op in ("div", "mod"):
                 n.width, n.secret = nodes[n.args[0]].width, False
+            elif n.op == "bcast":
+                n.width, n.secret = n.imm[0], nodes[n.args[0]].secret
             elif n.op == "reduce":
                 n.width, n.secret = 1, nodes[n.args[0]].secret
             elif n.op == "open":
@@ -163,6 +169,8 @@ def infer(prog: Program):
                 raise ProgramError(f"node {nid}: widths {x.width} and {y.width}")
         if n.op in ("lt", "eq") and (nodes[n.args[0]].secret or nodes[n.args[1]].secret):
             raise ProgramError(f"node {nid}: comparison of a secret value")
+        if n.op == "bcast" and nodes[n.args[0]].width != 1:
+            raise ProgramError(f"node {nid}: bcast of a value of width {nodes[n.args[0]].width}")
         if n.op in ("div", "mod") and nodes[n.args[0]].secret:
             raise ProgramError(f"node {nid}: integer division of a secret value")
         if n.op == "open" and not nodes[n.args[0]].secret:
@@ -272,6 +280,12 @@ class Exec:
             xb = F.from_limbs(self.pub(nd.args[1], w))
             r = [int(u < v) if nd.op == "lt" else int(u == v) for u, v in zip(xa, xb)]
             self.val[nd.id] = F.to_limbs(r, f.L)
+        elif nd.op == "bcast":
+            v, w = self.val[nd.args[0]], nd.imm[0]
+            if nd.secret:
+                self.val[nd.id] = F.Shares(np.repeat(v.val, w, axis=2), np.repeat(v.mac, w, axis=2))
+            else:
+                self.val[nd.id] = np.repeat(v, w, axis=1)
         elif nd.op in ("div", "mod"):   # a public value as an integer in [0, p) by a literal
             k = nd.imm[0]
             xa = F.from_limbs(self.val[nd.args[0]])

@@ -44,7 +44,7 @@ constexpr u64 NODE_STRIDE = 1 << 16;
 constexpr u64 PROG_TRIPLE0 = 1ull << 20;
 constexpr int64_t MAX_ENTRIES = 1000000;
 
-enum Op { OP_INPUT, OP_CONST, OP_ADD, OP_SUB, OP_MUL, OP_LT, OP_EQ, OP_REDUCE, OP_OPEN, OP_LOAD, OP_PHI, OP_LAYER, OP_DIV, OP_MOD };
+enum Op { OP_INPUT, OP_CONST, OP_ADD, OP_SUB, OP_MUL, OP_LT, OP_EQ, OP_REDUCE, OP_OPEN, OP_LOAD, OP_PHI, OP_LAYER, OP_DIV, OP_MOD, OP_BCAST };
 
 // a phi that another phi of its block reads keeps its previous value here while the
 // phis of a new entry are copied (phis reading each other in a cycle)
@@ -271,6 +271,10 @@ spdz_status parse(spdz_prog *g, const char *text) {
         n.op = op == "add" ? OP_ADD : op == "sub" ? OP_SUB : op == "mul" ? OP_MUL : op == "lt" ? OP_LT : OP_EQ;
         n.args = {(int)v[0], (int)v[1]};
         add_line(n);
+      } else if (op == "bcast") {
+        if (!need(2) || v[1] < 1) return fail(g, where + "bcast a w (w >= 1)");
+        n.op = OP_BCAST, n.args = {(int)v[0]}, n.imm = {v[1]};
+        add_line(n);
       } else if (op == "div" || op == "mod") {
         if (!need(2) || v[1] < 1) return fail(g, where + op + " a k (k >= 1)");
         n.op = op == "div" ? OP_DIV : OP_MOD, n.args = {(int)v[0]}, n.imm = {v[1]};
@@ -340,6 +344,7 @@ spdz_status infer(spdz_prog *g) {
           break;
         case OP_DIV:
         case OP_MOD: n.width = N[n.args[0]].width, n.secret = false; break;
+        case OP_BCAST: n.width = n.imm[0], n.secret = N[n.args[0]].secret; break;
         case OP_REDUCE: n.width = 1, n.secret = N[n.args[0]].secret; break;
         case OP_OPEN: n.width = N[n.args[0]].width, n.secret = false; break;
         case OP_LOAD: n.width = n.imm[0], n.secret = N[n.args[0]].secret; break;
@@ -358,6 +363,7 @@ spdz_status infer(spdz_prog *g) {
     if ((n.op == OP_LT || n.op == OP_EQ) && (N[n.args[0]].secret || N[n.args[1]].secret))
       return fail(g, nm + "comparison of a secret value");
     if ((n.op == OP_DIV || n.op == OP_MOD) && N[n.args[0]].secret) return fail(g, nm + "integer division of a secret value");
+    if (n.op == OP_BCAST && N[n.args[0]].width != 1) return fail(g, nm + "bcast of a value wider than 1");
     if (n.op == OP_OPEN && !N[n.args[0]].secret) return fail(g, nm + "open of a public value");
     if (n.op == OP_LOAD && (N[n.args[1]].secret || N[n.args[1]].width != 1)) return fail(g, nm + "load start must be a public scalar");
     if (n.op == OP_PHI)
@@ -938,6 +944,14 @@ spdz_status issue_group(spdz_prog *g, FGroup &G) {
   return SPDZ_OK;
 }
 
+// every one of `planes` rows of `w` words at dst takes the one word of its row at src
+__global__ __launch_bounds__(256) void k_bcast(const u64 *__restrict__ src, u64 *__restrict__ dst, int planes,
+                                               int64_t w) {
+  const int64_t total = (int64_t)planes * w;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256)
+    dst[i] = src[i / w];
+}
+
 // a phi's value: the source's words (public), its shares (secret), or a public source shared
 spdz_status copy_phi(spdz_prog *g, PNode &n) {
   spdz_ctx *c = g->c;
@@ -1028,6 +1042,22 @@ spdz_status issue(spdz_prog *g, PNode &n) {
       PNode &a = N[n.args[0]], &b = N[n.args[1]];
       host_visit([&](auto f) { host_binop<decltype(f)>(n.op, a.hpub, a.width, b.hpub, b.width, n.hpub, n.width); });
       if (n.dev_use) st = upload(g, n);
+      break;
+    }
+    case OP_BCAST: {
+      const PNode &a = N[n.args[0]];
+      if (n.secret) {  // the 2 n L planes of a width-1 node are consecutive words
+        const int planes = 2 * c->n * L;
+        const int64_t total = (int64_t)planes * n.width;
+        const unsigned grid = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_bcast, dim3(grid), dim3(256), 0, c->stream, a.sh.val, n.sh.val, planes, n.width);
+        st = hip_status(hipGetLastError());
+        g->launches++;
+      } else {
+        for (int l = 0; l < L; l++)
+          for (int64_t e = 0; e < n.width; e++) n.hpub[l * n.width + e] = a.hpub[l];
+        if (n.dev_use) st = upload(g, n);
+      }
       break;
     }
     case OP_DIV:

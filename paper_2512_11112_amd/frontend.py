@@ -444,7 +444,7 @@ class _Lower:
         else:
             raise FrontendError(f"icmp {pred}")
 
-    def gep(self, name, ety, base, idx):
+    def gep(self, lines, name, ety, base, idx):
         b = self.operand(base)
         if b.kind != "ptr":
             raise FrontendError("getelementptr on a value that is not a parameter's vector")
@@ -460,13 +460,18 @@ class _Lower:
             self.vals[name] = Val("ptr", base=b.base, width=b.width, secret=b.secret, start_node=b.start_node,
                                   start_const=b.start_const + off // 4)
             return
-        if esize != 4:
-            raise FrontendError("a variable index over elements that are not 32-bit words")
-        if b.start_node is not None:
-            raise FrontendError("a variable index on top of another variable index")
         if i.kind != "node" or i.secret or i.width != 1:
             raise FrontendError("a secret or vector index")
-        self.vals[name] = Val("ptr", base=b.base, width=b.width, secret=b.secret, start_node=i.node,
+        # the index in 32-bit words: byte and half-word indices into word arrays are whole words
+        # (a multiple of 4 bytes), so the quotient is exact
+        k = i.node
+        if esize > 4:
+            k = self.emit(lines, "mul", [k, self.const_node(esize // 4)], 1, False, "").node
+        elif esize < 4:
+            k = self.emit(lines, "div", [k], 1, False, "", extra=f" {4 // esize}").node
+        if b.start_node is not None:   # an index on top of another: their sum
+            k = self.emit(lines, "add", [b.start_node, k], 1, False, "").node
+        self.vals[name] = Val("ptr", base=b.base, width=b.width, secret=b.secret, start_node=k,
                               start_const=b.start_const)
 
     def load(self, lines, name, ty, ptr):
@@ -516,6 +521,30 @@ class _Lower:
             return
         raise FrontendError(f"call to @{fn}")
 
+    def _dominance_order(self) -> List[Tuple[str, List[str]]]:
+        """The blocks in reverse post-order from the entry: every block comes after those that
+        dominate it, so an instruction's operands (other than a phi's) are lowered before it
+        (LLVM's textual order does not promise that).  Unreachable blocks follow."""
+        blocks = dict(self.f.blocks)
+        succ = {}
+        for lab, ins in self.f.blocks:
+            term = ins[-1] if ins else ""
+            succ[lab] = re.findall(r"label\s+%([\w.$]+)", term) if term.lstrip().startswith("br") else []
+        entry = self.f.blocks[0][0]
+        seen, post = {entry}, []
+        stack = [(entry, iter(succ[entry]))]
+        while stack:
+            lab, it = stack[-1]
+            nxt = next(it, None)
+            if nxt is None:
+                post.append(lab)
+                stack.pop()
+            elif nxt not in seen and nxt in blocks:
+                seen.add(nxt)
+                stack.append((nxt, iter(succ[nxt])))
+        order = post[::-1] + [lab for lab, _ in self.f.blocks if lab not in seen]
+        return [(lab, blocks[lab]) for lab in order]
+
     def run(self) -> Tuple[str, int, Optional[int]]:
         body: List[Tuple[int, List[str], List[str]]] = []   # (block id, lines, terminator)
         pending_phis = []       # (block lines, index, name, ty, [(tok, label)])
@@ -523,7 +552,7 @@ class _Lower:
         revealed: Optional[int] = None
         insert: Dict[str, Val] = {}
         allocas = set()
-        for lab, ins in self.f.blocks:
+        for lab, ins in self._dominance_order():
             bid = self.block_id[lab]
             lines: List[str] = []
             term: List[str] = []
@@ -569,7 +598,7 @@ class _Lower:
                                   rest)
                     if not mm or len(_split_top(mm.group(3))) != 1:
                         raise FrontendError(f"cannot read {s!r}")
-                    self.gep(name, mm.group(1), mm.group(2), mm.group(3))
+                    self.gep(lines, name, mm.group(1), mm.group(2), mm.group(3))
                 elif op == "load":
                     mm = re.match(r"load\s+(<\d+ x i\d+>|i\d+),\s*ptr\s+(%[\w.$]+)", rest)
                     if not mm:
@@ -593,14 +622,15 @@ class _Lower:
                     self.vals[name] = Val("skip")
                 elif op == "shufflevector":
                     mm = re.match(r"shufflevector\s+<\d+ x i\d+>\s+(%[\w.$]+),\s*<\d+ x i\d+>\s+(?:poison|undef),\s*"
-                                  r"<\d+ x i\d+>\s+zeroinitializer$", rest)
+                                  r"<(\d+) x i\d+>\s+zeroinitializer$", rest)
                     if not mm or mm.group(1) not in insert:
                         raise FrontendError(f"shufflevector other than a broadcast: {s!r}")
                     sv = insert[mm.group(1)]
                     if sv.kind == "const":
                         self.vals[name] = sv
-                    elif sv.secret:
-                        raise FrontendError("broadcast of a secret scalar")
+                    elif sv.secret:   # a secret scalar repeated across the vector's lanes
+                        self.emit(lines, "bcast", [self.node_of(sv)], int(mm.group(2)), True, name,
+                                  extra=f" {int(mm.group(2))}")
                     else:
                         self.vals[name] = Val("bcast", node=sv.node, width=1, secret=False)
                 elif op in ("call", "tail"):

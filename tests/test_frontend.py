@@ -134,6 +134,46 @@ def test_runtime_bound_loop(vw, il, seed):
     assert want == sum(x[i] * y[i] + 3 * x[i] for i in range(n % 4001)) % P_PAPER
 
 
+@pytest.mark.parametrize("din,dout,vw", [(64, 32, 16), (64, 32, None), (100, 7, None), (128, 16, 8)])
+def test_nested_loops_over_rows(din, dout, vw):
+    """Rows addressed by a variable byte offset into the matrix, the inner dot product unrolled
+    and vectorized (blocks lowered in dominance order: at -O2 a value's definition can follow its
+    use in the text): sum_r (W_r . x)^2 equals the cleartext build and Python integers."""
+    defines = {"DIN": din, "DOUT": dout}
+    t = FE.translate(source("matvec.c"), "matvec_sum", sizes={0: din * dout, 1: din}, defines=defines,
+                     vector_width=vw)
+    assert "cbr" in t.text or dout == 1
+    seed = 13
+    res = run_program(t.text, P_PAPER, 2, seed, seed)
+    assert res["ok"]
+    vals = input_values(t, {}, seed)
+    fn = cleartext_function("matvec.c", "matvec_sum", defines)
+    fn.restype = ctypes.c_uint64
+    fn.argtypes = [ctypes.POINTER(ctypes.c_uint64)] * 2
+    want = fn(u64_array(vals[0]), u64_array(vals[1]))
+    assert opened(t, res) == [want]
+    W, x = vals[0], vals[1]
+    assert want == sum(sum(W[r * din + k] * x[k] for k in range(din)) ** 2 for r in range(dout)) % P_PAPER
+
+
+@pytest.mark.parametrize("vw", [8, None])
+def test_secret_scalar_broadcast(vw):
+    """A secret scalar parameter multiplied into vectors becomes the program's bcast."""
+    t = FE.translate(source("axpy.c"), "axpy_dot", sizes={0: 64, 1: 64}, vector_width=vw)
+    assert re.search(r"= bcast \d+ \d+$", t.text, flags=re.M)
+    seed = 17
+    res = run_program(t.text, P_PAPER, 2, seed, seed)
+    assert res["ok"]
+    vals = input_values(t, {}, seed)
+    fn = cleartext_function("axpy.c", "axpy_dot")
+    fn.restype = ctypes.c_uint64
+    fn.argtypes = [ctypes.POINTER(ctypes.c_uint64)] * 2 + [ctypes.c_uint64]
+    want = fn(u64_array(vals[0]), u64_array(vals[1]), vals[2][0])
+    assert opened(t, res) == [want]
+    x, y, a = vals[0], vals[1], vals[2][0]
+    assert want == sum((a * x[i] + y[i]) ** 2 for i in range(64)) % P_PAPER
+
+
 @pytest.mark.parametrize("tval", [2, 9])
 def test_public_branch(tval):
     """Both sides are loops, so the branch stays a conditional br on a public comparison, the

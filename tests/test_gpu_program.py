@@ -33,7 +33,7 @@ PROGRAMS = [("pipeline", P.pipeline(3001)), ("branch", P.branch(777)), ("loop", 
             ("layer", P.layer(300, 70, 16)), ("layer_public_bias", P.layer_public_bias(300, 70, 16)),
             ("loop_program", P.loop_program(2048, 4)), ("one_block_loop", P.one_block_loop(1000, 5)),
             ("phi_swap", P.phi_swap(777, 4)), ("public_div_mod", P.public_div_mod(1001)),
-            ("public_phi_swap", P.public_phi_swap(999, 6))]
+            ("public_phi_swap", P.public_phi_swap(999, 6)), ("broadcast", P.broadcast(3001))]
 
 
 @pytest.mark.parametrize("fuse", [True, False])
@@ -265,6 +265,9 @@ def frontend_programs():
                                        vector_width=16, interleave=2).text),
         ("dot_runtime_vw16", FE.translate(src("dot_runtime.c"), "dot_rt", sizes={0: 4096, 1: 4096},
                                           vector_width=16, interleave=2).text),
+        ("matvec_rows", FE.translate(src("matvec.c"), "matvec_sum", sizes={0: 512 * 48, 1: 512},
+                                     defines={"DIN": 512, "DOUT": 48}, vector_width=16).text),
+        ("axpy_bcast", FE.translate(src("axpy.c"), "axpy_dot", sizes={0: 64, 1: 64}, vector_width=8).text),
         ("branch_runtime_condition", FE.translate(src("branch.c"), "branchy", sizes={0: 64, 1: 64},
                                                   vector_width=8).text),
         ("poly_select", FE.translate(src("poly.c"), "poly", sizes={0: 4}).text),
@@ -277,8 +280,8 @@ def fe_programs():
 
 
 @pytest.mark.parametrize("fuse", [True, False])
-@pytest.mark.parametrize("name", ["fig2_layer", "dot_loop_vw16", "dot_runtime_vw16", "branch_runtime_condition",
-                                  "poly_select"])
+@pytest.mark.parametrize("name", ["fig2_layer", "dot_loop_vw16", "dot_runtime_vw16", "matvec_rows", "axpy_bcast",
+                                  "branch_runtime_condition", "poly_select"])
 def test_frontend_program_matches_oracle(fe_programs, name, fuse):
     from paper_2512_11112_amd.spdz import Program
     text = fe_programs[name]

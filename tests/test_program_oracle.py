@@ -51,6 +51,8 @@ def plain_run(text: str, p: int, seed: int):
                 val[nid] = [int(a < c) for a, c in zip(get(nd.args[0], w), get(nd.args[1], w))]
             elif nd.op == "eq":
                 val[nid] = [int(a == c) for a, c in zip(get(nd.args[0], w), get(nd.args[1], w))]
+            elif nd.op == "bcast":
+                val[nid] = val[nd.args[0]] * nd.imm[0]
             elif nd.op in ("div", "mod"):
                 k = nd.imm[0]
                 val[nid] = [a // k if nd.op == "div" else a % k for a in val[nd.args[0]]]
@@ -83,7 +85,7 @@ PROGRAMS = [("pipeline", P.pipeline(37)), ("branch", P.branch(21)), ("loop", P.l
             ("layer", P.layer(9, 7, 3)), ("layer_public_bias", P.layer_public_bias(9, 7, 3)),
             ("loop_program", P.loop_program(16, 3)), ("one_block_loop", P.one_block_loop(12, 4)),
             ("phi_swap", P.phi_swap(6, 5)), ("public_div_mod", P.public_div_mod(11)),
-            ("public_phi_swap", P.public_phi_swap(5, 6))]
+            ("public_phi_swap", P.public_phi_swap(5, 6)), ("broadcast", P.broadcast(9))]
 
 
 @pytest.mark.parametrize("p,n", [(P_PAPER, 2), (P61, 3), (P_TINY, 2)])

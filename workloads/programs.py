@@ -20,6 +20,7 @@ Text format (one statement per line, '#' starts a comment, ids are integers):
                                         an integer in [0, p), divided by k (quotient or
                                         remainder; loop-count arithmetic such as a bound
                                         rounded down to a multiple of the vector length)
+    <id> = bcast <a> <w>                a value of width 1 (secret or public) repeated w times
     <id> = reduce <a>                   sum of the elements (width 1)
     <id> = open <a>                     reveal a secret value (public result)
     <id> = load <base> <start> <count>  elements start .. start+count-1 of base; <start> is a
@@ -251,6 +252,24 @@ block 1
 cbr 19 1 2
 block 2
 16 = open 18
+ret
+"""
+
+
+def broadcast(W: int) -> str:
+    """A secret and a public scalar repeated across W lanes: z = bcast(s) y + bcast(c), opened."""
+    return f"""
+input 1 private 1 0
+input 2 private {W} 1
+input 3 public 1 2
+output 6
+output 8
+block 0
+4 = bcast 1 {W}
+5 = bcast 3 {W}
+7 = mul 4 2
+6 = add 7 5
+8 = open 6
 ret
 """
 
