@@ -134,7 +134,7 @@ def main():
         print(json.dumps(cpu_baseline(P127, 3, args.cpu_only, SEEDS_TIMING[0], min_s=3.0, max_passes=4)), flush=True)
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only: the build simulates all parties on one device "
+        print(f"bench.py measures one GPU only: all parties are simulated on one device "
               f"(--gpus {args.gpus} is not supported)", file=sys.stderr)
         sys.exit(2)
 
@@ -553,23 +553,26 @@ def cpu_baseline_dag(depth: int = 40):
 SEEDS_DAG_CPU = 1
 
 
-def loop_program_bytes(n: int, L: int, W: int, trips: int, fused: bool = True):
-    """Algorithmic bytes of the loop program's online device work per run.  Fused (the
-    runtime's default), the body's chain of three products and two additions is one kernel:
-    it reads the three outside operands (acc, x, y: 2 n L words per element each) and the
-    three triples (6 n L each) and writes the accumulator (2 n L); the phi copy moves 4 n L.
-    Node by node, each product moves 12 n L words and each addition 6 n L.  Dealing a
-    product's triple on the fly would write 6 n L more (reported apart)."""
-    per_iter = ((3 * 2 + 3 * 6 + 2 + 4) if fused else (3 * 12 + 2 * 6 + 4)) * n * L * 8 * W
+def loop_program_bytes(n: int, L: int, W: int, trips: int, fused: bool = True, phi_copy: bool = False):
+    """Bytes of the loop program's online device work per run.  Fused (the runtime's default),
+    the body's chain of three products and two additions is one kernel: it reads the three
+    outside operands (acc, x, y: 2 n L words per element each) and the three triples (6 n L
+    each) and writes the accumulator (2 n L).  Node by node, each product moves 12 n L words
+    and each addition 6 n L.  A phi copy moves 4 n L: on every trip when phis copy, once
+    (the accumulator's first value, x, handed back to x) when they take their sources'
+    buffers.  Dealing a product's triple on the fly would write 6 n L more (reported apart)."""
+    per_iter = ((3 * 2 + 3 * 6 + 2) if fused else (3 * 12 + 2 * 6)) * n * L * 8 * W
+    copies = (trips if phi_copy else 1) * 4 * n * L * 8 * W
     deal = 3 * 6 * n * L * 8 * W
-    return per_iter * trips, deal * trips
+    return per_iter * trips + copies, deal * trips
 
 
 def suite_program(args):
     """The control-flow runtime (Sec. III-C): a loop program whose body holds three Beaver
     products and two additions of width W (2 parties, p = 2^32 - 5), run end to end with
-    public loop control, phi copies and the final MAC check; and the same loop at width 64
-    (per block-entry latency of the scheduler).  Triples are dealt ahead (fake preprocessing,
+    public loop control, the loop-carried phi and the final MAC check; and the same loop at
+    width 64 (per block-entry latency of the scheduler); fused and node by node, and with
+    phis copying instead of taking their sources' buffers.  Triples are dealt ahead (fake preprocessing,
     as the paper's evaluation); the first, untimed run deals them on the fly and its wall
     time is reported beside."""
     import torch
@@ -577,10 +580,11 @@ def suite_program(args):
     from workloads import P_PAPER, SEEDS_TIMING, programs as PR
     seed, n, p = SEEDS_TIMING[0], 2, P_PAPER
     res = {}
-    for W, trips, reps, fuse in ((1 << 22, 16, 5, True), (64, 2000, 3, True), (1 << 22, 16, 3, False),
-                                 (64, 2000, 3, False)):
+    for W, trips, reps, fuse, handoff in ((1 << 22, 16, 5, True, True), (64, 2000, 3, True, True),
+                                          (1 << 22, 16, 3, False, True), (64, 2000, 3, False, True),
+                                          (1 << 22, 16, 3, True, False), (64, 2000, 3, True, False)):
         ctx = S.Context(n, p, S.deal_alpha(p, n, seed), seed)
-        prog = S.Program(ctx, PR.loop_program(W, trips), fuse=fuse)
+        prog = S.Program(ctx, PR.loop_program(W, trips), fuse=fuse, handoff=handoff)
         ok, _, ms_deal = prog.run(seed)   # warm-up, triples dealt on the fly
         assert ok
         prog.predeal(seed, trips)         # fake preprocessing ahead of the timed online runs
@@ -601,15 +605,16 @@ def suite_program(args):
         ctx.spdz_timing_enable(False)
         reps = 1
         ms = _median(walls)
-        alg, deal = loop_program_bytes(n, 1, W, trips, fused=fuse)
+        alg, deal = loop_program_bytes(n, 1, W, trips, fused=fuse, phi_copy=not handoff)
         mults = 3 * W * trips
-        res[f"W{W}_trips{trips}" + ("" if fuse else "_node_by_node")] = {
+        res[f"W{W}_trips{trips}" + ("" if fuse else "_node_by_node") + ("" if handoff else "_phi_copies")] = {
             "wall_ms": ms, "kernel_ms_sum": kern / reps, "host_overhead_ms": ms - kern / reps,
             "block_entries": st["block_entries"], "launches": st["launches"], "host_syncs": st["host_syncs"],
             "us_per_block_entry": ms * 1e3 / st["block_entries"], "mults_per_s": mults / (ms * 1e-3),
             "alg_GBps": alg / (ms * 1e-3) / 1e9, "alg_bytes": alg,
             "wall_ms_dealing_on_the_fly": ms_deal, "dealing_bytes": deal}
-        log(f"program W={W} trips={trips} {'fused' if fuse else 'node by node'}: {ms:.3f} ms wall, kernels {kern / reps:.3f} ms, "
+        log(f"program W={W} trips={trips} {'fused' if fuse else 'node by node'}{'' if handoff else ', phis copied'}: "
+            f"{ms:.3f} ms wall, kernels {kern / reps:.3f} ms, "
             f"{st['block_entries']} block entries ({ms * 1e3 / st['block_entries']:.1f} us each), "
             f"{st['launches']} launches, {st['host_syncs']} syncs, {mults / (ms * 1e-3) / 1e9:.2f} G mult/s")
         prog.close()
@@ -652,7 +657,7 @@ def suite_program(args):
            "steps": 5, "warmup": 1, "ms_per_step": big["wall_ms"], "vs_baseline": None,
            "dtype": "u64 words (residues < 2^32)", "data": "synthetic",
            "config": {"workload": "loop_program_n2_p32_w4194304_trips16", "parties": 2, "modulus": "2^32-5"},
-           "roofline": {"bound": "hbm", "kernel": "whole program (fused runs, phi copies)",
+           "roofline": {"bound": "hbm", "kernel": "whole program (fused runs, phis taking their sources' buffers)",
                         "achieved": big["alg_GBps"], "peak": 8000.0, "unit": "GB/s", "frac": big["alg_GBps"] / 8000.0,
                         "traffic": None},
            "results": res}

@@ -532,6 +532,16 @@ spdz_status spdz_prog_predeal(spdz_prog *prog, uint64_t seed, int64_t executions
  * runs the program has.  Not during a run. */
 spdz_status spdz_prog_set_fusion(spdz_prog *prog, int enable, int *n_groups);
 
+/* Phi buffer hand-off (a loop-carried value moves instead of being copied):
+ * a secret phi whose source is a secret node other than a phi takes the
+ * source's buffer (the two swap buffers) instead of copying the shares (one
+ * 2-D copy of 2 n L planes per block entry saved); the source's value then
+ * lives in the phi's buffer and is copied back only if something reads the
+ * source before it is computed again, and outputs are back in their own
+ * buffers when the run ends.  Results are bit-identical either way.  On by
+ * default.  enable: 0 copies every phi.  Not during a run. */
+spdz_status spdz_prog_set_handoff(spdz_prog *prog, int enable);
+
 /* After a run: an output node's final value, into out_shares (secret; len =
  * the node's width, any strides) or out_pub (public; DEVICE [L][width]).
  * SPDZ_E_INVAL for a node that is not an output.  Synchronous. */

@@ -78,6 +78,10 @@ struct PNode {
   int64_t log_off = 0;
   int phi_src = -1;
   std::vector<int> users;
+  // buffer hand-off: a phi takes its source's buffer instead of copying it; the source's value
+  // then lives in the phi's buffer (moved_to) until the source is computed again
+  int moved_to = -1;        // node whose buffer holds this node's value, or -1
+  std::vector<int> holds;   // (a phi) nodes whose values its buffer holds
 };
 
 struct PBlock {
@@ -143,6 +147,7 @@ struct spdz_prog {
   u64 pool_seed = 0;
   std::vector<FGroup> groups;
   bool fuse = true;
+  bool handoff = true;  // phis take their sources' buffers where they can
 };
 
 namespace {
@@ -746,6 +751,8 @@ void enqueue(spdz_prog *g, PNode &n) {
 
 spdz_status copy_phi(spdz_prog *g, PNode &n);
 spdz_status settle_opens(spdz_prog *g);
+spdz_status restore(spdz_prog *g, PNode &x);
+void recomputed(spdz_prog *g, PNode &x);
 spdz_status upload(spdz_prog *g, PNode &n);
 spdz_status copy_shares(spdz_prog *g, const spdz_shares &src, int64_t first, spdz_shares &dst);
 
@@ -903,6 +910,9 @@ spdz_status issue_group(spdz_prog *g, FGroup &G) {
   spdz_ctx *c = g->c;
   auto &N = g->nodes;
   G.queued = false;
+  for (const FGroup::Step &st : G.plan)
+    if (st.kind == FK_LOAD) SPDZ_RET(restore(g, N[st.node]));
+  for (int id : G.members) recomputed(g, N[id]);
   FusedIns ins[FUSED_MAX_INS];
   for (size_t q = 0; q < G.plan.size(); q++) {
     const FGroup::Step &st = G.plan[q];
@@ -952,7 +962,34 @@ __global__ __launch_bounds__(256) void k_bcast(const u64 *__restrict__ src, u64 
     dst[i] = src[i / w];
 }
 
-// a phi's value: the source's words (public), its shares (secret), or a public source shared
+// a node whose value was handed to a phi's buffer gets it back (before anything reads it)
+spdz_status restore(spdz_prog *g, PNode &x) {
+  if (x.moved_to < 0) return SPDZ_OK;
+  PNode &h = g->nodes[x.moved_to];
+  h.holds.erase(std::find(h.holds.begin(), h.holds.end(), x.id));
+  x.moved_to = -1;
+  return copy_shares(g, h.sh, 0, x.sh);
+}
+
+// a secret node is computed again: its value is the new one, whoever held the old
+void recomputed(spdz_prog *g, PNode &x) {
+  if (x.moved_to < 0) return;
+  PNode &h = g->nodes[x.moved_to];
+  h.holds.erase(std::find(h.holds.begin(), h.holds.end(), x.id));
+  x.moved_to = -1;
+}
+
+// the secret operands of a node, each in its own buffer
+spdz_status restore_args(spdz_prog *g, const PNode &n) {
+  for (int a : n.args)
+    if (g->nodes[a].secret) SPDZ_RET(restore(g, g->nodes[a]));
+  return SPDZ_OK;
+}
+
+// A phi's value: the source's words (public), its shares (secret), or a public source shared.
+// A secret source that is not a phi hands its buffer over (the two nodes swap buffers; the
+// phi's previous value has no reader left: its readers were issued before the block was
+// entered again, and stream order puts their reads before any later write).
 spdz_status copy_phi(spdz_prog *g, PNode &n) {
   spdz_ctx *c = g->c;
   PNode &s = g->nodes[n.phi_src];
@@ -960,9 +997,22 @@ spdz_status copy_phi(spdz_prog *g, PNode &n) {
     std::memcpy(n.hpub, s.hpub, (size_t)c->L * n.width * 8);
     return n.dev_use ? upload(g, n) : SPDZ_OK;
   }
-  if (s.secret) return copy_shares(g, s.sh, 0, n.sh);
-  g->launches++;
-  return launch_pubop(c, SPDZ_PUB_SHARE, nullptr, s.dpub, s.width, &n.sh);
+  if (!s.secret) {
+    for (int x : std::vector<int>(n.holds)) SPDZ_RET(restore(g, g->nodes[x]));
+    g->launches++;
+    return launch_pubop(c, SPDZ_PUB_SHARE, nullptr, s.dpub, s.width, &n.sh);
+  }
+  if (s.moved_to == n.id) return SPDZ_OK;  // the phi's buffer already holds the source's value
+  // the phi's buffer changes: values it holds for other nodes go back first
+  for (int x : std::vector<int>(n.holds)) SPDZ_RET(restore(g, g->nodes[x]));
+  if (g->handoff && s.op != OP_PHI && s.moved_to < 0) {
+    std::swap(n.sh, s.sh);
+    s.moved_to = n.id;
+    n.holds.push_back(s.id);
+    return SPDZ_OK;
+  }
+  const spdz_shares &from = s.moved_to >= 0 ? g->nodes[s.moved_to].sh : s.sh;
+  return copy_shares(g, from, 0, n.sh);
 }
 
 // waits for the stream; the host words of every open issued so far are then valid
@@ -987,6 +1037,10 @@ spdz_status issue(spdz_prog *g, PNode &n) {
   g->pending_total--;
   for (int l : g->blocks[n.block].loops) g->loops[l].outstanding--;
   spdz_status st = SPDZ_OK;
+  if (n.op != OP_PHI) {  // operands back in their own buffers; the node's old value is superseded
+    SPDZ_RET(restore_args(g, n));
+    if (n.secret) recomputed(g, n);
+  }
   auto host_visit = [&](auto fn) {
     switch (c->fid) {
       case FID_61: fn(F61{}); break;
@@ -1169,6 +1223,8 @@ spdz_status run(spdz_prog *g) {
     PNode &n = kv.second;
     n.inst = 0;
     n.pending = n.queued = n.await_host = false;
+    n.moved_to = -1;
+    n.holds.clear();
     const bool leaf = n.op == OP_INPUT || n.op == OP_CONST;
     n.dev_ready = n.host_ready = leaf && !n.secret;
     if (leaf && n.secret) n.dev_ready = true;
@@ -1196,6 +1252,8 @@ spdz_status run(spdz_prog *g) {
       SPDZ_RET(settle_opens(g));
     }
   }
+  for (int o : g->outputs)  // outputs in their own buffers for spdz_prog_output
+    if (N[o].secret) SPDZ_RET(restore(g, N[o]));
   c->log_count = g->log_cur;
   return SPDZ_OK;
 }
@@ -1336,6 +1394,12 @@ spdz_status spdz_prog_predeal(spdz_prog *g, uint64_t seed, int64_t executions) {
     }
   }
   return hip_status(hipStreamSynchronize(g->c->stream));
+}
+
+spdz_status spdz_prog_set_handoff(spdz_prog *g, int enable) {
+  if (!g) return SPDZ_E_INVAL;
+  g->handoff = enable != 0;
+  return SPDZ_OK;
 }
 
 spdz_status spdz_prog_set_fusion(spdz_prog *g, int enable, int *n_groups) {

@@ -102,6 +102,7 @@ def lib() -> ctypes.CDLL:
             "spdz_prog_run": (i32, [vp, ctypes.c_uint64, ctypes.POINTER(i32), u64p, ctypes.POINTER(ctypes.c_double)]),
             "spdz_prog_predeal": (i32, [vp, ctypes.c_uint64, i64]),
             "spdz_prog_set_fusion": (i32, [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+            "spdz_prog_set_handoff": (i32, [vp, ctypes.c_int]),
             "spdz_prog_output": (i32, [vp, i32, ctypes.POINTER(Shares), vp]),
             "spdz_prog_node_info": (i32, [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_int64)]),
             "spdz_prog_stats": (i32, [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
@@ -575,7 +576,7 @@ class ProgramError(Exception):
 class Program:
     """A control-flow program (text format of workloads.programs) on a context."""
 
-    def __init__(self, ctx: "Context", text: str, fuse: bool = True):
+    def __init__(self, ctx: "Context", text: str, fuse: bool = True, handoff: bool = True):
         self.ctx = ctx
         h = ctypes.c_void_p()
         err = ctypes.create_string_buffer(512)
@@ -584,12 +585,17 @@ class Program:
             raise ProgramError(f"spdz_prog_create: {status_str(st)}: {err.value.decode()}")
         self._h = h
         self.n_groups = self.set_fusion(fuse)
+        self.set_handoff(handoff)
 
     def set_fusion(self, enable: bool) -> int:
         """Fused element-wise runs on or off; returns the number of fused runs of the program."""
         ng = ctypes.c_int(0)
         _check(lib().spdz_prog_set_fusion(self._h, int(bool(enable)), ctypes.byref(ng)), "spdz_prog_set_fusion")
         return ng.value
+
+    def set_handoff(self, enable: bool):
+        """Phi buffer hand-off on (a loop-carried value moves) or off (every phi copies)."""
+        _check(lib().spdz_prog_set_handoff(self._h, int(bool(enable))), "spdz_prog_set_handoff")
 
     def close(self):
         if getattr(self, "_h", None):

@@ -33,22 +33,25 @@ PROGRAMS = [("pipeline", P.pipeline(3001)), ("branch", P.branch(777)), ("loop", 
             ("layer", P.layer(300, 70, 16)), ("layer_public_bias", P.layer_public_bias(300, 70, 16)),
             ("loop_program", P.loop_program(2048, 4)), ("one_block_loop", P.one_block_loop(1000, 5)),
             ("phi_swap", P.phi_swap(777, 4)), ("public_div_mod", P.public_div_mod(1001)),
-            ("public_phi_swap", P.public_phi_swap(999, 6)), ("broadcast", P.broadcast(3001))]
+            ("public_phi_swap", P.public_phi_swap(999, 6)), ("broadcast", P.broadcast(3001)),
+            ("loop_reads_source", P.loop_reads_source(1000, 4))]
 
 
+@pytest.mark.parametrize("handoff", [True, False])
 @pytest.mark.parametrize("fuse", [True, False])
 @pytest.mark.parametrize("p,n", [(P_PAPER, 2), (P61, 3), (P127, 2)])
 @pytest.mark.parametrize("name,text", PROGRAMS)
-def test_program_matches_oracle(name, text, p, n, fuse):
-    """Fused element-wise runs (default) and node-by-node execution both match the oracle."""
+def test_program_matches_oracle(name, text, p, n, fuse, handoff):
+    """Fused element-wise runs (default) and node-by-node execution, phis that take their
+    sources' buffers (default) and phis that copy: all match the oracle."""
     from paper_2512_11112_amd.spdz import Program
     if name.startswith("layer") and p == P127:
         pytest.skip("layers need a single-limb field")
-    print(f"case {name} p-bits={p.bit_length()} n={n} fuse={fuse}", flush=True)
+    print(f"case {name} p-bits={p.bit_length()} n={n} fuse={fuse} handoff={handoff}", flush=True)
     seed, check = 21, 22
     ref = run_program(text, p, n, seed, check)
     ctx = ctx_for(p, n, seed, check)
-    prog = Program(ctx, text, fuse=fuse)
+    prog = Program(ctx, text, fuse=fuse, handoff=handoff)
     ok, sigma, ms = prog.run(seed)
     for o, v in ref["outputs"].items():
         got = prog.output(o)
@@ -78,6 +81,8 @@ def test_program_reruns_are_identical():
     ref2 = run_program(text, p, n, 5, 6, epoch=1)
     assert r1[1] == ints_of_sigma(ref1["sigma"]) and r2[1] == ints_of_sigma(ref2["sigma"])
     assert r1[0] and r2[0]
+    out = prog.output(6)   # the loop's result (a phi that took its source's buffer) after two runs
+    assert np.array_equal(host(out.val), ref2["outputs"][6].val) and np.array_equal(host(out.mac), ref2["outputs"][6].mac)
 
 
 @pytest.mark.parametrize("p,n", [(P_PAPER, 3), (P127, 2)])

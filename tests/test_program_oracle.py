@@ -85,7 +85,8 @@ PROGRAMS = [("pipeline", P.pipeline(37)), ("branch", P.branch(21)), ("loop", P.l
             ("layer", P.layer(9, 7, 3)), ("layer_public_bias", P.layer_public_bias(9, 7, 3)),
             ("loop_program", P.loop_program(16, 3)), ("one_block_loop", P.one_block_loop(12, 4)),
             ("phi_swap", P.phi_swap(6, 5)), ("public_div_mod", P.public_div_mod(11)),
-            ("public_phi_swap", P.public_phi_swap(5, 6)), ("broadcast", P.broadcast(9))]
+            ("public_phi_swap", P.public_phi_swap(5, 6)), ("broadcast", P.broadcast(9)),
+            ("loop_reads_source", P.loop_reads_source(7, 3))]
 
 
 @pytest.mark.parametrize("p,n", [(P_PAPER, 2), (P61, 3), (P_TINY, 2)])

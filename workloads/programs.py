@@ -274,6 +274,38 @@ ret
 """
 
 
+def loop_reads_source(W: int, trips: int) -> str:
+    """The loop program with its back-edge value also read after the loop: acc = x; for i <
+    trips: v = acc y + i, acc = v; then open acc and v - acc (zero) and output v."""
+    return f"""
+input 1 private {W} 0
+input 2 private {W} 1
+const 3 1 {trips}
+const 4 1 0
+const 5 1 1
+output 9
+output 12
+output 14
+block 0
+br 1
+block 1
+6 = phi 1 0 9 2
+7 = phi 4 0 10 2
+8 = lt 7 3
+cbr 8 2 3
+block 2
+11 = mul 6 2
+9 = add 11 7
+10 = add 7 5
+br 1
+block 3
+12 = open 6
+13 = sub 9 6
+14 = open 13
+ret
+"""
+
+
 def nested(W: int, outer: int) -> str:
     """for i < outer: for j < i + 1: acc = acc * y + x; acc opened after every outer
     iteration (its reduction); the inner trip count depends on the outer counter."""
