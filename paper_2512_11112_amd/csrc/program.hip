@@ -963,10 +963,15 @@ __global__ __launch_bounds__(256) void k_bcast(const u64 *__restrict__ src, u64 
 }
 
 // a node whose value was handed to a phi's buffer gets it back (before anything reads it)
+void unhold(PNode &h, int id) {
+  auto it = std::find(h.holds.begin(), h.holds.end(), id);
+  if (it != h.holds.end()) h.holds.erase(it);
+}
+
 spdz_status restore(spdz_prog *g, PNode &x) {
   if (x.moved_to < 0) return SPDZ_OK;
   PNode &h = g->nodes[x.moved_to];
-  h.holds.erase(std::find(h.holds.begin(), h.holds.end(), x.id));
+  unhold(h, x.id);
   x.moved_to = -1;
   return copy_shares(g, h.sh, 0, x.sh);
 }
@@ -974,8 +979,7 @@ spdz_status restore(spdz_prog *g, PNode &x) {
 // a secret node is computed again: its value is the new one, whoever held the old
 void recomputed(spdz_prog *g, PNode &x) {
   if (x.moved_to < 0) return;
-  PNode &h = g->nodes[x.moved_to];
-  h.holds.erase(std::find(h.holds.begin(), h.holds.end(), x.id));
+  unhold(g->nodes[x.moved_to], x.id);
   x.moved_to = -1;
 }
 
