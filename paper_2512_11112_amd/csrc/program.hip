@@ -82,6 +82,12 @@ struct PNode {
   // then lives in the phi's buffer (moved_to) until the source is computed again
   int moved_to = -1;        // node whose buffer holds this node's value, or -1
   std::vector<int> holds;   // (a phi) nodes whose values its buffer holds
+  // a layer over p = 2^32 - 5 runs the packed kernel: its operands one residue per 32-bit word
+  spdz_shares32 pkW{}, pkx{}, pkb{}, pky{};
+  spdz_triple32 tri32{};                 // packed copy of a triple dealt during the run
+  std::vector<spdz_triple32> pool32;     // packed copies of the triples dealt ahead
+  bool w_at_deal = false;                // W is an input, packed when it is dealt
+  std::vector<int> pack_for;             // (an input) layers whose packed W it fills when dealt
 };
 
 struct PBlock {
@@ -428,6 +434,14 @@ spdz_status infer(spdz_prog *g) {
   }
   for (int o : g->outputs)
     if (!N[o].secret) N[o].dev_use = true;
+  // a layer's W that is an input is packed once, when it is dealt (packed layers, p = 2^32 - 5)
+  if (g->c->fid == FID_32)
+    for (int b : g->block_order)
+      for (int id : g->blocks[b].lines)
+        if (N[id].op == OP_LAYER && N[N[id].args[1]].op == OP_INPUT) {
+          N[id].w_at_deal = true;
+          N[N[id].args[1]].pack_for.push_back(id);
+        }
   // a hold for each phi that another phi of its block reads
   std::vector<int> held;
   for (int b : g->block_order)
@@ -631,6 +645,26 @@ spdz_status alloc_shares(spdz_prog *g, spdz_shares &s, int64_t w) {
   return SPDZ_OK;
 }
 
+// packed 32-bit shares of a node-shaped value: [values: n][w] then [MACs: n][w]
+spdz_status alloc_shares32(spdz_prog *g, spdz_shares32 &s, int64_t w) {
+  const size_t words = (size_t)g->c->n * w;
+  u32 *v = nullptr;
+  if (hipMalloc((void **)&v, 2 * words * 4) != hipSuccess) return SPDZ_E_NOMEM;
+  s = spdz_shares32{v, v + words, w, w};
+  return SPDZ_OK;
+}
+
+void free_shares32(spdz_shares32 &s) {
+  if (s.val) hipFree(s.val);
+  s = spdz_shares32{};
+}
+
+void free_triple32(spdz_triple32 &t) {
+  free_shares32(t.a);
+  free_shares32(t.b);
+  free_shares32(t.c);
+}
+
 void free_shares(spdz_shares &s) {
   if (s.val) hipFree(s.val);
   s = spdz_shares{};
@@ -658,6 +692,15 @@ spdz_status alloc_buffers(spdz_prog *g) {
       SPDZ_RET(alloc_shares(g, n.tri.c, dout));
       if (hipMalloc((void **)&n.ltmp, (size_t)(dout * din + tiles * din + dout) * 8) != hipSuccess) return SPDZ_E_NOMEM;
       if (!g->nodes[n.args[2]].secret) SPDZ_RET(alloc_shares(g, n.bsh, dout));
+      if (c->fid == FID_32) {  // the packed kernel's operands and the packed triple of a run-time deal
+        SPDZ_RET(alloc_shares32(g, n.pkW, dout * din));
+        SPDZ_RET(alloc_shares32(g, n.pkx, din));
+        SPDZ_RET(alloc_shares32(g, n.pkb, dout));
+        SPDZ_RET(alloc_shares32(g, n.pky, dout));
+        SPDZ_RET(alloc_shares32(g, n.tri32.a, dout * din));
+        SPDZ_RET(alloc_shares32(g, n.tri32.b, tiles * din));
+        SPDZ_RET(alloc_shares32(g, n.tri32.c, dout));
+      }
     }
   }
   return SPDZ_OK;
@@ -954,6 +997,45 @@ spdz_status issue_group(spdz_prog *g, FGroup &G) {
   return SPDZ_OK;
 }
 
+// residues below 2^32 between the 64-bit node layout and the packed one: both hold the 2 n
+// planes (values, then MACs) of w words back to back, so word i maps to word i
+__global__ __launch_bounds__(256) void k_pack32(const u64 *__restrict__ src, u32 *__restrict__ dst, int64_t total) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256)
+    dst[i] = (u32)src[i];
+}
+
+__global__ __launch_bounds__(256) void k_unpack32(const u32 *__restrict__ src, u64 *__restrict__ dst, int64_t total) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256)
+    dst[i] = src[i];
+}
+
+spdz_status pack32(spdz_prog *g, const spdz_shares &src, spdz_shares32 &dst) {
+  const int64_t total = 2 * (int64_t)g->c->n * src.len;
+  const unsigned grid = (unsigned)std::min<int64_t>((total + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_pack32, dim3(grid), dim3(256), 0, g->c->stream, src.val, dst.val, total);
+  return hip_status(hipGetLastError());
+}
+
+spdz_status unpack32(spdz_prog *g, const spdz_shares32 &src, spdz_shares &dst) {
+  const int64_t total = 2 * (int64_t)g->c->n * dst.len;
+  const unsigned grid = (unsigned)std::min<int64_t>((total + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_unpack32, dim3(grid), dim3(256), 0, g->c->stream, src.val, dst.val, total);
+  return hip_status(hipGetLastError());
+}
+
+spdz_status pack_triple32(spdz_prog *g, const spdz_triple &t, spdz_triple32 &t32) {
+  SPDZ_RET(pack32(g, t.a, t32.a));
+  SPDZ_RET(pack32(g, t.b, t32.b));
+  return pack32(g, t.c, t32.c);
+}
+
+spdz_status alloc_triple32(spdz_prog *g, const PNode &n, spdz_triple32 &t) {
+  const int64_t din = n.imm[0], dout = n.imm[1], tiles = (dout + n.imm[2] - 1) / n.imm[2];
+  SPDZ_RET(alloc_shares32(g, t.a, dout * din));
+  SPDZ_RET(alloc_shares32(g, t.b, tiles * din));
+  return alloc_shares32(g, t.c, dout);
+}
+
 // every one of `planes` rows of `w` words at dst takes the one word of its row at src
 __global__ __launch_bounds__(256) void k_bcast(const u64 *__restrict__ src, u64 *__restrict__ dst, int planes,
                                                int64_t w) {
@@ -1180,6 +1262,21 @@ spdz_status issue(spdz_prog *g, PNode &n) {
         bs = &n.bsh;
         g->launches++;
       }
+      if (st == SPDZ_OK && c->fid == FID_32) {
+        // the packed kernel (half the bytes): operands packed here unless dealt packed, the
+        // triple's packed copy from the pool dealt ahead (or packed now), y unpacked after
+        const int64_t k = n.inst - 1;
+        const spdz_triple32 *t32 = &n.tri32;
+        if (g->pool_seed == g->seed && k < (int64_t)n.pool32.size()) t32 = &n.pool32[k];
+        else st = pack_triple32(g, *t, n.tri32);
+        if (st == SPDZ_OK && !n.w_at_deal) st = pack32(g, W.sh, n.pkW);
+        if (st == SPDZ_OK) st = pack32(g, x.sh, n.pkx);
+        if (st == SPDZ_OK) st = pack32(g, *bs, n.pkb);
+        if (st == SPDZ_OK) st = launch_linear_layer32(c, dout, din, tr, &n.pkW, &n.pkx, &n.pkb, t32, &n.pky, nullptr, nullptr);
+        if (st == SPDZ_OK) st = unpack32(g, n.pky, n.sh);
+        g->launches += 5;
+        break;
+      }
       if (st == SPDZ_OK) st = launch_linear_layer(c, dout, din, tr, &W.sh, &x.sh, bs, t, &n.sh, nullptr, nullptr, nullptr);
       g->launches += 2;
       break;
@@ -1268,6 +1365,7 @@ spdz_status deal_inputs(spdz_prog *g) {
     PNode &n = g->nodes[id];
     if (n.op == OP_INPUT && n.secret) {
       SPDZ_RET(launch_deal_secret(c, g->seed, (u64)n.imm[0], nullptr, &n.sh, nullptr));
+      for (int l : n.pack_for) SPDZ_RET(pack32(g, n.sh, g->nodes[l].pkW));
     } else {
       // public input: elements of the array's value stream; constant: every entry the value
       visit(c, [&](auto f, auto) -> spdz_status {
@@ -1308,6 +1406,9 @@ void destroy(spdz_prog *g) {
     if (n.dpub) hipFree(n.dpub);
     if (n.hpub) hipHostFree(n.hpub);
     if (n.ltmp) hipFree(n.ltmp);
+    for (spdz_shares32 *p : {&n.pkW, &n.pkx, &n.pkb, &n.pky}) free_shares32(*p);
+    free_triple32(n.tri32);
+    for (auto &t : n.pool32) free_triple32(t);
   }
   delete g;
 }
@@ -1379,6 +1480,8 @@ spdz_status spdz_prog_predeal(spdz_prog *g, uint64_t seed, int64_t executions) {
       free_shares(t.c);
     }
     n.pool.clear();
+    for (auto &t : n.pool32) free_triple32(t);
+    n.pool32.clear();
   }
   g->pool_seed = seed;
   for (auto &kv : g->nodes) {
@@ -1395,6 +1498,13 @@ spdz_status spdz_prog_predeal(spdz_prog *g, uint64_t seed, int64_t executions) {
       if (st == SPDZ_OK) st = deal_node_triple(g, n, k, seed, t);
       n.pool.push_back(t);
       if (st != SPDZ_OK) return st;
+      if (n.op == OP_LAYER && g->c->fid == FID_32) {  // the packed kernel's copy, made ahead as well
+        spdz_triple32 t32{};
+        st = alloc_triple32(g, n, t32);
+        if (st == SPDZ_OK) st = pack_triple32(g, t, t32);
+        n.pool32.push_back(t32);
+        if (st != SPDZ_OK) return st;
+      }
     }
   }
   return hip_status(hipStreamSynchronize(g->c->stream));
