@@ -160,7 +160,9 @@ spdz_status launch_reduce(spdz_ctx *c, const spdz_shares *x, spdz_shares *out);
 // One instruction of a fused element-wise group of the program runtime (fused.hip).  Slots
 // are per-thread LDS registers holding one secret value (n value and n MAC shares); a
 // node buffer is the runtime's layout [values: n][L][W] then [MACs: n][L][W].
-enum FusedKind : uint8_t { FK_LOAD = 0, FK_BEAVER = 1, FK_LIN = 2, FK_PUBADD = 3, FK_PUBMUL = 4 };
+// FK_LOADS: `flags` (1..3) external operands at p0, p1, p2 into slots dst, a, b, all requested
+// before any is stored (one memory round trip for all of them)
+enum FusedKind : uint8_t { FK_LOAD = 0, FK_BEAVER = 1, FK_LIN = 2, FK_PUBADD = 3, FK_PUBMUL = 4, FK_LOADS = 5 };
 enum FusedFlag : uint8_t { FF_STORE = 1, FF_SUB = 2, FF_NEG_A = 4, FF_NEG_P = 8, FF_PUB_VEC = 16 };
 struct FusedIns {
   uint8_t kind, dst, a, b, flags, pad[3];

@@ -63,6 +63,28 @@ __global__ __launch_bounds__(BLOCK) void k_fused(const FusedArgs<F, N> A) {
         }
         continue;
       }
+      if constexpr (2 * N * L <= 12) {  // (the runtime merges loads only while they fit 24 words)
+      if (I.kind == FK_LOADS) {  // two or three operands, every word requested before any store
+        constexpr int MJ = 24 / (2 * N * L) < 3 ? 24 / (2 * N * L) : 3;  // the runtime's most per step
+        E v[MJ][2 * N];
+        const u64 *src[3] = {I.p0, I.p1, I.p2};
+#pragma unroll
+        for (int j = 0; j < MJ; j++)
+          if (j < I.flags)
+#pragma unroll
+            for (int i = 0; i < N; i++) {
+              v[j][i] = F::load(src[j] + i * plane, W, e);
+              v[j][N + i] = F::load(src[j] + half + i * plane, W, e);
+            }
+        const int dst[3] = {I.dst, I.a, I.b};
+#pragma unroll
+        for (int j = 0; j < MJ; j++)
+          if (j < I.flags)
+#pragma unroll
+            for (int k = 0; k < 2 * N; k++) put(dst[j], k, v[j][k]);
+        continue;
+      }
+      }
       if (I.kind == FK_BEAVER) {
         E av[N], bv[N];
         E d = F::zero(), ee = F::zero();

@@ -110,8 +110,9 @@ struct Loop {
 struct FGroup {
   struct Step {
     uint8_t kind, dst, a, b, flags;
-    int node;  // LOAD: the external node; otherwise the member computed
+    int node;  // LOAD(S): the (first) external node; otherwise the member computed
     int pub;   // public operand of FK_PUBADD / FK_PUBMUL
+    int node2 = -1, node3 = -1;  // LOADS: the second and third external nodes
   };
   std::vector<int> members;  // program order; members[0] represents the group in the queues
   std::vector<Step> plan;
@@ -548,15 +549,28 @@ bool compile_group(spdz_prog *g, const std::vector<int> &run, int maxs, FGroup &
     return true;
   };
   G = FGroup{};
-  for (size_t k = 0; k < run.size(); k++) {
-    const PNode &n = N[run[k]];
-    for (int a : n.args)
-      if (N[a].secret && !slot.count(a)) {  // an external secret operand: load it
+  // every external secret operand is loaded up front, up to three per step, so that one
+  // memory round trip brings several of them (as many words per step as registers allow)
+  std::vector<int> ext;
+  for (size_t k = 0; k < run.size(); k++)
+    for (int a : N[run[k]].args)
+      if (N[a].secret && !idx.count(a) && !slot.count(a)) {
         int q;
         if (!take(q)) return false;
         slot[a] = q;
-        G.plan.push_back({FK_LOAD, (uint8_t)q, 0, 0, 0, a, -1});
+        ext.push_back(a);
       }
+  const int words = 2 * g->c->n * g->c->L, per_step = std::max(1, std::min(3, 24 / words));
+  for (size_t i = 0; i < ext.size(); i += per_step) {
+    const int m = (int)std::min<size_t>(per_step, ext.size() - i);
+    FGroup::Step st{m == 1 ? FK_LOAD : FK_LOADS, (uint8_t)slot[ext[i]], 0, 0, (uint8_t)m, ext[i], -1};
+    if (m > 1) st.a = (uint8_t)slot[ext[i + 1]], st.node2 = ext[i + 1];
+    if (m > 2) st.b = (uint8_t)slot[ext[i + 2]], st.node3 = ext[i + 2];
+    if (m == 1) st.flags = 0;
+    G.plan.push_back(st);
+  }
+  for (size_t k = 0; k < run.size(); k++) {
+    const PNode &n = N[run[k]];
     int dst;
     if (!take(dst)) return false;  // never an operand's slot: operands are read while it is written
     FGroup::Step st{0, (uint8_t)dst, 0, 0, 0, n.id, -1};
@@ -954,7 +968,9 @@ spdz_status issue_group(spdz_prog *g, FGroup &G) {
   auto &N = g->nodes;
   G.queued = false;
   for (const FGroup::Step &st : G.plan)
-    if (st.kind == FK_LOAD) SPDZ_RET(restore(g, N[st.node]));
+    if (st.kind == FK_LOAD || st.kind == FK_LOADS)
+      for (int x : {st.node, st.node2, st.node3})
+        if (x >= 0) SPDZ_RET(restore(g, N[x]));
   for (int id : G.members) recomputed(g, N[id]);
   FusedIns ins[FUSED_MAX_INS];
   for (size_t q = 0; q < G.plan.size(); q++) {
@@ -967,8 +983,10 @@ spdz_status issue_group(spdz_prog *g, FGroup &G) {
     I.b = st.b;
     I.flags = st.flags;
     PNode &m = N[st.node];
-    if (st.kind == FK_LOAD) {
+    if (st.kind == FK_LOAD || st.kind == FK_LOADS) {
       I.p0 = m.sh.val;
+      if (st.node2 >= 0) I.p1 = N[st.node2].sh.val;
+      if (st.node3 >= 0) I.p2 = N[st.node3].sh.val;
       continue;
     }
     if (st.kind == FK_BEAVER) {
