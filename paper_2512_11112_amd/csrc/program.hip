@@ -23,6 +23,13 @@
 // a statically known number of values, so at block entry every opening of the
 // block receives its position in the program-order log; out-of-order issue
 // then produces exactly the sequential program's MAC-check sums.
+//
+// Phis take the values their sources held when the block was entered (as LLVM's
+// do): a phi whose source the entered block recomputes is copied at entry. A
+// secret phi whose source is not a phi takes the source's buffer instead of a
+// copy (the source's value is copied back only if read before it is recomputed).
+// Runs of consecutive secret element-wise nodes execute as one fused kernel, and a
+// layer over p = 2^32 - 5 runs the packed 32-bit kernel.
 #include <algorithm>
 #include <chrono>
 #include <cstring>
