@@ -53,6 +53,13 @@ def test_program_matches_oracle(name, text, p, n, fuse, handoff):
     ctx = ctx_for(p, n, seed, check)
     prog = Program(ctx, text, fuse=fuse, handoff=handoff)
     ok, sigma, ms = prog.run(seed)
+    check_run(prog, ref, ok, sigma, ms, name)
+    prog.close()
+
+
+def check_run(prog, ref, ok, sigma, ms, name):
+    """Every output (shares and MAC shares, or public values), the verdict, every sigma_i,
+    the block entries and the number of opened values equal the oracle's."""
     for o, v in ref["outputs"].items():
         got = prog.output(o)
         if isinstance(v, F.Shares):
@@ -66,7 +73,29 @@ def test_program_matches_oracle(name, text, p, n, fuse, handoff):
     assert st["block_entries"] == ref["entries"]
     assert st["opened"] == sum(o.shape[1] for o in ref["opened"])
     assert ms > 0
-    prog.close()
+
+
+@pytest.mark.parametrize("seed", range(160))
+def test_random_program_matches_oracle(seed):
+    """Seeded random programs (public branches merged by phis that may mix a public and a
+    secret value, loops of one block whose phis may take each other's values, zero-trip
+    header loops, nested regions, opens fed back as public operands, sums broadcast back)
+    at widths 1 .. 4099 over the three fields: fused and node by node, phis handing off
+    their buffers and copying, each equal to the oracle."""
+    from paper_2512_11112_amd.spdz import Program
+    p, n = [(P_PAPER, 2), (P61, 3), (P127, 2), (P_PAPER, 3)][seed % 4]
+    W = [1, 63, 64, 65, 1000, 4099][seed // 4 % 6]
+    text = P.random_program(seed, W, regions=4 + seed % 5, depth=3 if seed % 3 == 0 else 2)
+    ref = run_program(text, p, n, seed, seed + 1)
+    for fuse, handoff in ((True, True), (True, False), (False, True), (False, False)):
+        print(f"case random seed={seed} W={W} p-bits={p.bit_length()} n={n} fuse={fuse} handoff={handoff}",
+              flush=True)
+        ctx = ctx_for(p, n, seed, seed + 1)
+        prog = Program(ctx, text, fuse=fuse, handoff=handoff)
+        ok, sigma, ms = prog.run(seed)
+        check_run(prog, ref, ok, sigma, ms, f"random {seed}")
+        prog.close()
+        ctx.close()
 
 
 def test_program_reruns_are_identical():

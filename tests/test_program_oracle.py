@@ -89,19 +89,20 @@ PROGRAMS = [("pipeline", P.pipeline(37)), ("branch", P.branch(21)), ("loop", P.l
             ("loop_reads_source", P.loop_reads_source(7, 3))]
 
 
-@pytest.mark.parametrize("p,n", [(P_PAPER, 2), (P61, 3), (P_TINY, 2)])
-@pytest.mark.parametrize("name,text", PROGRAMS)
-def test_program_reconstructs_plaintext(name, text, p, n):
-    if name == "revealed_branch" and p == P_TINY:
-        pytest.skip("its constant exceeds p = 101")
-    res = run_program(text, p, n, 5, 5)
-    plain, plain_open, entries = plain_run(text, p, 5)
-    al = sum(int(a) for a in F.from_limbs(res["alpha"].T.copy())) % p
+def check_reconstructs(text: str, p: int, n: int, seed: int = 5):
+    """The oracle's shares of every output reconstruct to the cleartext run's values (MAC
+    shares to alpha times them), every open's plaintext appears in the opened log in order,
+    the block-entry counts agree and the MAC check accepts."""
+    res = run_program(text, p, n, seed, seed)
+    plain, plain_open, entries = plain_run(text, p, seed)
+    al = sum(F.from_limbs(res["alpha"].T.copy())) % p
     for o, v in res["outputs"].items():
         want = plain[o]
         if isinstance(v, F.Shares):
-            got = [sum(int(v.val[i, 0, e]) for i in range(n)) % p for e in range(v.width)]
-            gotm = [sum(int(v.mac[i, 0, e]) for i in range(n)) % p for e in range(v.width)]
+            vals = [F.from_limbs(v.val[i]) for i in range(n)]
+            macs = [F.from_limbs(v.mac[i]) for i in range(n)]
+            got = [sum(q[e] for q in vals) % p for e in range(v.width)]
+            gotm = [sum(q[e] for q in macs) % p for e in range(v.width)]
             assert got == want, f"output {o}"
             assert gotm == [al * x % p for x in want], f"output {o} MAC"
         else:
@@ -113,6 +114,24 @@ def test_program_reconstructs_plaintext(name, text, p, n):
         assert any(got == want for got in it)
     assert res["entries"] == entries
     assert res["ok"] and sum(int(s) for s in F.from_limbs(res["sigma"].T.copy())) % p == 0
+
+
+@pytest.mark.parametrize("p,n", [(P_PAPER, 2), (P61, 3), (P_TINY, 2)])
+@pytest.mark.parametrize("name,text", PROGRAMS)
+def test_program_reconstructs_plaintext(name, text, p, n):
+    if name == "revealed_branch" and p == P_TINY:
+        pytest.skip("its constant exceeds p = 101")
+    check_reconstructs(text, p, n)
+
+
+@pytest.mark.parametrize("seed", range(160))
+def test_random_program_reconstructs_plaintext(seed):
+    """Seeded random programs (branches merged by phis mixing public and secret values, loops
+    of one block with phis that take each other's values, zero-trip loops, nested regions,
+    opens fed back as public operands) over the four fields and widths 1..9."""
+    p, n = [(P_PAPER, 2), (P61, 3), (P_TINY, 2), (P127, 2)][seed % 4]
+    text = P.random_program(seed, [1, 2, 5, 9][seed // 4 % 4], regions=4 + seed % 5, depth=3 if seed % 3 == 0 else 2)
+    check_reconstructs(text, p, n)
 
 
 def test_loop_closed_form():

@@ -502,3 +502,226 @@ block 3
 15 = open 16
 ret
 """
+
+
+def random_program(seed: int, W: int, regions: int = 5, depth: int = 2) -> str:
+    """A seeded random program over vectors of width W: straight runs of +, -, * (secret by
+    secret, by a public vector, by a public scalar), shl, select, opens whose values come back
+    as public operands, secret or public sums broadcast back to W lanes, public div / mod;
+    public branches (on a public input or on an opened sum's parity) merged by phis that may
+    mix a public and a secret value; loops of one block (counter, carried phis, sometimes two
+    phis that take each other's values, body values read after the loop) and of a header and
+    a body (0..3 trips, nested regions in the body).  Every loop has a literal trip count, so
+    every program ends; constants stay below 101, so every field of the format accepts them."""
+    import random
+    rng = random.Random(seed)
+    head, order, body = [], [], {}
+    ids = [0]
+    consts = {}
+    cur = [0]
+    secret = {}
+
+    def new():
+        ids[0] += 1
+        return ids[0]
+
+    def const(v):
+        if v not in consts:
+            c = new()
+            consts[v] = c
+            head.append(f"const {c} 1 {v}")
+        return consts[v]
+
+    def start(b):
+        cur[0] = b
+        body[b] = []
+        order.append(b)
+
+    def emit(line):
+        body[cur[0]].append(line)
+
+    nblk = [1]
+
+    def newblock():
+        nblk[0] += 1
+        return nblk[0] - 1
+
+    xs = [new() for _ in range(3)]
+    for k, v in enumerate(xs):
+        head.append(f"input {v} private {W} {k}")
+        secret[v] = True
+    pv = new()
+    head.append(f"input {pv} public {W} 3")
+    secret[pv] = False
+    ps = new()
+    head.append(f"input {ps} public 1 4")
+
+    def put(v, is_secret, S, P):
+        secret[v] = is_secret
+        (S if is_secret else P).append(v)
+        return v
+
+    def elementwise(S, P, out=None, a=None):
+        """one secret result of width W, written to `out` if given; `a`, the secret operand,
+        drawn from S if not given"""
+        v = new() if out is None else out
+        a = rng.choice(S) if a is None else a
+        r = rng.random()
+        if r < 0.28:
+            emit(f"{v} = mul {a} {rng.choice(S)}")
+        elif r < 0.38:
+            emit(f"{v} = mul {rng.choice(P)} {a}")
+        elif r < 0.46:
+            emit(f"{v} = mul {a} {const(rng.randrange(2, 100))}")
+        elif r < 0.64:
+            emit(f"{v} = add {a} {rng.choice(S + P)}")
+        elif r < 0.80:
+            b = rng.choice(S + P)
+            emit(f"{v} = sub {b} {a}" if rng.random() < 0.5 else f"{v} = sub {a} {b}")
+        elif r < 0.86:
+            emit(f"{v} = add {rng.choice([ps, const(rng.randrange(0, 100))])} {a}")
+        elif r < 0.93:
+            emit(f"{v} = shl {a} {rng.randrange(0, 40)}")
+        else:
+            emit(f"{v} = select {rng.choice(S + P)} {a} {rng.choice(S + P)}")
+        secret[v] = True
+        return v
+
+    def straight(S, P, k):
+        for _ in range(k):
+            r = rng.random()
+            if r < 0.08:
+                put(new(), False, S, P)
+                emit(f"{P[-1]} = open {rng.choice(S)}")
+            elif r < 0.14:
+                src = rng.choice(S + P)
+                s, b = new(), new()
+                emit(f"{s} = reduce {src}")
+                emit(f"{b} = bcast {s} {W}")
+                put(b, secret[src], S, P)
+            elif r < 0.20:
+                q = new()
+                emit(f"{q} = {rng.choice(['add', 'mul', 'sub'])} {rng.choice(P)} {rng.choice(P)}")
+                put(q, False, S, P)
+            elif r < 0.24:
+                q = new()
+                emit(f"{q} = {rng.choice(['div', 'mod'])} {rng.choice(P)} {rng.randrange(1, 9)}")
+                put(q, False, S, P)
+            else:
+                S.append(elementwise(S, P))
+
+    def branch_region(S, P, d):
+        if rng.random() < 0.5:
+            c = new()
+            emit(f"{c} = lt {ps} {const(rng.randrange(0, 100))}")
+        else:
+            s, o, c = new(), new(), new()
+            emit(f"{s} = reduce {rng.choice(S)}")
+            emit(f"{o} = open {s}")
+            emit(f"{c} = mod {o} 2")
+        T, Fb, M = newblock(), newblock(), newblock()
+        emit(f"cbr {c} {T} {Fb}")
+        sides = []
+        for b in (T, Fb):
+            start(b)
+            S2, P2 = list(S), list(P)
+            region_seq(S2, P2, d - 1, rng.randint(0, 2))
+            sides.append((cur[0], S2, P2))
+            emit(f"br {M}")
+        start(M)
+        (bt, St, Pt), (bf, Sf, Pf) = sides
+        for _ in range(rng.randint(1, 3)):
+            vt, vf = rng.choice(St + Pt), rng.choice(Sf + Pf)
+            ph = new()
+            emit(f"{ph} = phi {vt} {bt} {vf} {bf}")
+            put(ph, secret[vt] or secret[vf], S, P)
+
+    def one_block_loop(S, P):
+        pre, L, X = cur[0], newblock(), newblock()
+        emit(f"br {L}")
+        start(L)
+        trips = rng.randint(1, 4)
+        i, inx = new(), new()
+        k = rng.randint(1, 3)
+        phis = [new() for _ in range(k)]
+        inits = [rng.choice(S + P) for _ in range(k)]
+        swap = k >= 2 and rng.random() < 0.4
+        nexts = [new() for _ in range(k)]
+        if swap:
+            nexts[0], nexts[1] = phis[1], phis[0]
+        emit(f"{i} = phi {const(0)} {pre} {inx} {L}")
+        base = list(S)  # secret whatever the loop's phis turn out to be
+        for ph, ini, nx in zip(phis, inits, nexts):
+            emit(f"{ph} = phi {ini} {pre} {nx} {L}")
+        for j, ph in enumerate(phis):
+            if swap and j < 2:
+                put(ph, secret[inits[0]] or secret[inits[1]], S, P)
+            else:
+                put(ph, True, S, P)
+        if not S:
+            S.append(xs[0])
+        straight(S, P, rng.randint(0, 3))
+        for j, nx in enumerate(nexts):
+            if not (swap and j < 2):
+                S.append(elementwise(S, P, out=nx, a=rng.choice(base)))
+        c = new()
+        emit(f"{inx} = add {i} {const(1)}")
+        emit(f"{c} = lt {inx} {const(trips)}")
+        emit(f"cbr {c} {L} {X}")
+        start(X)
+
+    def header_loop(S, P, d):
+        pre, H, B, X = cur[0], newblock(), newblock(), newblock()
+        emit(f"br {H}")
+        start(H)
+        hlines = body[H]
+        trips = rng.randint(0, 3)
+        i, inx = new(), new()
+        k = rng.randint(1, 3)
+        phis = [new() for _ in range(k)]
+        inits = [rng.choice(S + P) for _ in range(k)]
+        nexts = [new() for _ in range(k)]
+        c = new()
+        start(B)
+        base = list(S)
+        S2, P2 = list(S), list(P)
+        for ph in phis:
+            put(ph, True, S2, P2)
+        region_seq(S2, P2, d - 1, rng.randint(1, 2))
+        for nx in nexts:
+            S2.append(elementwise(S2, P2, out=nx, a=rng.choice(base)))
+        emit(f"{inx} = add {i} {const(1)}")
+        emit(f"br {H}")
+        back = cur[0]
+        hlines.append(f"{i} = phi {const(0)} {pre} {inx} {back}")
+        for ph, ini, nx in zip(phis, inits, nexts):
+            hlines.append(f"{ph} = phi {ini} {pre} {nx} {back}")
+        hlines.append(f"{c} = lt {i} {const(trips)}")
+        hlines.append(f"cbr {c} {B} {X}")
+        for ph in phis:
+            put(ph, True, S, P)
+        start(X)
+
+    def region_seq(S, P, d, count):
+        for _ in range(count):
+            r = rng.random()
+            if d > 0 and r < 0.25:
+                branch_region(S, P, d)
+            elif d > 0 and r < 0.45:
+                one_block_loop(S, P)
+            elif d > 0 and r < 0.6:
+                header_loop(S, P, d)
+            else:
+                straight(S, P, rng.randint(1, 4))
+
+    start(0)
+    S, P = list(xs), [pv]
+    region_seq(S, P, depth, regions)
+    outs = rng.sample(S, min(3, len(S))) + rng.sample(P, min(1, len(P)))
+    emit("ret")
+    head += [f"output {o}" for o in dict.fromkeys(outs)]
+    lines = head[:]
+    for b in order:
+        lines.append(f"block {b}")
+        lines += body[b]
+    return "\n".join(lines) + "\n"
