@@ -67,6 +67,7 @@ template <int N>
 struct LevelArgs {
   const DagOpDev *ops;       // op table of the DAG
   const int32_t *list;       // indices of this launch's ops (ascending tile0)
+  const int32_t *item_op;    // per work item of the launch, its op (null: the launch's one op, list[0])
   int32_t nlist;
   int64_t item0;             // first work item of this launch (tile0 of a single-op launch)
   int64_t total_tiles;
@@ -193,8 +194,6 @@ __device__ __forceinline__ void beaver_out(const LevelArgs<N> &A, const DagOpDev
   mc[0] = F::add(mc[0], F::wreduce(t));
 }
 
-constexpr int LTAB = 1024;  // launches of up to this many ops keep their op table in LDS
-
 template <int N>
 __global__ __launch_bounds__(BLOCK) void k_dag_level(const LevelArgs<N> A) {
   using F = F61;
@@ -204,30 +203,12 @@ __global__ __launch_bounds__(BLOCK) void k_dag_level(const LevelArgs<N> A) {
   for (int k = 0; k <= N; k++) mc[k] = F::zero();
   const u64 cstate = A.params->coef_state;
   const int64_t jb = A.params->j_base;
-  // the launch's op ids and first work items, read once per block into LDS: the search for
-  // an item's op then costs LDS reads instead of a chain of dependent global loads
-  __shared__ int64_t s_t0[LTAB];
-  __shared__ int32_t s_op[LTAB];
-  const bool tab = A.nlist > 1 && A.nlist <= LTAB;
-  if (tab) {
-    for (int i = threadIdx.x; i < A.nlist; i += BLOCK) {
-      const int32_t k = A.list[i];
-      s_op[i] = k;
-      s_t0[i] = A.ops[k].tile0;
-    }
-    __syncthreads();
-  }
   for (int64_t item = A.item0 + blockIdx.x; item < A.total_tiles; item += gridDim.x) {
-    // op owning this work item: last list entry with tile0 <= item
-    int lo = 0, hi = A.nlist - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if ((tab ? s_t0[mid] : A.ops[A.list[mid]].tile0) <= item) lo = mid;
-      else hi = mid - 1;
-    }
-    // the op is the same for the whole block: its descriptor goes to scalar registers, and the
-    // arrays are addressed as a uniform base plus a 32-bit lane offset
-    const DagOpDev op = A.ops[__builtin_amdgcn_readfirstlane(tab ? s_op[lo] : A.list[lo])];
+    // the work item's op (from the launch's item table: two dependent scalar loads reach its
+    // descriptor); the op is the same for the whole block, so the descriptor sits in scalar
+    // registers and the arrays are addressed as a uniform base plus a 32-bit lane offset
+    const int32_t k = A.item_op ? A.item_op[item] : A.list[0];
+    const DagOpDev op = A.ops[__builtin_amdgcn_readfirstlane(k)];
     const int64_t w = op.width;
     const int64_t e0 = (item - op.tile0) * A.tile;
     const int64_t e1 = min(e0 + (int64_t)A.tile, w);
@@ -279,6 +260,8 @@ struct spdz_dag {
   u64 *nval = nullptr, *nmac = nullptr, *tval = nullptr, *tmac = nullptr;
   DagOpDev *d_ops = nullptr;
   int32_t *d_list = nullptr;
+  int32_t *d_item = nullptr;  // per work item of a plan, its op (grown as plans need)
+  int64_t item_cap = 0;
   DagParams *d_params = nullptr;
   std::vector<DagOpDev> h_ops;
   // launch shape (autotuned)
@@ -324,6 +307,8 @@ struct spdz_dag {
   // the graph's plan lives in its own buffers so later non-graph runs cannot change it
   DagOpDev *d_ops_graph = nullptr;
   int32_t *d_list_graph = nullptr;
+  int32_t *d_item_graph = nullptr;
+  int64_t item_cap_graph = 0;
   int graph_slots = 0;
   u64 *tune_acc = nullptr;  // accumulator slots written while autotuning (never checked)
 };
@@ -456,6 +441,8 @@ spdz_status spdz_dag_destroy(spdz_dag *g) {
   if (g->d_params) (void)hipFree(g->d_params);
   if (g->d_ops_graph) (void)hipFree(g->d_ops_graph);
   if (g->d_list_graph) (void)hipFree(g->d_list_graph);
+  for (int32_t *p : {g->d_item, g->d_item_graph})
+    if (p) (void)hipFree(p);
   if (g->tune_acc) (void)hipFree(g->tune_acc);
   for (float *p : {g->d_model, g->d_feat, g->d_pred})
     if (p) (void)hipFree(p);
@@ -534,12 +521,14 @@ struct LaunchTarget {
 };
 
 template <int N>
-static spdz_status launch_level_n(spdz_dag *g, const DagOpDev *d_ops, const int32_t *d_list, int32_t cnt,
-                                  int64_t item0, int64_t total_tiles, int tile, int bpc, const LaunchTarget &T) {
+static spdz_status launch_level_n(spdz_dag *g, const DagOpDev *d_ops, const int32_t *d_list, const int32_t *d_item,
+                                  int32_t cnt, int64_t item0, int64_t total_tiles, int tile, int bpc,
+                                  const LaunchTarget &T) {
   spdz_ctx *c = g->c;
   LevelArgs<N> A;
   A.ops = d_ops;
   A.list = d_list;
+  A.item_op = d_item;
   A.nlist = cnt;
   A.item0 = item0;
   A.total_tiles = total_tiles;
@@ -560,16 +549,16 @@ static spdz_status launch_level_n(spdz_dag *g, const DagOpDev *d_ops, const int3
   return hip_status(hipGetLastError());
 }
 
-static spdz_status launch_level(spdz_dag *g, const DagOpDev *d_ops, const int32_t *d_list, int32_t cnt, int64_t item0,
-                                int64_t total_tiles, int tile, int bpc, const LaunchTarget &T) {
+static spdz_status launch_level(spdz_dag *g, const DagOpDev *d_ops, const int32_t *d_list, const int32_t *d_item,
+                                int32_t cnt, int64_t item0, int64_t total_tiles, int tile, int bpc, const LaunchTarget &T) {
   switch (g->c->n) {
-    case 2: return launch_level_n<2>(g, d_ops, d_list, cnt, item0, total_tiles, tile, bpc, T);
-    case 3: return launch_level_n<3>(g, d_ops, d_list, cnt, item0, total_tiles, tile, bpc, T);
-    case 4: return launch_level_n<4>(g, d_ops, d_list, cnt, item0, total_tiles, tile, bpc, T);
-    case 5: return launch_level_n<5>(g, d_ops, d_list, cnt, item0, total_tiles, tile, bpc, T);
-    case 6: return launch_level_n<6>(g, d_ops, d_list, cnt, item0, total_tiles, tile, bpc, T);
-    case 7: return launch_level_n<7>(g, d_ops, d_list, cnt, item0, total_tiles, tile, bpc, T);
-    case 8: return launch_level_n<8>(g, d_ops, d_list, cnt, item0, total_tiles, tile, bpc, T);
+    case 2: return launch_level_n<2>(g, d_ops, d_list, d_item, cnt, item0, total_tiles, tile, bpc, T);
+    case 3: return launch_level_n<3>(g, d_ops, d_list, d_item, cnt, item0, total_tiles, tile, bpc, T);
+    case 4: return launch_level_n<4>(g, d_ops, d_list, d_item, cnt, item0, total_tiles, tile, bpc, T);
+    case 5: return launch_level_n<5>(g, d_ops, d_list, d_item, cnt, item0, total_tiles, tile, bpc, T);
+    case 6: return launch_level_n<6>(g, d_ops, d_list, d_item, cnt, item0, total_tiles, tile, bpc, T);
+    case 7: return launch_level_n<7>(g, d_ops, d_list, d_item, cnt, item0, total_tiles, tile, bpc, T);
+    case 8: return launch_level_n<8>(g, d_ops, d_list, d_item, cnt, item0, total_tiles, tile, bpc, T);
   }
   return SPDZ_E_UNSUPPORTED;
 }
@@ -585,6 +574,8 @@ struct GpuPlan {
   std::vector<int64_t> tile0;        // per list entry: first work item within its batch
   std::vector<int64_t> batch_begin;  // list index of each batch's first op (+ end sentinel)
   std::vector<int64_t> batch_tiles;  // work items per batch
+  std::vector<int32_t> item_op;      // per work item (batches one after another), its op
+  std::vector<int64_t> batch_item0;  // index in item_op of each batch's first work item
   std::vector<int64_t> level_batch;  // first batch of each level (+ end sentinel)
   std::vector<int64_t> urgent_batch; // per level: the batch after which the level's urgent outputs are complete, -1 if none
   int64_t early_flushes = 0;         // batches cut before a level's queue emptied
@@ -609,12 +600,14 @@ static void make_plan(spdz_dag *g, const std::vector<uint8_t> &on_gpu, int tile,
         if (!on_gpu[k] || heavy != want_heavy || urg != want_urgent) continue;
         if (!open) {
           plan.batch_begin.push_back((int64_t)plan.list.size());
+          plan.batch_item0.push_back((int64_t)plan.item_op.size());
           tiles = elems = 0;
           open = true;
         }
         g->h_ops[k].tile0 = tiles;
         plan.tile0.push_back(tiles);
         tiles += tiles_of(g->ops[k].width, tile);
+        plan.item_op.insert(plan.item_op.end(), (size_t)tiles_of(g->ops[k].width, tile), k);
         elems += g->ops[k].width;
         plan.list.push_back(k);
         if (urg) plan.urgent_batch[l] = (int64_t)plan.batch_begin.size() - 1;
@@ -632,7 +625,22 @@ static void make_plan(spdz_dag *g, const std::vector<uint8_t> &on_gpu, int tile,
   plan.batch_begin.push_back((int64_t)plan.list.size());
 }
 
-static spdz_status upload_plan(spdz_dag *g, const GpuPlan &plan, DagOpDev *d_ops, int32_t *d_list, hipStream_t st) {
+// the plan's op list, item table and op descriptors to the device; the item table's buffer
+// grows (after the stream has drained) when a plan needs more work items than it holds
+static spdz_status upload_plan(spdz_dag *g, const GpuPlan &plan, DagOpDev *d_ops, int32_t *d_list, int32_t *&d_item,
+                               int64_t &item_cap, hipStream_t st) {
+  const int64_t ni = (int64_t)plan.item_op.size();
+  if (ni > item_cap) {
+    SPDZ_RET(hip_status(hipStreamSynchronize(st)));
+    if (d_item) (void)hipFree(d_item);
+    const int64_t want = std::max<int64_t>(ni, 2 * item_cap);
+    d_item = nullptr;
+    item_cap = 0;
+    if (hipMalloc((void **)&d_item, want * sizeof(int32_t)) != hipSuccess) return SPDZ_E_NOMEM;
+    item_cap = want;
+  }
+  if (ni > 0)
+    SPDZ_RET(hip_status(hipMemcpyAsync(d_item, plan.item_op.data(), ni * sizeof(int32_t), hipMemcpyHostToDevice, st)));
   if (!plan.list.empty())
     SPDZ_RET(hip_status(
         hipMemcpyAsync(d_list, plan.list.data(), plan.list.size() * sizeof(int32_t), hipMemcpyHostToDevice, st)));
@@ -643,19 +651,20 @@ static spdz_status upload_plan(spdz_dag *g, const GpuPlan &plan, DagOpDev *d_ops
 
 // batches [b0, b1) of a plan: one fused launch per batch (mode 1) or one launch per op (mode 0)
 static spdz_status enqueue_batches(spdz_dag *g, const GpuPlan &plan, const DagOpDev *d_ops, const int32_t *d_list,
-                                   int64_t b0, int64_t b1, int mode, int tile, int bpc, const LaunchTarget &T,
-                                   int64_t *launches = nullptr) {
+                                   const int32_t *d_item, int64_t b0, int64_t b1, int mode, int tile, int bpc,
+                                   const LaunchTarget &T, int64_t *launches = nullptr) {
   for (int64_t b = b0; b < b1; b++) {
     const int64_t lb = plan.batch_begin[b], le = plan.batch_begin[b + 1];
     if (le == lb) continue;
     if (mode == 0) {
       for (int64_t q = lb; q < le; q++) {
         const int64_t t0 = plan.tile0[q], nt = tiles_of(g->ops[plan.list[q]].width, tile);
-        SPDZ_RET(launch_level(g, d_ops, d_list + q, 1, t0, t0 + nt, tile, bpc, T));
+        SPDZ_RET(launch_level(g, d_ops, d_list + q, nullptr, 1, t0, t0 + nt, tile, bpc, T));
         if (launches) *launches += 1;
       }
     } else {
-      SPDZ_RET(launch_level(g, d_ops, d_list + lb, (int32_t)(le - lb), 0, plan.batch_tiles[b], tile, bpc, T));
+      SPDZ_RET(launch_level(g, d_ops, d_list + lb, d_item + plan.batch_item0[b], (int32_t)(le - lb), 0,
+                            plan.batch_tiles[b], tile, bpc, T));
       if (launches) *launches += 1;
     }
   }
@@ -664,9 +673,10 @@ static spdz_status enqueue_batches(spdz_dag *g, const GpuPlan &plan, const DagOp
 
 // every batch of level l
 static spdz_status enqueue_level(spdz_dag *g, const GpuPlan &plan, const DagOpDev *d_ops, const int32_t *d_list,
-                                 size_t l, int mode, int tile, int bpc, const LaunchTarget &T, int64_t *launches = nullptr) {
-  return enqueue_batches(g, plan, d_ops, d_list, plan.level_batch[l], plan.level_batch[l + 1], mode, tile, bpc, T,
-                         launches);
+                                 const int32_t *d_item, size_t l, int mode, int tile, int bpc, const LaunchTarget &T,
+                                 int64_t *launches = nullptr) {
+  return enqueue_batches(g, plan, d_ops, d_list, d_item, plan.level_batch[l], plan.level_batch[l + 1], mode, tile,
+                         bpc, T, launches);
 }
 
 // --------------------------------------------------------------------------
@@ -1098,7 +1108,7 @@ static spdz_status run_graph(spdz_dag *g) {
     std::vector<uint8_t> all(g->n_ops, 1);
     std::vector<int64_t> flush_at(g->levels.size(), g->flush_elems);
     make_plan(g, all, g->tile, plan, nullptr, &flush_at);
-    SPDZ_RET(upload_plan(g, plan, g->d_ops_graph, g->d_list_graph, g->stream));
+    SPDZ_RET(upload_plan(g, plan, g->d_ops_graph, g->d_list_graph, g->d_item_graph, g->item_cap_graph, g->stream));
     g->graph_launches = (int64_t)plan.batch_tiles.size();
     g->graph_early = plan.early_flushes;
     g->graph_slots = 0;
@@ -1106,7 +1116,7 @@ static spdz_status run_graph(spdz_dag *g) {
     SPDZ_RET(hip_status(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal)));
     spdz_status st = SPDZ_OK;
     for (size_t l = 0; l < g->levels.size() && st == SPDZ_OK; l++)
-      st = enqueue_level(g, plan, g->d_ops_graph, g->d_list_graph, l, 1, g->tile, g->blocks_per_cu, T);
+      st = enqueue_level(g, plan, g->d_ops_graph, g->d_list_graph, g->d_item_graph, l, 1, g->tile, g->blocks_per_cu, T);
     hipGraph_t gr = nullptr;
     const hipError_t ec = hipStreamEndCapture(g->stream, &gr);
     if (st != SPDZ_OK) return st;
@@ -1190,7 +1200,7 @@ spdz_status spdz_dag_run(spdz_dag *g, int mode, int policy, double *wall_ms) {
       SPDZ_RET(ensure_host_mirrors(g));
       SPDZ_RET(stage_triples(g, on_gpu));
     }
-    SPDZ_RET(upload_plan(g, plan, g->d_ops, g->d_list, g->stream));
+    SPDZ_RET(upload_plan(g, plan, g->d_ops, g->d_list, g->d_item, g->item_cap, g->stream));
     SPDZ_RET(set_params(g));
     int64_t dmax = 0, hmax = 0;
     for (size_t st = 0; st <= nl; st++) {
@@ -1234,10 +1244,10 @@ spdz_status spdz_dag_run(spdz_dag *g, int mode, int policy, double *wall_ms) {
       const int64_t b0 = plan.level_batch[l], b1 = plan.level_batch[l + 1], ub = plan.urgent_batch[l];
       const bool d2h = xp.d2h_e[st] > xp.d2h_b[st];
       const int64_t bsplit = d2h ? (ub >= 0 ? ub + 1 : b1) : b1;
-      SPDZ_RET(enqueue_batches(g, plan, g->d_ops, g->d_list, b0, bsplit, gmode, g->tile, g->blocks_per_cu, T,
+      SPDZ_RET(enqueue_batches(g, plan, g->d_ops, g->d_list, g->d_item, b0, bsplit, gmode, g->tile, g->blocks_per_cu, T,
                                &g->last_launches));
       if (d2h) SPDZ_RET(launch_xfer(g, dsegs + xp.d2h_b[st], xp.d2h_e[st] - xp.d2h_b[st], (int)(st & 1), true));
-      SPDZ_RET(enqueue_batches(g, plan, g->d_ops, g->d_list, bsplit, b1, gmode, g->tile, g->blocks_per_cu, T,
+      SPDZ_RET(enqueue_batches(g, plan, g->d_ops, g->d_list, g->d_item, bsplit, b1, gmode, g->tile, g->blocks_per_cu, T,
                                &g->last_launches));
       // the CPU part of the level runs while the GPU works: it needs what earlier stages sent
       // to the host, the latest of which is stage l (its staging buffer is read now, before
@@ -1337,12 +1347,13 @@ spdz_status spdz_dag_autotune(spdz_dag *g, int max_levels, int *tile_out, int *b
   for (int tile : tiles) {
     GpuPlan plan;
     make_plan(g, all, tile, plan);
-    st = upload_plan(g, plan, g->d_ops, g->d_list, g->stream);
+    st = upload_plan(g, plan, g->d_ops, g->d_list, g->d_item, g->item_cap, g->stream);
     if (st != SPDZ_OK) break;
     for (int bpc : bpcs) {
       for (int rep = 0; rep < 2 && st == SPDZ_OK; rep++) {  // rep 0 warms up
         (void)hipEventRecord(e0, g->stream);
-        for (size_t l = 0; l < nl && st == SPDZ_OK; l++) st = enqueue_level(g, plan, g->d_ops, g->d_list, l, 1, tile, bpc, T);
+        for (size_t l = 0; l < nl && st == SPDZ_OK; l++)
+          st = enqueue_level(g, plan, g->d_ops, g->d_list, g->d_item, l, 1, tile, bpc, T);
         (void)hipEventRecord(e1, g->stream);
         if (hipEventSynchronize(e1) != hipSuccess) st = SPDZ_E_HIP;
         float ms = 0.f;
@@ -1526,7 +1537,7 @@ spdz_status spdz_dag_time_level(spdz_ctx *c, int kind, int64_t width, int64_t q,
   std::vector<uint8_t> all(qq, 1);
   GpuPlan plan;
   make_plan(g, all, g->tile, plan);
-  s = upload_plan(g, plan, g->d_ops, g->d_list, g->stream);
+  s = upload_plan(g, plan, g->d_ops, g->d_list, g->d_item, g->item_cap, g->stream);
   if (s != SPDZ_OK) return fin(s);
   LaunchTarget T{g->stream, g->tune_acc, nullptr};
   hipEvent_t e0, e1;
@@ -1534,7 +1545,7 @@ spdz_status spdz_dag_time_level(spdz_ctx *c, int kind, int64_t width, int64_t q,
   std::vector<double> gt, ct;
   for (int r = 0; r <= reps && s == SPDZ_OK; r++) {
     (void)hipEventRecord(e0, g->stream);
-    s = enqueue_level(g, plan, g->d_ops, g->d_list, 0, 1, g->tile, g->blocks_per_cu, T);
+    s = enqueue_level(g, plan, g->d_ops, g->d_list, g->d_item, 0, 1, g->tile, g->blocks_per_cu, T);
     (void)hipEventRecord(e1, g->stream);
     float ms = 0.f;
     if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) s = SPDZ_E_HIP;
