@@ -267,10 +267,7 @@ __global__ __launch_bounds__(256, 1) void k_gemm_mfma(const GemmArgs A) {
     a0[0] = *reinterpret_cast<const v4i *>(sl + aoff);
     a0[1] = *reinterpret_cast<const v4i *>(sl + SCH * RUN + aoff);
     // first half: each group of 8 MFMAs reads a first-half operand two groups ahead and two
-    // second-half operands, and after its MFMAs starts two loads of the next stage into the
-    // other buffer (last read in stage st - 1, before every wave passed the previous
-    // barrier); the compiler waits for the group's LDS reads before such a load (it cannot
-    // tell the buffers apart), which by then have landed, so no wait holds up the matrix pipe
+    // second-half operands, so the second half reads nothing from LDS
 #pragma unroll
     for (int dk = 0; dk < NDIG; dk++) {
       __builtin_amdgcn_sched_barrier(0);
@@ -280,17 +277,26 @@ __global__ __launch_bounds__(256, 1) void k_gemm_mfma(const GemmArgs A) {
 #pragma unroll
       for (int dl = 0; dl < NDIG; dl++)
         acc[dk + dl] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0[dk], b0[dl], acc[dk + dl], 0, 0, 0);
-      __builtin_amdgcn_sched_barrier(0);
-      to_lds(gl + dk * SCH * RUN, wl + dk * SCH * RUN + woff);
-      to_lds(gr + dk * SCH * RUN, wrr + dk * SCH * RUN + woff);
     }
-    // second half
+    // second half: after each of its first four groups, four loads of the next stage into the
+    // other buffer (last read in stage st - 1, before every wave passed the previous barrier):
+    // the LDS takes them while it serves no operand reads, and the last four groups leave
+    // them time to land before the barrier
 #pragma unroll
     for (int dk = 0; dk < NDIG; dk++) {
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int dl = 0; dl < NDIG; dl++)
         acc[dk + dl] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1[dk], b1[dl], acc[dk + dl], 0, 0, 0);
+      if (dk < NDIG / 2) {
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+          const int d = 2 * dk + h;
+          to_lds(gl + d * SCH * RUN, wl + d * SCH * RUN + woff);
+          to_lds(gr + d * SCH * RUN, wrr + d * SCH * RUN + woff);
+        }
+      }
     }
     __builtin_amdgcn_sched_barrier(0);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the next stage has landed in LDS
