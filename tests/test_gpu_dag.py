@@ -83,6 +83,33 @@ def test_dag_modes_and_policies(n):
         check_nodes(g, ref, range(dag.n_ops + 2))
 
 
+@pytest.mark.parametrize("tile,bpc", [(64, 1), (512, 16), (8192, 2)])
+def test_dag_launch_shapes(tile, bpc):
+    """Every launch shape finds each work item's op: tiles of 64 elements with one block per CU
+    (blocks stride over more work items than the grid holds), of 512 with 16 per CU, and of 8192
+    (most ops one item); graph, per-level and hybrid (static, early flushes) runs all equal the
+    oracle node for node."""
+    from paper_2512_11112_amd import spdz as S
+    dag = make_dag(13, P61, n_parties=2, **SMALL)
+    ref, ok, sigma = dag_run(dag, seed=7, check_seed=7)
+    ctx, g = build(dag, 7)
+    g.set_launch(tile, bpc)
+    runs = [(S.MODE_GRAPH, S.POLICY_ALL_GPU, 0), (S.MODE_PER_LEVEL, S.POLICY_ALL_GPU, 0),
+            (S.MODE_PER_LEVEL, S.POLICY_STATIC, 1000)]
+    g.set_threshold(400)
+    for epoch, (mode, policy, flush) in enumerate(runs):
+        print(f"case tile={tile} bpc={bpc} mode={mode} policy={policy} flush={flush}", flush=True)
+        g.set_flush(flush)
+        g.run(mode, policy)
+        g.fetch_host_outputs()
+        ok_d, sig_d = ctx.spdz_mac_check()
+        sig_e = sigma if epoch == 0 else dag_run(dag, seed=7, check_seed=7, epoch=epoch, keep=set())[2]
+        assert ok_d and sig_d == ints_of_sigma(sig_e), (mode, policy)
+        check_nodes(g, ref, range(dag.n_ops + 2))
+    g.close()
+    ctx.close()
+
+
 def width_model(S):
     """MLP parameters (layout of spdz.h) whose CPU output is log2 width and GPU output 9."""
     W = np.zeros(S.MLP_NPARAM, dtype=np.float32)
