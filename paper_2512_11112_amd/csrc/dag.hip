@@ -203,6 +203,10 @@ __global__ __launch_bounds__(BLOCK) void k_dag_level(const LevelArgs<N> A) {
   for (int k = 0; k <= N; k++) mc[k] = F::zero();
   const u64 cstate = A.params->coef_state;
   const int64_t jb = A.params->j_base;
+  // this block's MAC-check slot (its own: no other block of the launch touches it), requested
+  // now so that the sum at the end does not wait for it
+  u64 *slot = A.acc + (size_t)blockIdx.x * (N + 1);
+  const E prev = threadIdx.x < N + 1 ? F::from_words(slot + threadIdx.x) : F::zero();
   for (int64_t item = A.item0 + blockIdx.x; item < A.total_tiles; item += gridDim.x) {
     // the work item's op (from the launch's item table: two dependent scalar loads reach its
     // descriptor); the op is the same for the whole block, so the descriptor sits in scalar
@@ -234,7 +238,8 @@ __global__ __launch_bounds__(BLOCK) void k_dag_level(const LevelArgs<N> A) {
       }
     }
   }
-  block_add_to_slot<F, N + 1>(mc, A.acc + (size_t)blockIdx.x * (N + 1));
+  const E tot = block_sum<F, N + 1>(mc);
+  if (threadIdx.x < N + 1) F::to_words(F::add(prev, tot), slot + threadIdx.x);
 }
 
 // --------------------------------------------------------------------------
