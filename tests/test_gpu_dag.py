@@ -110,6 +110,28 @@ def test_dag_launch_shapes(tile, bpc):
     ctx.close()
 
 
+@pytest.mark.parametrize("n", [4, 5, 8])
+def test_dag_more_parties(n):
+    """Four, five and eight parties (the level kernel instantiated per party count): graph and
+    per-level runs and a hybrid static run equal the oracle node for node."""
+    from paper_2512_11112_amd import spdz as S
+    dag = make_dag(14 + n, P61, n_parties=n, **dict(SMALL, depth=6, ops_per_level=24))
+    ref, ok, sigma = dag_run(dag, seed=8, check_seed=8)
+    ctx, g = build(dag, 8)
+    g.set_threshold(400)
+    runs = [(S.MODE_GRAPH, S.POLICY_ALL_GPU), (S.MODE_PER_LEVEL, S.POLICY_ALL_GPU), (S.MODE_PER_LEVEL, S.POLICY_STATIC)]
+    for epoch, (mode, policy) in enumerate(runs):
+        print(f"case n={n} mode={mode} policy={policy}", flush=True)
+        g.run(mode, policy)
+        g.fetch_host_outputs()
+        ok_d, sig_d = ctx.spdz_mac_check()
+        sig_e = sigma if epoch == 0 else dag_run(dag, seed=8, check_seed=8, epoch=epoch, keep=set())[2]
+        assert ok_d and sig_d == ints_of_sigma(sig_e), (mode, policy)
+        check_nodes(g, ref, range(dag.n_ops + 2))
+    g.close()
+    ctx.close()
+
+
 def width_model(S):
     """MLP parameters (layout of spdz.h) whose CPU output is log2 width and GPU output 9."""
     W = np.zeros(S.MLP_NPARAM, dtype=np.float32)

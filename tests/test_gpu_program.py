@@ -80,11 +80,11 @@ def test_random_program_matches_oracle(seed):
     """Seeded random programs (public branches merged by phis that may mix a public and a
     secret value, loops of one block whose phis may take each other's values, zero-trip
     header loops, nested regions, opens fed back as public operands, sums broadcast back)
-    at widths 1 .. 4099 over the three fields: fused and node by node, phis handing off
-    their buffers and copying, each equal to the oracle."""
+    at widths 1 .. 4099 over the three fields and 2, 3, 4 or 8 parties: fused and node by node,
+    phis handing off their buffers and copying, each equal to the oracle."""
     from paper_2512_11112_amd.spdz import Program
-    p, n = [(P_PAPER, 2), (P61, 3), (P127, 2), (P_PAPER, 3)][seed % 4]
-    W = [1, 63, 64, 65, 1000, 4099][seed // 4 % 6]
+    p, n = [(P_PAPER, 2), (P61, 3), (P127, 2), (P_PAPER, 3), (P61, 4), (P_PAPER, 8)][seed % 6]
+    W = [1, 63, 64, 65, 1000, 4099][seed // 6 % 6]
     text = P.random_program(seed, W, regions=4 + seed % 5, depth=3 if seed % 3 == 0 else 2)
     ref = run_program(text, p, n, seed, seed + 1)
     for fuse, handoff in ((True, True), (True, False), (False, True), (False, False)):
