@@ -214,14 +214,15 @@ def taint(f: IRFunction, privacy: Dict[int, str]) -> set:
 class Val:
     """A value of the function: a program node, a pointer view into a parameter's vector, a
     compile-time integer, or the broadcast of a public scalar node."""
-    kind: str                      # "node" | "ptr" | "const" | "bcast" | "skip"
-    node: int = 0
+    kind: str                      # "node" | "ptr" | "const" | "bcast" | "ptrsel" | "skip"
+    node: int = 0                  # (ptrsel: the public condition node)
     width: int = 1
     secret: bool = False
     base: int = 0                  # ptr: the parameter's input node
     start_node: Optional[int] = None   # ptr: public scalar node of the dynamic part of the index
     start_const: int = 0           # ptr: constant part of the index (elements)
     const: int = 0
+    alts: Tuple = ()               # ptrsel: the pointers chosen when the condition is nonzero / zero
 
 
 @dataclass
@@ -315,8 +316,13 @@ class _Lower:
             return self.vals[tok]
         if tok in ("true", "false"):
             return Val("const", const=int(tok == "true"))
-        if tok == "zeroinitializer":
+        if tok in ("zeroinitializer", "poison", "undef"):   # an undefined lane may take any value
             return Val("const", const=0)
+        m = re.match(r"<(.*)>$", tok)
+        if m:   # a constant vector: one value in every defined lane
+            vals = {e.split()[-1] for e in _split_top(m.group(1))} - {"poison", "undef"}
+            if len(vals) <= 1 and all(re.match(r"-?\d+$", v) for v in vals):
+                return Val("const", const=int(vals.pop()) if vals else 0)
         m = re.match(r"splat \(i\d+ (-?\d+)\)", tok)
         if m:
             return Val("const", const=int(m.group(1)))
@@ -475,22 +481,57 @@ class _Lower:
                               start_const=b.start_const)
 
     def load(self, lines, name, ty, ptr):
-        v = self.operand(ptr)
-        if v.kind != "ptr":
-            raise FrontendError("load through a pointer that is not a parameter's vector")
-        cnt = _width(ty)
         if not re.match(r"(<\d+ x i32>|i32)$", ty):
             raise FrontendError(f"load of {ty} (32-bit words only)")
+        self.vals[name] = self.load_val(lines, self.operand(ptr), _width(ty))
+
+    def load_val(self, lines, v: Val, cnt: int) -> Val:
+        if v.kind == "ptrsel":   # a load through a pointer chosen by a public condition
+            a, b = (self.load_val(lines, alt, cnt) for alt in v.alts)
+            return self.emit(lines, "select", [v.node, self.node_of(a), self.node_of(b)], cnt,
+                             a.secret or b.secret, "")
+        if v.kind != "ptr":
+            raise FrontendError("load through a pointer that is not a parameter's vector")
         if v.start_node is None and v.start_const == 0 and cnt == v.width:
-            self.vals[name] = Val("node", node=v.base, width=cnt, secret=v.secret)
-            return
+            return Val("node", node=v.base, width=cnt, secret=v.secret)
         if v.start_node is None:
             s = self.const_node(v.start_const)
         elif v.start_const:
             s = self.emit(lines, "add", [v.start_node, self.const_node(v.start_const)], 1, False, "").node
         else:
             s = v.start_node
-        self.emit(lines, "load", [v.base, s], cnt, v.secret, name, extra=f" {cnt}")
+        return self.emit(lines, "load", [v.base, s], cnt, v.secret, "", extra=f" {cnt}")
+
+    def lanes(self, lines, name, v: Val, mask: List[Optional[int]]):
+        """Lanes of a vector value picked by a constant mask (None: an undefined lane): every
+        defined lane the same source lane (a broadcast) or consecutive source lanes (a view)."""
+        out = len(mask)
+        if v.kind in ("const", "bcast"):
+            self.vals[name] = v
+            return
+        if v.kind != "node":
+            raise FrontendError(f"lanes of a {v.kind} value")
+        defined = [(i, m) for i, m in enumerate(mask) if m is not None]
+        if not defined:
+            self.vals[name] = Val("const", const=0)
+            return
+        if len({m for _, m in defined}) == 1:
+            t = self.emit(lines, "load", [v.node, self.const_node(defined[0][1])], 1, v.secret, "", extra=" 1")
+            if out == 1:
+                self.vals[name] = t
+            elif v.secret:
+                self.emit(lines, "bcast", [t.node], out, True, name, extra=f" {out}")
+            else:
+                self.vals[name] = Val("bcast", node=t.node, width=1, secret=False)
+            return
+        starts = {m - i for i, m in defined}
+        if len(starts) != 1 or min(starts) < 0 or min(starts) + out > v.width:
+            raise FrontendError(f"lanes {mask} of a vector of width {v.width}: neither one lane nor a run")
+        s0 = starts.pop()
+        if s0 == 0 and out == v.width:
+            self.vals[name] = v
+        else:
+            self.emit(lines, "load", [v.node, self.const_node(s0)], out, v.secret, name, extra=f" {out}")
 
     def call(self, lines, name, rest):
         m = re.match(r"(?:tail\s+)?call\s+(?:[\w\s]*?)(void|i\d+|ptr|<\d+ x i\d+>)\s+@([\w.$]+)\((.*)\)", rest)
@@ -587,6 +628,9 @@ class _Lower:
                     if cv.secret:
                         raise FrontendError("select on a secret condition is not in the subset")
                     nc = self.public_scalar(lines, cv)
+                    if ty == "ptr":   # resolved at the loads through it
+                        self.vals[name] = Val("ptrsel", node=nc, alts=(tv, fv2))
+                        continue
                     w = max(_width(ty), 1)
                     self.emit(lines, "select", [nc, self.node_of(tv), self.node_of(fv2)], w,
                               tv.secret or fv2.secret, name)
@@ -608,7 +652,12 @@ class _Lower:
                     mm = re.match(r"phi\s+(<\d+ x i\d+>|i\d+)\s+(.+)$", rest)
                     if not mm:
                         raise FrontendError(f"phi of a type other than 32/64-bit words: {s!r}")
-                    pairs = re.findall(r"\[\s*([^,\]]+?)\s*,\s*%([\w.$]+)\s*\]", mm.group(2))
+                    pairs = []   # [ value, %label ] items; a value may be a constant vector with commas
+                    for item in _split_top(mm.group(2)):
+                        im = re.match(r"\[\s*(.+?)\s*,\s*%([\w.$]+)\s*\]$", item)
+                        if not im:
+                            raise FrontendError(f"cannot read the phi {s!r}")
+                        pairs.append((im.group(1), im.group(2)))
                     nid = self.new_id()
                     lines.append(None)                      # filled once every value is defined
                     pending_phis.append((lines, len(lines) - 1, nid, mm.group(1), pairs))
@@ -620,6 +669,27 @@ class _Lower:
                         raise FrontendError(f"insertelement other than a broadcast: {s!r}")
                     insert[name] = self.operand(mm.group(2))
                     self.vals[name] = Val("skip")
+                elif op == "extractelement":
+                    mm = re.match(r"extractelement\s+<\d+ x i\d+>\s+(\S+),\s*i\d+\s+(\d+)$", rest)
+                    if not mm:
+                        raise FrontendError(f"extractelement at a variable lane: {s!r}")
+                    self.lanes(lines, name, self.operand(mm.group(1)), [int(mm.group(2))])
+                elif op == "shufflevector" and not (
+                        re.match(r"shufflevector\s+<\d+ x i\d+>\s+(%[\w.$]+),\s*<\d+ x i\d+>\s+(?:poison|undef),\s*"
+                                 r"<\d+ x i\d+>\s+zeroinitializer$", rest)
+                        and re.match(r"shufflevector\s+<\d+ x i\d+>\s+(%[\w.$]+)", rest).group(1) in insert):
+                    # one source vector, a constant mask
+                    mm = re.match(r"shufflevector\s+<(\d+) x i\d+>\s+(%[\w.$]+),\s*<\d+ x i\d+>\s+(?:poison|undef),\s*"
+                                  r"<(\d+) x i\d+>\s+(zeroinitializer|<.*>)$", rest)
+                    if not mm:
+                        raise FrontendError(f"shufflevector of two vectors: {s!r}")
+                    out = int(mm.group(3))
+                    if mm.group(4) == "zeroinitializer":
+                        mask = [0] * out
+                    else:
+                        mask = [None if e.split()[-1] in ("poison", "undef") else int(e.split()[-1])
+                                for e in _split_top(mm.group(4)[1:-1])]
+                    self.lanes(lines, name, self.operand(mm.group(2)), mask)
                 elif op == "shufflevector":
                     mm = re.match(r"shufflevector\s+<\d+ x i\d+>\s+(%[\w.$]+),\s*<\d+ x i\d+>\s+(?:poison|undef),\s*"
                                   r"<(\d+) x i\d+>\s+zeroinitializer$", rest)

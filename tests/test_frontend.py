@@ -278,3 +278,48 @@ define dso_local i32 @g(ptr noundef %0, i64 noundef %1) local_unnamed_addr #0 {
             starts.append(consts[int(m.group(1))] + consts[int(m.group(2))])
     assert sorted(starts) == [256, 384]
     assert re.search(r"= reduce ", text) and revealed is not None
+
+
+RANDOM_C_SEEDS = range(60)
+
+
+@pytest.fixture(scope="module")
+def random_c_outcomes():
+    """Each seeded random C function (tests/frontend/random_c.py) translated and run by the
+    oracle's interpreter next to its cleartext build: 'ok', or the front end's refusal."""
+    import sys
+    sys.path.insert(0, HERE)
+    from random_c import random_c
+    out = {}
+    d = tempfile.mkdtemp()
+    for seed in RANDOM_C_SEEDS:
+        src = random_c(seed)
+        try:
+            t = FE.translate(src, "fz", sizes={0: 64, 1: 64}, vector_width=[None, 4, 8][seed % 3])
+        except FE.FrontendError as e:
+            out[seed] = f"refused: {e}"
+            continue
+        res = run_program(t.text, P_PAPER, 2, seed, seed)
+        vals = input_values(t, {}, seed)
+        path = os.path.join(d, f"fz{seed}.c")
+        with open(path, "w") as fh:
+            fh.write(src)
+        fn = cleartext_function(path, "fz")
+        fn.restype = ctypes.c_uint64
+        fn.argtypes = [ctypes.POINTER(ctypes.c_uint64)] * 2 + [ctypes.c_uint64, ctypes.c_uint32]
+        tv = vals[3][0] if 3 in vals else 0
+        want = fn(u64_array(vals[0]), u64_array(vals[1]), vals[2][0], tv % (1 << 32))
+        out[seed] = "ok" if res["ok"] and opened(t, res) == [want] else f"wrong: {opened(t, res)} != {want}"
+    return out
+
+
+def test_random_c_functions(random_c_outcomes):
+    """Random straight-line code, vectorized dot-product loops, Horner loops, public branches,
+    selects of values and of pointers, and loops bounded by a mask of a public parameter: every
+    function the front end accepts computes the cleartext result; the rest are refused by name
+    (no translation runs and gives a wrong value)."""
+    wrong = {s: o for s, o in random_c_outcomes.items() if o.startswith("wrong")}
+    assert not wrong, wrong
+    ok = sum(o == "ok" for o in random_c_outcomes.values())
+    print(f"{ok} of {len(random_c_outcomes)} accepted", flush=True)
+    assert ok >= len(random_c_outcomes) // 3
