@@ -62,11 +62,14 @@ def parse(text: str, p: int) -> Program:
         if t[0] == "input":
             nid, kind, w, aid = int(t[1]), t[2], int(t[3]), int(t[4])
             nodes[nid] = Node(nid, "input", [], w, kind == "private", -1, [aid])
-        elif t[0] == "const":
-            nid, w, v = int(t[1]), int(t[2]), int(t[3])
-            if not 0 <= v < p:
-                raise ProgramError(f"constant {v} not below p")
-            nodes[nid] = Node(nid, "const", [], w, False, -1, [v])
+        elif t[0] == "const":   # one value for every lane, or one value per lane
+            nid, w, vals = int(t[1]), int(t[2]), [int(x) for x in t[3:]]
+            if len(vals) != 1 and len(vals) != w:
+                raise ProgramError(f"bad line: {raw}")
+            for v in vals:
+                if not 0 <= v < p:
+                    raise ProgramError(f"constant {v} not below p")
+            nodes[nid] = Node(nid, "const", [], w, False, -1, vals)
         elif t[0] == "output":
             outputs.append(int(t[1]))
         elif t[0] == "block":
@@ -346,7 +349,7 @@ class Exec:
                 else:
                     self.val[nid] = f.deal_values(self.seed, nd.imm[0], nd.width)
             elif nd.op == "const":
-                self.val[nid] = F.to_limbs([nd.imm[0]] * nd.width, f.L)
+                self.val[nid] = F.to_limbs(nd.imm * nd.width if len(nd.imm) == 1 else list(nd.imm), f.L)
         blk, pred = prog.entry, None
         while True:
             self.entries += 1

@@ -64,6 +64,7 @@ struct PNode {
   std::vector<int> args;                 // operand node ids
   std::vector<std::pair<int, int>> phi;  // (value, predecessor block)
   std::vector<int64_t> imm;              // input array id / constant / load count / layer din, dout, tile rows
+  std::vector<int64_t> lanes;            // a constant with one value per lane (empty: imm[0] in every lane)
   int64_t width = 1;
   bool secret = false, is_private = false;
   int block = -1;
@@ -221,9 +222,14 @@ spdz_status parse(spdz_prog *g, const char *text) {
       g->nodes[n.id] = n;
       g->decl.push_back(n.id);
     } else if (t[0] == "const") {
-      if (t.size() != 4 || !ints(1) || v[1] < 1 || v[2] < 0 || !below_p(g->c, (u64)v[2])) return fail(g, where + "bad constant");
+      // const <id> <width> <value>, or one value per lane
+      if (t.size() < 4 || !ints(1) || v[1] < 1 || (t.size() != 4 && (int64_t)t.size() - 3 != v[1]))
+        return fail(g, where + "bad constant");
+      for (size_t k = 2; k < v.size(); k++)
+        if (v[k] < 0 || !below_p(g->c, (u64)v[k])) return fail(g, where + "bad constant");
       PNode n;
       n.id = (int)v[0], n.op = OP_CONST, n.width = v[1], n.imm = {v[2]};
+      if (t.size() > 4) n.lanes.assign(v.begin() + 2, v.end());
       g->nodes[n.id] = n;
       g->decl.push_back(n.id);
     } else if (t[0] == "output") {
@@ -1400,6 +1406,8 @@ spdz_status deal_inputs(spdz_prog *g) {
           u64 w[2] = {0, 0};
           if (n.op == OP_INPUT) {
             F::to_words(uniform_elem<F>(st, (u64)e), w);
+          } else if (!n.lanes.empty()) {
+            w[0] = (u64)n.lanes[e];
           } else {
             w[0] = (u64)n.imm[0];
             w[1] = n.imm.size() > 1 ? (u64)n.imm[1] : 0;

@@ -214,7 +214,7 @@ def taint(f: IRFunction, privacy: Dict[int, str]) -> set:
 class Val:
     """A value of the function: a program node, a pointer view into a parameter's vector, a
     compile-time integer, or the broadcast of a public scalar node."""
-    kind: str                      # "node" | "ptr" | "const" | "bcast" | "ptrsel" | "skip"
+    kind: str                      # "node" | "ptr" | "const" | "cvec" | "bcast" | "ptrsel" | "skip"
     node: int = 0                  # (ptrsel: the public condition node)
     width: int = 1
     secret: bool = False
@@ -222,7 +222,8 @@ class Val:
     start_node: Optional[int] = None   # ptr: public scalar node of the dynamic part of the index
     start_const: int = 0           # ptr: constant part of the index (elements)
     const: int = 0
-    alts: Tuple = ()               # ptrsel: the pointers chosen when the condition is nonzero / zero
+    alts: Tuple = ()               # ptrsel: the pointers chosen when the condition is nonzero / zero;
+                                   # cvec: the lanes' integers
 
 
 @dataclass
@@ -306,7 +307,18 @@ class _Lower:
             return self.const_node(v.const)
         if v.kind == "bcast":
             return v.node
+        if v.kind == "cvec":
+            return self.const_vec_node(v.alts)
         raise FrontendError(f"a {v.kind} value used as an operand")
+
+    def const_vec_node(self, lanes) -> int:
+        vals = tuple(self.field_const(c) for c in lanes)
+        key = ("lanes", vals)
+        if key not in self.consts:
+            nid = self.new_id()
+            self.decl.append(f"const {nid} {len(vals)} {' '.join(str(v) for v in vals)}")
+            self.consts[key] = nid
+        return self.consts[key]
 
     def operand(self, tok: str, ty: str = "") -> Val:
         tok = tok.strip()
@@ -320,9 +332,13 @@ class _Lower:
             return Val("const", const=0)
         m = re.match(r"<(.*)>$", tok)
         if m:   # a constant vector: one value in every defined lane
-            vals = {e.split()[-1] for e in _split_top(m.group(1))} - {"poison", "undef"}
-            if len(vals) <= 1 and all(re.match(r"-?\d+$", v) for v in vals):
-                return Val("const", const=int(vals.pop()) if vals else 0)
+            lanes = [e.split()[-1] for e in _split_top(m.group(1))]
+            lanes = [0 if e in ("poison", "undef") else e for e in lanes]
+            if all(isinstance(e, int) or re.match(r"-?\d+$", e) for e in lanes):
+                ints = [int(e) for e in lanes]
+                if len(set(ints)) == 1:
+                    return Val("const", const=ints[0])
+                return Val("cvec", width=len(ints), alts=tuple(ints))
         m = re.match(r"splat \(i\d+ (-?\d+)\)", tok)
         if m:
             return Val("const", const=int(m.group(1)))
@@ -502,6 +518,32 @@ class _Lower:
             s = v.start_node
         return self.emit(lines, "load", [v.base, s], cnt, v.secret, "", extra=f" {cnt}")
 
+    def insert_lane(self, lines, name, width: int, base: Val, x: Val, k: int):
+        """A constant vector with lane k replaced by x: (base with lane k zero) + x * e_k."""
+        if base.kind == "const":
+            lanes = [base.const] * width
+        elif base.kind == "cvec":
+            lanes = list(base.alts)
+        else:
+            raise FrontendError(f"an insertelement into a {base.kind} value")
+        if x.kind == "const":
+            lanes[k] = x.const
+            self.vals[name] = Val("cvec", width=width, alts=tuple(lanes))
+            return
+        lanes[k] = 0
+        if x.kind != "node" or x.width != 1:
+            raise FrontendError("an insertelement of a value that is not a scalar")
+        onehot = self.const_vec_node([int(j == k) for j in range(width)])
+        if x.secret:
+            xb = self.emit(lines, "bcast", [x.node], width, True, "", extra=f" {width}").node
+        else:
+            xb = x.node   # a public scalar multiplies every lane
+        t = self.emit(lines, "mul", [xb, onehot], width, x.secret, "")
+        if any(lanes):
+            self.emit(lines, "add", [t.node, self.const_vec_node(lanes)], width, x.secret, name)
+        else:
+            self.vals[name] = t
+
     def lanes(self, lines, name, v: Val, mask: List[Optional[int]]):
         """Lanes of a vector value picked by a constant mask (None: an undefined lane): every
         defined lane the same source lane (a broadcast) or consecutive source lanes (a view)."""
@@ -665,10 +707,15 @@ class _Lower:
                                           secret=name in self.secret_names)
                 elif op == "insertelement":
                     mm = re.match(r"insertelement\s+<\d+ x i\d+>\s+(?:poison|undef),\s*(i\d+)\s+(\S+),\s*i\d+\s+0$", rest)
+                    if mm:   # the first half of a broadcast (the shufflevector that follows)
+                        insert[name] = self.operand(mm.group(2))
+                        self.vals[name] = Val("skip")
+                        continue
+                    mm = re.match(r"insertelement\s+<(\d+) x i\d+>\s+(.+),\s*i\d+\s+(\S+),\s*i\d+\s+(\d+)$", rest)
                     if not mm:
-                        raise FrontendError(f"insertelement other than a broadcast: {s!r}")
-                    insert[name] = self.operand(mm.group(2))
-                    self.vals[name] = Val("skip")
+                        raise FrontendError(f"insertelement at a variable lane: {s!r}")
+                    self.insert_lane(lines, name, int(mm.group(1)), self.operand(mm.group(2)),
+                                     self.operand(mm.group(3)), int(mm.group(4)))
                 elif op == "extractelement":
                     mm = re.match(r"extractelement\s+<\d+ x i\d+>\s+(\S+),\s*i\d+\s+(\d+)$", rest)
                     if not mm:

@@ -6,9 +6,10 @@
 x and y point to `n` elements.  The body mixes straight-line +, -, * on private values and odd
 literals, dot-product loops the vectorizer turns into vector reductions, Horner-style loops it
 cannot vectorize, if/else and ?: on public comparisons of t, and loops whose trip count is a
-low-bit mask of t.  No shifts and only odd constants: the C function and its translation agree
-in F_p only while clang's bit-level reasoning about 32-bit integers (known trailing zeros of a
-product, folded shift chains) has nothing to act on.
+low-bit mask of t.  No shifts, only odd constants and no value added to itself or appearing twice in the returned
+sum: the C function and its translation agree in F_p only while clang's bit-level reasoning
+about 32-bit integers has nothing to act on (known trailing zeros of a product; or, where a value
+is only ever used doubled, constants feeding it rewritten modulo 2^31).
 """
 import random
 
@@ -31,7 +32,10 @@ def random_c(seed: int, n: int = 64, statements: int = 8) -> str:
 
     def binexpr():
         a, b = leaf(), leaf(allow_const=False)
-        return f"{a} {rng.choice(['+', '-', '*'])} {b}"
+        op = rng.choice(['+', '-', '*'])
+        if a == b and op == "+":   # a + a doubles a
+            op = "*"
+        return f"{a} {op} {b}"
 
     def new_name():
         v = f"v{len(names)}"
@@ -44,8 +48,11 @@ def random_c(seed: int, n: int = 64, statements: int = 8) -> str:
             e = binexpr()
             body.append(f"word_t {new_name()} = {e};")
         elif r < 0.40:
-            v = rng.choice(names)
-            body.append(f"{v} = {v} {rng.choice(['+', '-', '*'])} {leaf()};")
+            v, w = rng.choice(names), leaf()
+            op = rng.choice(['+', '-', '*'])
+            if w == v and op == "+":
+                op = "*"
+            body.append(f"{v} = {v} {op} {w};")
         elif r < 0.55:
             init = leaf()
             v = new_name()
@@ -72,8 +79,12 @@ def random_c(seed: int, n: int = 64, statements: int = 8) -> str:
             mask = rng.choice([7, 15, 31])
             body.append(f"word_t {v} = {init};")
             body.append(f"for (uint32_t i = 0; i < (t & {mask}u); i++) {v} += x[i] * y[i];")
-    k = min(3, len(names))
-    ret = " + ".join(f"{a} * {b}" for a, b in zip(names[-k:], reversed(names[-k:])))
+    if len(names) >= 3:
+        ret = f"{names[-1]} * {names[-2]} + {names[-3]}"
+    elif len(names) == 2:
+        ret = f"{names[-1]} * {names[-2]}"
+    else:
+        ret = names[-1]
     src = ["word_t fz(const word_t *x SPDZ_PRIVATE, const word_t *y SPDZ_PRIVATE, word_t s SPDZ_PRIVATE,",
            "          uint32_t t SPDZ_PUBLIC) {"]
     src += ["    " + b for b in body]

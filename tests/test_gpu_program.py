@@ -34,7 +34,7 @@ PROGRAMS = [("pipeline", P.pipeline(3001)), ("branch", P.branch(777)), ("loop", 
             ("loop_program", P.loop_program(2048, 4)), ("one_block_loop", P.one_block_loop(1000, 5)),
             ("phi_swap", P.phi_swap(777, 4)), ("public_div_mod", P.public_div_mod(1001)),
             ("public_phi_swap", P.public_phi_swap(999, 6)), ("broadcast", P.broadcast(3001)),
-            ("loop_reads_source", P.loop_reads_source(1000, 4))]
+            ("loop_reads_source", P.loop_reads_source(1000, 4)), ("lane_constants", P.lane_constants(333))]
 
 
 @pytest.mark.parametrize("handoff", [True, False])
@@ -336,3 +336,32 @@ def test_frontend_program_matches_oracle(fe_programs, name, fuse):
     assert sigma == ints_of_sigma(ref["sigma"])
     prog.close()
     ctx.close()
+
+
+def test_random_c_functions_on_the_runtime():
+    """The seeded random C functions the front end accepts (tests/frontend/random_c.py; lane
+    picks, constant vectors with a lane inserted, selects of pointers, vector reductions) run by
+    the device runtime, fused and node by node, equal to the oracle's run."""
+    import os
+    import sys
+    from paper_2512_11112_amd import frontend as FE
+    from paper_2512_11112_amd.spdz import Program
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "frontend"))
+    from random_c import random_c
+    ran = 0
+    for seed in range(40):
+        try:
+            text = FE.translate(random_c(seed), "fz", sizes={0: 64, 1: 64}, vector_width=[None, 4, 8][seed % 3]).text
+        except FE.FrontendError:
+            continue
+        ref = run_program(text, P_PAPER, 2, seed, seed + 1)
+        for fuse in (True, False):
+            print(f"case random C seed={seed} fuse={fuse}", flush=True)
+            ctx = ctx_for(P_PAPER, 2, seed, seed + 1)
+            prog = Program(ctx, text, fuse=fuse)
+            ok, sigma, ms = prog.run(seed)
+            check_run(prog, ref, ok, sigma, ms, f"random C {seed}")
+            prog.close()
+            ctx.close()
+        ran += 1
+    assert ran >= 10

@@ -24,7 +24,7 @@ def plain_run(text: str, p: int, seed: int):
         if nd.op == "input":
             val[nid] = [int(v) for v in F.from_limbs(f.deal_values(seed, nd.imm[0], nd.width))]
         elif nd.op == "const":
-            val[nid] = [nd.imm[0]] * nd.width
+            val[nid] = nd.imm * nd.width if len(nd.imm) == 1 else list(nd.imm)
 
     def get(nid, w):
         v = val[nid]
@@ -86,7 +86,8 @@ PROGRAMS = [("pipeline", P.pipeline(37)), ("branch", P.branch(21)), ("loop", P.l
             ("loop_program", P.loop_program(16, 3)), ("one_block_loop", P.one_block_loop(12, 4)),
             ("phi_swap", P.phi_swap(6, 5)), ("public_div_mod", P.public_div_mod(11)),
             ("public_phi_swap", P.public_phi_swap(5, 6)), ("broadcast", P.broadcast(9)),
-            ("loop_reads_source", P.loop_reads_source(7, 3))]
+            ("loop_reads_source", P.loop_reads_source(7, 3)),
+            ("lane_constants", P.lane_constants(9))]
 
 
 def check_reconstructs(text: str, p: int, n: int, seed: int = 5):

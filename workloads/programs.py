@@ -9,6 +9,7 @@ Text format (one statement per line, '#' starts a comment, ids are integers):
         secret input dealt from array <array_id>, or public input whose values are
         element 0..width-1 of that array's value stream
     const <id> <width> <value>          public vector, every entry <value> (0 <= value < p)
+    const <id> <width> <v0> ... <v(w-1)>  public vector, one value per lane
     output <id>                         a result: the value of <id> when the program returns
     block <bid>                         the following lines belong to block <bid>; the first
                                         block of the file is the entry
@@ -725,3 +726,23 @@ def random_program(seed: int, W: int, regions: int = 5, depth: int = 2) -> str:
         lines.append(f"block {b}")
         lines += body[b]
     return "\n".join(lines) + "\n"
+
+
+def lane_constants(W: int) -> str:
+    """Public constants with one value per lane: z = x * c + d, opened, and the sum of c x."""
+    c = " ".join(str((7 * k + 3) % 100) for k in range(W))
+    d = " ".join(str((k * k) % 97) for k in range(W))
+    return f"""
+input 1 private {W} 0
+const 2 {W} {c}
+const 3 {W} {d}
+output 6
+output 8
+block 0
+4 = mul 1 2
+5 = add 4 3
+6 = open 5
+7 = reduce 4
+8 = open 7
+ret
+"""
