@@ -367,6 +367,16 @@ class _Lower:
             self.vals[name] = v
         return v
 
+    @staticmethod
+    def lane_count(v: Val) -> int:
+        return v.width if v.kind in ("node", "cvec") else 1
+
+    def public_operand(self, lines: List[str], v: Val) -> int:
+        """A public value's node: a scalar, or a vector whose lanes are compared one by one."""
+        if v.kind in ("const", "cvec", "bcast") or (v.kind == "node" and not v.secret):
+            return self.node_of(v)
+        raise FrontendError("an index or a condition must be public")
+
     def public_scalar(self, lines: List[str], v: Val) -> int:
         if v.kind == "const":
             return self.const_node(v.const)
@@ -444,25 +454,27 @@ class _Lower:
             return
         if x.secret or y.secret:
             raise FrontendError("comparison of a secret value (the gate set is arithmetic)")
-        nx, ny = self.public_scalar(lines, x), self.public_scalar(lines, y)
+        # public scalars, or public vectors compared lane by lane (the vectorizer's lane masks)
+        nx, ny = self.public_operand(lines, x), self.public_operand(lines, y)
+        w = max(self.lane_count(x), self.lane_count(y))
         one = None
         if pred in ("ne", "ule", "sle", "uge", "sge"):
             one = self.const_node(1)
         if pred == "eq":
-            self.emit(lines, "eq", [nx, ny], 1, False, name)
+            self.emit(lines, "eq", [nx, ny], w, False, name)
         elif pred == "ne":
-            e = self.emit(lines, "eq", [nx, ny], 1, False, "")
-            self.emit(lines, "sub", [one, e.node], 1, False, name)
+            e = self.emit(lines, "eq", [nx, ny], w, False, "")
+            self.emit(lines, "sub", [one, e.node], w, False, name)
         elif pred in ("ult", "slt"):
-            self.emit(lines, "lt", [nx, ny], 1, False, name)
+            self.emit(lines, "lt", [nx, ny], w, False, name)
         elif pred in ("ugt", "sgt"):
-            self.emit(lines, "lt", [ny, nx], 1, False, name)
+            self.emit(lines, "lt", [ny, nx], w, False, name)
         elif pred in ("ule", "sle"):          # a <= b  <=>  not (b < a)
-            t = self.emit(lines, "lt", [ny, nx], 1, False, "")
-            self.emit(lines, "sub", [one, t.node], 1, False, name)
+            t = self.emit(lines, "lt", [ny, nx], w, False, "")
+            self.emit(lines, "sub", [one, t.node], w, False, name)
         elif pred in ("uge", "sge"):          # a >= b  <=>  not (a < b)
-            t = self.emit(lines, "lt", [nx, ny], 1, False, "")
-            self.emit(lines, "sub", [one, t.node], 1, False, name)
+            t = self.emit(lines, "lt", [nx, ny], w, False, "")
+            self.emit(lines, "sub", [one, t.node], w, False, name)
         else:
             raise FrontendError(f"icmp {pred}")
 
@@ -519,7 +531,20 @@ class _Lower:
         return self.emit(lines, "load", [v.base, s], cnt, v.secret, "", extra=f" {cnt}")
 
     def insert_lane(self, lines, name, width: int, base: Val, x: Val, k: int):
-        """A constant vector with lane k replaced by x: (base with lane k zero) + x * e_k."""
+        """A vector with lane k replaced by x: (base with lane k zero) + x * e_k; a constant base
+        has its lane k zeroed at translation time, another one is multiplied by 1 - e_k."""
+        if base.kind in ("node", "bcast"):
+            if x.kind == "const":
+                x = Val("node", node=self.const_node(x.const), width=1, secret=False)
+            if x.kind != "node" or x.width != 1:
+                raise FrontendError("an insertelement of a value that is not a scalar")
+            keep = self.const_vec_node([int(j != k) for j in range(width)])
+            onehot = self.const_vec_node([int(j == k) for j in range(width)])
+            kept = self.emit(lines, "mul", [self.node_of(base), keep], width, base.secret, "")
+            xb = self.emit(lines, "bcast", [x.node], width, True, "", extra=f" {width}").node if x.secret else x.node
+            t = self.emit(lines, "mul", [xb, onehot], width, x.secret, "")
+            self.emit(lines, "add", [kept.node, t.node], width, base.secret or x.secret, name)
+            return
         if base.kind == "const":
             lanes = [base.const] * width
         elif base.kind == "cvec":
@@ -669,7 +694,7 @@ class _Lower:
                         continue
                     if cv.secret:
                         raise FrontendError("select on a secret condition is not in the subset")
-                    nc = self.public_scalar(lines, cv)
+                    nc = self.public_scalar(lines, cv) if ty == "ptr" else self.public_operand(lines, cv)
                     if ty == "ptr":   # resolved at the loads through it
                         self.vals[name] = Val("ptrsel", node=nc, alts=(tv, fv2))
                         continue
@@ -707,9 +732,18 @@ class _Lower:
                                           secret=name in self.secret_names)
                 elif op == "insertelement":
                     mm = re.match(r"insertelement\s+<\d+ x i\d+>\s+(?:poison|undef),\s*(i\d+)\s+(\S+),\s*i\d+\s+0$", rest)
-                    if mm:   # the first half of a broadcast (the shufflevector that follows)
-                        insert[name] = self.operand(mm.group(2))
-                        self.vals[name] = Val("skip")
+                    if mm:   # the first half of a broadcast (the shufflevector that follows); the other
+                        # lanes are undefined, so where the vector itself is used every lane may hold x
+                        x = insert[name] = self.operand(mm.group(2))
+                        w0 = int(re.match(r"insertelement\s+<(\d+)", rest).group(1))
+                        if x.kind == "const":
+                            self.vals[name] = x
+                        elif x.kind == "node" and not x.secret and x.width == 1:
+                            self.vals[name] = Val("bcast", node=x.node, width=1, secret=False)
+                        elif x.kind == "node" and x.width == 1:   # the broadcast's shuffle reuses it
+                            self.emit(lines, "bcast", [x.node], w0, True, name, extra=f" {w0}")
+                        else:
+                            raise FrontendError(f"insertelement of a {x.kind} value: {s!r}")
                         continue
                     mm = re.match(r"insertelement\s+<(\d+) x i\d+>\s+(.+),\s*i\d+\s+(\S+),\s*i\d+\s+(\d+)$", rest)
                     if not mm:
@@ -743,8 +777,11 @@ class _Lower:
                     if not mm or mm.group(1) not in insert:
                         raise FrontendError(f"shufflevector other than a broadcast: {s!r}")
                     sv = insert[mm.group(1)]
+                    made = self.vals.get(mm.group(1))
                     if sv.kind == "const":
                         self.vals[name] = sv
+                    elif made is not None and made.kind == "node" and made.width == int(mm.group(2)):
+                        self.vals[name] = made
                     elif sv.secret:   # a secret scalar repeated across the vector's lanes
                         self.emit(lines, "bcast", [self.node_of(sv)], int(mm.group(2)), True, name,
                                   extra=f" {int(mm.group(2))}")
