@@ -576,6 +576,13 @@ class _Lower:
         if v.kind in ("const", "bcast"):
             self.vals[name] = v
             return
+        if v.kind == "cvec":   # lanes of a constant vector, picked at translation time
+            if any(m is not None and m >= v.width for m in mask):
+                raise FrontendError(f"lanes {mask} of a constant vector of width {v.width}")
+            vals = [v.alts[m] if m is not None else 0 for m in mask]
+            self.vals[name] = (Val("const", const=vals[0]) if len(set(vals)) == 1
+                               else Val("cvec", width=out, alts=tuple(vals)))
+            return
         if v.kind != "node":
             raise FrontendError(f"lanes of a {v.kind} value")
         defined = [(i, m) for i, m in enumerate(mask) if m is not None]
