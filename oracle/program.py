@@ -125,7 +125,7 @@ def lower(nodes, blk: Block, nid: int, op: str, a: List[int], p: int):
         if len(a) != 2 or a[1] < 1:
             raise ProgramError(f"{op} a k with a literal k >= 1")
         add(Node(nid, op, a[:1], imm=[a[1]]))
-    elif op in ("add", "sub", "mul", "lt", "eq"):
+    elif op in ("add", "sub", "mul", "lt", "eq", "cat"):
         add(Node(nid, op, a[:2]))
     elif op in ("reduce", "open"):
         add(Node(nid, op, a[:1]))
@@ -154,6 +154,9 @@ def infer(prog: Program):
                 n.secret = False
             elif n.op in ("div", "mod"):
                 n.width, n.secret = nodes[n.args[0]].width, False
+            elif n.op == "cat":
+                x, y = nodes[n.args[0]], nodes[n.args[1]]
+                n.width, n.secret = x.width + y.width, x.secret or y.secret
             elif n.op == "bcast":
                 n.width, n.secret = n.imm[0], nodes[n.args[0]].secret
             elif n.op == "reduce":
@@ -283,6 +286,14 @@ class Exec:
             xb = F.from_limbs(self.pub(nd.args[1], w))
             r = [int(u < v) if nd.op == "lt" else int(u == v) for u, v in zip(xa, xb)]
             self.val[nd.id] = F.to_limbs(r, f.L)
+        elif nd.op == "cat":   # the lanes of the first value, then those of the second
+            parts = [self.val[i] for i in nd.args]
+            if nd.secret:
+                parts = [v if isinstance(v, F.Shares) else self.share_pub(v) for v in parts]
+                self.val[nd.id] = F.Shares(np.concatenate([v.val for v in parts], axis=2),
+                                           np.concatenate([v.mac for v in parts], axis=2))
+            else:
+                self.val[nd.id] = np.concatenate(parts, axis=1)
         elif nd.op == "bcast":
             v, w = self.val[nd.args[0]], nd.imm[0]
             if nd.secret:

@@ -51,7 +51,7 @@ constexpr u64 NODE_STRIDE = 1 << 16;
 constexpr u64 PROG_TRIPLE0 = 1ull << 20;
 constexpr int64_t MAX_ENTRIES = 1000000;
 
-enum Op { OP_INPUT, OP_CONST, OP_ADD, OP_SUB, OP_MUL, OP_LT, OP_EQ, OP_REDUCE, OP_OPEN, OP_LOAD, OP_PHI, OP_LAYER, OP_DIV, OP_MOD, OP_BCAST };
+enum Op { OP_INPUT, OP_CONST, OP_ADD, OP_SUB, OP_MUL, OP_LT, OP_EQ, OP_REDUCE, OP_OPEN, OP_LOAD, OP_PHI, OP_LAYER, OP_DIV, OP_MOD, OP_BCAST, OP_CAT };
 
 // a phi that another phi of its block reads keeps its previous value here while the
 // phis of a new entry are copied (phis reading each other in a cycle)
@@ -296,6 +296,10 @@ spdz_status parse(spdz_prog *g, const char *text) {
         n.op = op == "add" ? OP_ADD : op == "sub" ? OP_SUB : op == "mul" ? OP_MUL : op == "lt" ? OP_LT : OP_EQ;
         n.args = {(int)v[0], (int)v[1]};
         add_line(n);
+      } else if (op == "cat") {
+        if (!need(2)) return fail(g, where + "cat a b");
+        n.op = OP_CAT, n.args = {(int)v[0], (int)v[1]};
+        add_line(n);
       } else if (op == "bcast") {
         if (!need(2) || v[1] < 1) return fail(g, where + "bcast a w (w >= 1)");
         n.op = OP_BCAST, n.args = {(int)v[0]}, n.imm = {v[1]};
@@ -370,6 +374,10 @@ spdz_status infer(spdz_prog *g) {
         case OP_DIV:
         case OP_MOD: n.width = N[n.args[0]].width, n.secret = false; break;
         case OP_BCAST: n.width = n.imm[0], n.secret = N[n.args[0]].secret; break;
+        case OP_CAT:
+          n.width = N[n.args[0]].width + N[n.args[1]].width;
+          n.secret = N[n.args[0]].secret || N[n.args[1]].secret;
+          break;
         case OP_REDUCE: n.width = 1, n.secret = N[n.args[0]].secret; break;
         case OP_OPEN: n.width = N[n.args[0]].width, n.secret = false; break;
         case OP_LOAD: n.width = n.imm[0], n.secret = N[n.args[0]].secret; break;
@@ -440,6 +448,9 @@ spdz_status infer(spdz_prog *g) {
         } else if (n.op == OP_PHI) {
           for (auto &pv : n.phi)
             if (!N[pv.first].secret) N[pv.first].dev_use = true;
+        } else if (n.op == OP_CAT) {  // a public part is shared on the device
+          for (int a : n.args)
+            if (!N[a].secret) N[a].dev_use = true;
         } else if (n.op == OP_LAYER && !N[n.args[2]].secret) {
           N[n.args[2]].dev_use = true;  // a public bias is shared on the device
         }
@@ -1229,6 +1240,30 @@ spdz_status issue(spdz_prog *g, PNode &n) {
           for (int64_t e = 0; e < n.width; e++) n.hpub[l * n.width + e] = a.hpub[l];
         if (n.dev_use) st = upload(g, n);
       }
+      break;
+    }
+    case OP_CAT: {  // the lanes of the first value, then those of the second
+      const PNode *parts[2] = {&N[n.args[0]], &N[n.args[1]]};
+      int64_t off = 0;
+      for (const PNode *s : parts) {
+        if (n.secret && s->secret) {  // the 2 n L planes: rows of the part's width into rows of n's
+          st = hip_status(hipMemcpy2DAsync(n.sh.val + off, n.width * 8, s->sh.val, s->width * 8, s->width * 8,
+                                           (size_t)2 * c->n * L, hipMemcpyDeviceToDevice, c->stream));
+        } else if (n.secret) {  // a public part shared into its lanes of the result
+          spdz_shares view = n.sh;
+          view.val += off;
+          view.mac += off;
+          view.len = s->width;
+          st = launch_pubop(c, SPDZ_PUB_SHARE, nullptr, s->dpub, s->width, &view);
+          g->launches++;
+        } else {
+          for (int l = 0; l < L; l++)
+            for (int64_t e = 0; e < s->width; e++) n.hpub[l * n.width + off + e] = s->hpub[l * s->width + e];
+        }
+        if (st != SPDZ_OK) break;
+        off += s->width;
+      }
+      if (st == SPDZ_OK && !n.secret && n.dev_use) st = upload(g, n);
       break;
     }
     case OP_DIV:

@@ -530,6 +530,23 @@ class _Lower:
             s = v.start_node
         return self.emit(lines, "load", [v.base, s], cnt, v.secret, "", extra=f" {cnt}")
 
+    def vector(self, v: Val, width: int) -> Val:
+        """v as a vector of `width` lanes (a constant or a public scalar repeated)."""
+        if v.kind == "const":
+            return Val("node", node=self.const_node(v.const, width), width=width, secret=False)
+        if v.kind == "cvec":
+            return Val("node", node=self.const_vec_node(v.alts), width=width, secret=False)
+        if v.kind == "node" and v.width == width:
+            return v
+        raise FrontendError(f"a {v.kind} value of width {v.width} as a vector of {width} lanes")
+
+    def join(self, lines, a: Val, b: Val) -> Val:
+        """The lanes of a followed by those of b."""
+        if b.kind == "const":
+            b = self.vector(b, b.width)
+        a = self.vector(a, a.width)
+        return self.emit(lines, "cat", [a.node, b.node], a.width + b.width, a.secret or b.secret, "")
+
     def insert_lane(self, lines, name, width: int, base: Val, x: Val, k: int):
         """A vector with lane k replaced by x: (base with lane k zero) + x * e_k; a constant base
         has its lane k zeroed at translation time, another one is multiplied by 1 - e_k."""
@@ -598,10 +615,30 @@ class _Lower:
             else:
                 self.vals[name] = Val("bcast", node=t.node, width=1, secret=False)
             return
+        if max(m for _, m in defined) >= v.width:
+            raise FrontendError(f"lanes {mask} of a vector of width {v.width}")
         starts = {m - i for i, m in defined}
-        if len(starts) != 1 or min(starts) < 0 or min(starts) + out > v.width:
-            raise FrontendError(f"lanes {mask} of a vector of width {v.width}: neither one lane nor a run")
+        if len(starts) != 1 or min(starts) < 0:
+            # several runs: each a view of the vector (an undefined lane continues the run before
+            # it), joined in order
+            segs = []   # [first source lane, lanes]
+            for m in mask:
+                if segs and (m is None or m == segs[-1][0] + segs[-1][1]) and segs[-1][0] + segs[-1][1] < v.width:
+                    segs[-1][1] += 1
+                elif m is None:
+                    segs.append([0, 1])
+                else:
+                    segs.append([m, 1])
+            acc = None
+            for first, cnt in segs:
+                part = (v if first == 0 and cnt == v.width else
+                        self.emit(lines, "load", [v.node, self.const_node(first)], cnt, v.secret, "", extra=f" {cnt}"))
+                acc = part if acc is None else self.join(lines, acc, part)
+            self.vals[name] = acc
+            return
         s0 = starts.pop()
+        if s0 + out > v.width:   # the run's undefined tail reaches past the vector: zero lanes
+            v = self.join(lines, v, Val("const", const=0, width=s0 + out - v.width))
         if s0 == 0 and out == v.width:
             self.vals[name] = v
         else:
@@ -766,18 +803,21 @@ class _Lower:
                         re.match(r"shufflevector\s+<\d+ x i\d+>\s+(%[\w.$]+),\s*<\d+ x i\d+>\s+(?:poison|undef),\s*"
                                  r"<\d+ x i\d+>\s+zeroinitializer$", rest)
                         and re.match(r"shufflevector\s+<\d+ x i\d+>\s+(%[\w.$]+)", rest).group(1) in insert):
-                    # one source vector, a constant mask
-                    mm = re.match(r"shufflevector\s+<(\d+) x i\d+>\s+(%[\w.$]+),\s*<\d+ x i\d+>\s+(?:poison|undef),\s*"
-                                  r"<(\d+) x i\d+>\s+(zeroinitializer|<.*>)$", rest)
-                    if not mm:
-                        raise FrontendError(f"shufflevector of two vectors: {s!r}")
-                    out = int(mm.group(3))
-                    if mm.group(4) == "zeroinitializer":
+                    # a constant mask over one source vector, or over two joined lane by lane (cat)
+                    parts = _split_top(rest[len("shufflevector"):])
+                    if len(parts) != 3:
+                        raise FrontendError(f"cannot read {s!r}")
+                    (ta, va), (_, vb), (tm, vm) = (self.typed(x) for x in parts)
+                    wa, out = _width(ta), _width(tm)
+                    if vm == "zeroinitializer":
                         mask = [0] * out
                     else:
                         mask = [None if e.split()[-1] in ("poison", "undef") else int(e.split()[-1])
-                                for e in _split_top(mm.group(4)[1:-1])]
-                    self.lanes(lines, name, self.operand(mm.group(2)), mask)
+                                for e in _split_top(vm[1:-1])]
+                    src = self.operand(va)
+                    if any(m is not None and m >= wa for m in mask):
+                        src = self.join(lines, self.vector(src, wa), self.vector(self.operand(vb), wa))
+                    self.lanes(lines, name, src, mask)
                 elif op == "shufflevector":
                     mm = re.match(r"shufflevector\s+<\d+ x i\d+>\s+(%[\w.$]+),\s*<\d+ x i\d+>\s+(?:poison|undef),\s*"
                                   r"<(\d+) x i\d+>\s+zeroinitializer$", rest)

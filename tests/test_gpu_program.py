@@ -34,7 +34,8 @@ PROGRAMS = [("pipeline", P.pipeline(3001)), ("branch", P.branch(777)), ("loop", 
             ("loop_program", P.loop_program(2048, 4)), ("one_block_loop", P.one_block_loop(1000, 5)),
             ("phi_swap", P.phi_swap(777, 4)), ("public_div_mod", P.public_div_mod(1001)),
             ("public_phi_swap", P.public_phi_swap(999, 6)), ("broadcast", P.broadcast(3001)),
-            ("loop_reads_source", P.loop_reads_source(1000, 4)), ("lane_constants", P.lane_constants(333))]
+            ("loop_reads_source", P.loop_reads_source(1000, 4)), ("lane_constants", P.lane_constants(333)),
+            ("concatenation", P.concatenation(1001))]
 
 
 @pytest.mark.parametrize("handoff", [True, False])
@@ -364,4 +365,4 @@ def test_random_c_functions_on_the_runtime():
             prog.close()
             ctx.close()
         ran += 1
-    assert ran >= 10
+    assert ran >= 30

@@ -53,6 +53,8 @@ def plain_run(text: str, p: int, seed: int):
                 val[nid] = [int(a == c) for a, c in zip(get(nd.args[0], w), get(nd.args[1], w))]
             elif nd.op == "bcast":
                 val[nid] = val[nd.args[0]] * nd.imm[0]
+            elif nd.op == "cat":
+                val[nid] = val[nd.args[0]] + val[nd.args[1]]
             elif nd.op in ("div", "mod"):
                 k = nd.imm[0]
                 val[nid] = [a // k if nd.op == "div" else a % k for a in val[nd.args[0]]]
@@ -87,7 +89,8 @@ PROGRAMS = [("pipeline", P.pipeline(37)), ("branch", P.branch(21)), ("loop", P.l
             ("phi_swap", P.phi_swap(6, 5)), ("public_div_mod", P.public_div_mod(11)),
             ("public_phi_swap", P.public_phi_swap(5, 6)), ("broadcast", P.broadcast(9)),
             ("loop_reads_source", P.loop_reads_source(7, 3)),
-            ("lane_constants", P.lane_constants(9))]
+            ("lane_constants", P.lane_constants(9)),
+            ("concatenation", P.concatenation(5))]
 
 
 def check_reconstructs(text: str, p: int, n: int, seed: int = 5):

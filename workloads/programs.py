@@ -22,6 +22,8 @@ Text format (one statement per line, '#' starts a comment, ids are integers):
                                         remainder; loop-count arithmetic such as a bound
                                         rounded down to a multiple of the vector length)
     <id> = bcast <a> <w>                a value of width 1 (secret or public) repeated w times
+    <id> = cat <a> <b>                  the lanes of a followed by those of b (a public one shared
+                                        when the other is secret)
     <id> = reduce <a>                   sum of the elements (width 1)
     <id> = open <a>                     reveal a secret value (public result)
     <id> = load <base> <start> <count>  elements start .. start+count-1 of base; <start> is a
@@ -744,5 +746,36 @@ block 0
 6 = open 5
 7 = reduce 4
 8 = open 7
+ret
+"""
+
+
+def concatenation(W: int) -> str:
+    """Lanes joined (W >= 3): cat(x, c) * cat(y, c) with a public constant c of 3 lanes (shared
+    into the secret result), a view of it, cat(open(x), c) + a view of cat(x, y), and
+    cat(open(x), y); all opened."""
+    return f"""
+input 1 private {W} 0
+input 2 private {W} 1
+const 3 3 5 6 7
+const 15 1 2
+const 17 1 0
+output 7
+output 10
+output 19
+block 0
+4 = cat 1 3
+5 = cat 2 3
+6 = mul 4 5
+11 = load 6 15 {W}
+7 = open 11
+8 = open 1
+9 = cat 8 3
+12 = cat 1 2
+13 = load 12 17 {W + 3}
+14 = add 9 13
+10 = open 14
+18 = cat 8 2
+19 = open 18
 ret
 """
